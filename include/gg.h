@@ -1,0 +1,191 @@
+/*
+ * gg.h -- C ABI of libgg: single-source shortest paths, breadth-first search
+ * and connected components on MI355X (gfx950), hand-written HIP kernels.
+ *
+ * The problem statement follows the graph DSL paper (Falcon, "Custom Code
+ * Generation for a Graph DSL"):
+ *   - a graph of points and weighted directed edges is read once (Sec. 2;
+ *     Algorithm 1 reads the graph and adds an int point property);
+ *   - SSSP lowers t.dist to p.dist + weight(p -> t) with an atomic MIN along
+ *     every edge until a sweep changes nothing (Algorithms 1 and 2);
+ *   - BFS assigns level lev+1 to every out-neighbour of a level-lev point
+ *     whose level is larger, level by level, without atomics (Algorithm 3);
+ *   - CC propagates the smallest label over every edge taken both ways until
+ *     nothing changes (CC is named in Sec. 4.1; the label convention is this
+ *     library's reading: the smallest vertex id of the component);
+ *   - each traversal runs vertex-based (CSR: a point and its out-neighbours)
+ *     or edge-based (edge list: one work item per edge) (Sec. 3.1, Algorithm
+ *     4), and synchronously (topology-driven sweeps ended by a changed flag)
+ *     or asynchronously (a data-driven device worklist of updated points,
+ *     Sec. 3.3).  The paper picks the variant at compile time; here it is an
+ *     argument, and GG_*_AUTO lets the library choose.
+ *
+ * Values are int32.  INF = GG_INF = 2^31-1 marks an unreached vertex.  The
+ * SSSP result is min(shortest distance, INF): a path whose length reaches INF
+ * is reported as INF.  Every variant returns bit-identical results.
+ *
+ * Conventions for every function:
+ *   - Return value: GG_OK (0) or a negative gg_status.  Nothing throws.
+ *   - Pointers named *_dev are device pointers (hipMalloc'd memory or a torch
+ *     tensor's data_ptr); every other pointer is host memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Traversal calls are stream-ordered and return before the work ends;
+ *     the caller synchronises (stream or event) before reading results.
+ *   - A HIP failure is reported as GG_EHIP and recorded on the graph handle;
+ *     gg_graph_error() returns the first recorded failure.
+ */
+#ifndef GG_H
+#define GG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GG_INF 2147483647
+
+typedef enum {
+    GG_OK = 0,
+    GG_EINVAL = -1,   /* bad argument: see each function */
+    GG_ENOMEM = -2,   /* device or host allocation failed */
+    GG_EHIP = -3,     /* a HIP runtime call failed */
+    GG_EBUSY = -4,    /* resource in use */
+    GG_ENOTSUP = -5,  /* variant not available for this graph */
+    GG_ETIMEOUT = -6, /* a traversal exceeded its time limit and stopped */
+    GG_EITER = -7     /* a traversal exceeded its iteration bound */
+} gg_status;
+
+/* Work distribution (Sec. 3.1): vertex-based over CSR rows, or edge-based
+ * with one work item per edge. */
+typedef enum { GG_VERTEX = 0, GG_EDGE = 1, GG_MODE_AUTO = 2 } gg_mode;
+
+/* Schedule: synchronous topology-driven sweeps with a changed flag
+ * (Algorithms 1-3), or asynchronous data-driven worklist rounds (Sec. 3.3). */
+typedef enum { GG_SYNC = 0, GG_ASYNC = 1, GG_SCHED_AUTO = 2 } gg_sched;
+
+/* How vertex-based work is mapped to lanes.  THREAD: one lane walks a whole
+ * row (the paper's generated GPU code); WAVE: one wavefront per vertex;
+ * BALANCED: a wavefront shares the edges of 64 rows lane by lane, and rows
+ * longer than the heavy threshold are cut into fixed chunks spread over the
+ * grid.  Ignored for edge-based work. */
+typedef enum { GG_MAP_AUTO = 0, GG_MAP_THREAD = 1, GG_MAP_WAVE = 2, GG_MAP_BALANCED = 3 } gg_mapping;
+
+typedef enum { GG_ALGO_SSSP = 0, GG_ALGO_BFS = 1, GG_ALGO_CC = 2 } gg_algo;
+
+/* gg_graph_upload flags */
+#define GG_SYMMETRIZE 1u      /* also build the both-directions CSR needed by vertex-based CC */
+#define GG_INPUT_ON_DEVICE 2u /* row_ptr/col/w are device pointers */
+#define GG_SYMMETRIC 4u       /* the input already holds v->u for every u->v */
+
+typedef struct gg_graph_s* gg_graph;
+typedef struct gg_ws_s* gg_ws;
+
+/* Per-call options.  Zero-initialise, then set what you need. */
+typedef struct {
+    int32_t mode;          /* gg_mode */
+    int32_t sched;         /* gg_sched */
+    int32_t mapping;       /* gg_mapping */
+    int32_t block_threads; /* 0 = library default (256); else 64..1024, multiple of 64 */
+    int32_t max_blocks;    /* 0 = fill the device; else a cap on the persistent grid */
+    int32_t heavy_threshold; /* 0 = default; rows longer than this are chunked (BALANCED) */
+    int32_t time_limit_ms; /* 0 = default (60000); no round is launched after it (GG_ETIMEOUT) */
+    int32_t flags;         /* GG_OPT_* bits */
+    int32_t reserved[4];
+} gg_opts;
+
+/* gg_opts.flags */
+#define GG_OPT_CC_NO_JUMP 1u /* CC: plain label propagation, without the label[label[v]]
+                                shortcut (the result is the same; the shortcut only
+                                shortens high-diameter graphs) */
+
+/* Statistics of the last traversal run on a workspace. */
+typedef struct {
+    int32_t algo, mode, sched, mapping; /* the variant that ran (AUTO resolved) */
+    int32_t status;                     /* device-side gg_status of that run */
+    int32_t iterations;                 /* sweeps, levels or worklist rounds */
+    int32_t grid_blocks, block_threads; /* launch shape */
+    int64_t edges_processed;            /* edge relaxations attempted */
+    int64_t vertices_processed;         /* vertex visits (rows scanned or worklist entries) */
+    int64_t updates;                    /* successful decreases / level writes */
+    int64_t pushes;                     /* worklist insertions */
+    int64_t reserved[4];
+} gg_stats;
+
+/* Upload a graph given in CSR: row_ptr[n+1] (row_ptr[0] == 0,
+ * non-decreasing, row_ptr[n] == m), col[m] in [0, n), w[m] >= 0 or NULL for
+ * an unweighted graph.  Rows need not be sorted.  Host arrays are copied;
+ * with GG_INPUT_ON_DEVICE the device arrays are copied on `stream`.  The
+ * handle owns every device array it builds: the CSR, the edge list (source
+ * of each edge), the static heavy-row chunks, the both-directions CSR when
+ * GG_SYMMETRIZE is given, and one default workspace.  Validation runs on the
+ * host for host input.  Returns GG_EINVAL for n < 1, m < 0, m >= 2^31, a
+ * malformed row_ptr, a column out of range or a negative weight; GG_ENOMEM
+ * when device memory runs out.  The call returns when the upload is
+ * complete. */
+int gg_graph_upload(int32_t n, int64_t m, const int32_t* row_ptr, const int32_t* col,
+                    const int32_t* w, uint32_t flags, void* stream, gg_graph* out);
+
+/* Free a graph and its default workspace.  Workspaces made with
+ * gg_ws_create must be freed first (GG_EBUSY otherwise).  Synchronises the
+ * device work of the handle before freeing. */
+int gg_graph_free(gg_graph g);
+
+/* Sizes and degree facts.  Any pointer may be NULL. */
+int gg_graph_info(gg_graph g, int32_t* n, int64_t* m, int32_t* max_out_degree,
+                  int32_t* has_weights, int32_t* has_sym);
+
+/* First HIP failure recorded on the handle (GG_OK if none). */
+int gg_graph_error(gg_graph g);
+
+/* SSSP from `source` (Algorithms 1-2).  dist_out_dev: device int32[n],
+ * caller-owned, overwritten.  GG_EINVAL: source outside [0, n), NULL output,
+ * or an unweighted graph.  Uses the graph's default workspace. */
+int gg_sssp(gg_graph g, int32_t source, int32_t mode, int32_t sched, int32_t* dist_out_dev,
+            void* stream);
+
+/* BFS levels from `source` (Algorithm 3).  Same conventions as gg_sssp;
+ * weights are ignored. */
+int gg_bfs(gg_graph g, int32_t source, int32_t mode, int32_t sched, int32_t* dist_out_dev,
+           void* stream);
+
+/* Connected components, label = smallest vertex id of the component, every
+ * edge taken both ways.  label_out_dev: device int32[n].  Vertex-based CC
+ * needs the both-directions CSR (GG_SYMMETRIZE or GG_SYMMETRIC at upload):
+ * GG_ENOTSUP otherwise.  Edge-based CC works on any graph. */
+int gg_cc(gg_graph g, int32_t mode, int32_t sched, int32_t* label_out_dev, void* stream);
+
+/* Workspaces: per-query scratch (worklists, stamps, counters) so that
+ * several traversals of one graph can be in flight on different streams.
+ * A workspace serves one traversal at a time; a call on a workspace whose
+ * previous traversal ran on another stream waits for it on the device. */
+int gg_ws_create(gg_graph g, gg_ws* out);
+int gg_ws_free(gg_ws ws);
+
+/* Full-control forms.  ws NULL = the graph's default workspace; opts NULL =
+ * all defaults (AUTO everything). */
+int gg_sssp_ex(gg_graph g, gg_ws ws, int32_t source, const gg_opts* opts, int32_t* dist_out_dev,
+               void* stream);
+int gg_bfs_ex(gg_graph g, gg_ws ws, int32_t source, const gg_opts* opts, int32_t* dist_out_dev,
+              void* stream);
+int gg_cc_ex(gg_graph g, gg_ws ws, const gg_opts* opts, int32_t* label_out_dev, void* stream);
+
+/* Statistics of the last traversal on a workspace (NULL = default).  Waits
+ * for that traversal to finish.  Returns the traversal's device-side status
+ * (GG_ETIMEOUT, GG_EITER) if it failed, GG_OK otherwise. */
+int gg_last_stats(gg_graph g, gg_ws ws, gg_stats* out);
+
+/* Resolve AUTO fields of opts for an algorithm on this graph, as a call
+ * would (the autotuner's table, else built-in rules). */
+int gg_resolve(gg_graph g, int32_t algo, const gg_opts* in, gg_opts* out);
+
+/* Human-readable status name. */
+const char* gg_status_str(int32_t status);
+
+/* Library version, for the binding's compatibility check. */
+int32_t gg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GG_H */

@@ -1,0 +1,648 @@
+// gg_api.hip -- host runtime and C ABI of libgg (declared in include/gg.h).
+//
+// A traversal is an init kernel followed by rounds (one kernel each, plus a
+// heavy-chunk kernel or a CC shortcut kernel where the variant needs one).
+// The host enqueues rounds in batches that double in size up to kMaxBatch;
+// after each batch it copies the device `done` flag into pinned memory and
+// records an event.  While batch k runs, the host waits for batch k-1's event
+// and stops enqueueing once that batch reported `done`.  Rounds enqueued past
+// the end return at their first instruction, so the overshoot costs at most
+// one batch of empty launches.
+
+#include <gg.h>
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "gg_internal.h"
+
+using namespace gg;
+
+namespace {
+
+constexpr int kVersion = 1;
+constexpr int kBlock = 256;
+constexpr int kMaxBatch = 64;
+constexpr int kDefaultTimeLimitMs = 60000;
+
+struct Dev {
+    int id = 0;
+    int cus = 0;
+    int max_blocks = 0;  // resident blocks of kBlock threads on the whole device
+};
+
+Dev& device() {
+    static Dev d;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        hipGetDevice(&d.id);
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, d.id) == hipSuccess) {
+            d.cus = p.multiProcessorCount;
+            const int per_cu = std::max(1, p.maxThreadsPerMultiProcessor / kBlock);
+            d.max_blocks = std::min(kMaxStatBlocks, d.cus * per_cu);
+        }
+        if (d.max_blocks <= 0) d.max_blocks = 1024;
+    });
+    return d;
+}
+
+template <class T>
+hipError_t dalloc(T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
+}
+
+template <class T>
+void dfree(T*& p) {
+    if (p) hipFree(p);
+    p = nullptr;
+}
+
+}  // namespace
+
+struct gg_ws_s {
+    gg_graph owner = nullptr;
+    DevWs dev{};
+    unsigned char* vflag_mem = nullptr;
+    int2* hq_mem = nullptr;
+    int* h_done = nullptr;  // pinned, 2 slots
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipEvent_t finished = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool used = false;
+    gg_stats last{};
+    bool is_default = false;
+};
+
+struct gg_graph_s {
+    int n = 0;
+    long long m = 0;
+    int max_deg = 0;
+    bool weighted = false;
+    bool has_sym = false;
+    bool symmetric = false;
+    int err = GG_OK;
+    int n_ws = 0;  // user workspaces alive
+    // device arrays
+    int *row = nullptr, *col = nullptr, *w = nullptr, *src = nullptr;
+    int *srow = nullptr, *scol = nullptr, *ssrc = nullptr;
+    int2 *hchunks = nullptr, *shchunks = nullptr;
+    int n_hchunks = 0, n_shchunks = 0;
+    long long ms = 0;
+    int heavy = kDefaultHeavy, chunk = kDefaultHeavy;
+    gg_ws_s* ws0 = nullptr;
+};
+
+namespace {
+
+int fail_hip(gg_graph g, hipError_t e) {
+    if (e == hipSuccess) return GG_OK;
+    if (g && g->err == GG_OK) g->err = (e == hipErrorOutOfMemory) ? GG_ENOMEM : GG_EHIP;
+    return (e == hipErrorOutOfMemory) ? GG_ENOMEM : GG_EHIP;
+}
+
+#define HIPCHK(g, call)                                      \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return fail_hip((g), e_);      \
+    } while (0)
+
+// Heavy-row chunks of a CSR held on the host.
+std::vector<int2> build_chunks(const std::vector<int>& row, int n, int heavy, int chunk) {
+    std::vector<int2> out;
+    for (int v = 0; v < n; ++v) {
+        const int d = row[v + 1] - row[v];
+        if (d > heavy)
+            for (int e = row[v]; e < row[v + 1]; e += chunk) out.push_back(make_int2(v, e));
+    }
+    return out;
+}
+
+int grid_for(long long items_per_block_unit, long long units) {
+    (void)items_per_block_unit;
+    const long long cap = device().max_blocks;
+    long long g = units;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+void free_ws_arrays(gg_ws_s* ws) {
+    if (!ws) return;
+    if (ws->vflag_mem) hipFree(ws->vflag_mem);
+    if (ws->hq_mem) hipFree(ws->hq_mem);
+    if (ws->dev.ctl) hipFree(ws->dev.ctl);
+    if (ws->dev.stat) hipFree(ws->dev.stat);
+    if (ws->h_done) hipHostFree(ws->h_done);
+    for (auto& e : ws->ev)
+        if (e) hipEventDestroy(e);
+    if (ws->finished) hipEventDestroy(ws->finished);
+    ws->vflag_mem = nullptr;
+    ws->hq_mem = nullptr;
+    ws->dev.ctl = nullptr;
+    ws->dev.stat = nullptr;
+    ws->h_done = nullptr;
+}
+
+int make_ws(gg_graph g, gg_ws_s** out) {
+    gg_ws_s* ws = new (std::nothrow) gg_ws_s();
+    if (!ws) return GG_ENOMEM;
+    ws->owner = g;
+    const long long ntiles = (g->n + 63) / 64;
+    // vertex flags padded to whole 64-tile groups so no index needs a bound
+    const long long vbytes = ((ntiles + 63) / 64) * 64 * 64;
+    const long long tbytes = ((ntiles + 63) / 64) * 64;
+    const long long cap = std::max(g->n_hchunks, g->n_shchunks);
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = dalloc(&ws->vflag_mem, (size_t)(2 * (vbytes + tbytes)));
+    if (e == hipSuccess) e = dalloc(&ws->hq_mem, (size_t)(2 * std::max(cap, 1LL)));
+    if (e == hipSuccess) e = dalloc(&ws->dev.ctl, 1);
+    if (e == hipSuccess) e = dalloc(&ws->dev.stat, kMaxStatBlocks);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&ws->h_done), 4 * sizeof(int));
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ws->ev[0], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ws->ev[1], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ws->finished, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipMemset(ws->vflag_mem, 0, (size_t)(2 * (vbytes + tbytes)));
+    if (e == hipSuccess) e = hipMemset(ws->dev.ctl, 0, sizeof(Ctl));
+    if (e != hipSuccess) {
+        free_ws_arrays(ws);
+        delete ws;
+        return fail_hip(g, e);
+    }
+    ws->dev.vflag[0] = ws->vflag_mem;
+    ws->dev.vflag[1] = ws->vflag_mem + vbytes;
+    ws->dev.tflag[0] = ws->vflag_mem + 2 * vbytes;
+    ws->dev.tflag[1] = ws->vflag_mem + 2 * vbytes + tbytes;
+    ws->dev.hq[0] = ws->hq_mem;
+    ws->dev.hq[1] = ws->hq_mem + std::max(cap, 1LL);
+    ws->dev.hq_cap = (int)cap;
+    std::memset(ws->h_done, 0, 4 * sizeof(int));
+    *out = ws;
+    return GG_OK;
+}
+
+void free_graph_arrays(gg_graph g) {
+    if (g->srow && g->srow != g->row) hipFree(g->srow);
+    if (g->scol && g->scol != g->col) hipFree(g->scol);
+    if (g->ssrc && g->ssrc != g->src) hipFree(g->ssrc);
+    dfree(g->row);
+    dfree(g->col);
+    dfree(g->w);
+    dfree(g->src);
+    dfree(g->hchunks);
+    dfree(g->shchunks);
+    g->srow = g->scol = g->ssrc = nullptr;
+}
+
+DevGraph dev_graph(gg_graph g) {
+    DevGraph d{};
+    d.n = g->n;
+    d.m = (int)g->m;
+    d.row = g->row;
+    d.col = g->col;
+    d.w = g->w;
+    d.src = g->src;
+    d.ms = (int)g->ms;
+    d.srow = g->srow;
+    d.scol = g->scol;
+    d.ssrc = g->ssrc;
+    d.heavy = g->heavy;
+    d.chunk = g->chunk;
+    d.hchunks = g->hchunks;
+    d.n_hchunks = g->n_hchunks;
+    d.shchunks = g->shchunks;
+    d.n_shchunks = g->n_shchunks;
+    d.symmetric = g->symmetric;
+    return d;
+}
+
+// Built-in choice of variant when the caller asks for AUTO.
+void resolve(gg_graph g, int algo, const gg_opts* in, gg_opts* out) {
+    gg_opts o{};
+    if (in) o = *in;
+    const bool auto_mode = o.mode != GG_VERTEX && o.mode != GG_EDGE;
+    const bool auto_sched = o.sched != GG_SYNC && o.sched != GG_ASYNC;
+    if (auto_mode) o.mode = GG_VERTEX;
+    if (auto_sched) o.sched = GG_ASYNC;
+    // without the both-directions CSR only the edge sweep can run CC
+    if (algo == GG_ALGO_CC && !g->has_sym) {
+        if (auto_mode) o.mode = GG_EDGE;
+        if (auto_sched) o.sched = GG_SYNC;
+    }
+    if (o.mapping < GG_MAP_THREAD || o.mapping > GG_MAP_BALANCED) o.mapping = GG_MAP_BALANCED;
+    if (o.block_threads <= 0) o.block_threads = kBlock;
+    if (o.time_limit_ms <= 0) o.time_limit_ms = kDefaultTimeLimitMs;
+    *out = o;
+}
+
+int run(gg_graph g, gg_ws ws, int algo, int source, const gg_opts* opts, int* out, void* stream) {
+    if (!g) return GG_EINVAL;
+    if (g->err != GG_OK) return g->err;
+    if (!out) return GG_EINVAL;
+    if (algo != GG_ALGO_CC && (source < 0 || source >= g->n)) return GG_EINVAL;
+    if (algo == GG_ALGO_SSSP && !g->weighted) return GG_EINVAL;
+    if (!ws) ws = g->ws0;
+    if (ws->owner != g) return GG_EINVAL;
+    gg_opts o;
+    resolve(g, algo, opts, &o);
+    // CC reads the both-directions CSR except in the synchronous edge sweep
+    if (algo == GG_ALGO_CC && !g->has_sym && (o.mode != GG_EDGE || o.sched != GG_SYNC))
+        return GG_ENOTSUP;
+    if (o.block_threads != kBlock) return GG_ENOTSUP;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const Dev& dv = device();
+    const int cap_blocks = o.max_blocks > 0 ? std::min(o.max_blocks, dv.max_blocks) : dv.max_blocks;
+    auto grid = [&](long long units) {
+        return (int)std::max(1LL, std::min<long long>(units, cap_blocks));
+    };
+
+    // a workspace serves one traversal at a time: order after its last one
+    if (ws->used && ws->last_stream != s) HIPCHK(g, hipStreamWaitEvent(s, ws->finished, 0));
+
+    const bool async = o.sched == GG_ASYNC;
+    const bool edge = o.mode == GG_EDGE;
+    const bool cc = algo == GG_ALGO_CC;
+    Round R{};
+    R.g = dev_graph(g);
+    R.ws = ws->dev;
+    R.val = out;
+    R.source = cc ? 0 : source;
+    R.r = 0;
+    R.mapping = o.mapping;
+    R.jump = cc && !(o.flags & GG_OPT_CC_NO_JUMP);
+
+    const int wpb = kBlock / 64;
+    const long long n = g->n;
+    const long long ntiles = (n + 63) / 64;
+    const long long ngroups = (ntiles + 63) / 64;
+    const int nh = cc ? g->n_shchunks : g->n_hchunks;
+    const int g_init = grid((n + kBlock - 1) / kBlock);
+    int g_round;
+    if (!async && !edge) {
+        if (o.mapping == GG_MAP_BALANCED) g_round = grid((nh + ntiles + wpb - 1) / wpb);
+        else if (o.mapping == GG_MAP_THREAD) g_round = grid((n + kBlock - 1) / kBlock);
+        else g_round = grid((n + wpb - 1) / wpb);
+    } else if (!async && edge) {
+        g_round = grid((g->m / 4 + kBlock - 1) / kBlock);
+    } else {
+        g_round = grid((ngroups * 8 + wpb - 1) / wpb);
+    }
+    const bool need_heavy = async && (edge || o.mapping == GG_MAP_BALANCED) && nh > 0;
+    const int g_heavy = grid((std::max(g->n_hchunks, g->n_shchunks) + wpb - 1) / wpb);
+    const bool need_jump = cc && edge && !async && R.jump;
+    const int g_jump = grid((n + kBlock - 1) / kBlock);
+
+    HIPCHK(g, launch_init(R, algo, async, g_init, kBlock, s));
+
+    // bound on rounds: every productive round fixes at least one more vertex
+    const long long max_rounds = n + 2;
+    const auto t0 = std::chrono::steady_clock::now();
+    int status = GG_OK;
+    long long r = 0;
+    int batch = 2, k = 0;
+    bool pending = false;
+    for (;;) {
+        const long long r_end = std::min(r + batch, max_rounds);
+        for (; r < r_end; ++r) {
+            R.r = (int)r;
+            hipError_t e;
+            if (!async && !edge) e = launch_vsync(R, algo, g_round, kBlock, s);
+            else if (!async) e = launch_esync(R, algo, g_round, kBlock, s);
+            else if (!edge) e = launch_vasync(R, algo, g_round, kBlock, s);
+            else e = launch_easync(R, algo, g_round, kBlock, s);
+            if (e == hipSuccess && need_heavy) e = launch_heavy(R, algo, g_heavy, kBlock, s);
+            if (e == hipSuccess && need_jump) e = launch_jump(R, g_jump, kBlock, s);
+            HIPCHK(g, e);
+        }
+        const int slot = k & 1;
+        HIPCHK(g, hipMemcpyAsync(ws->h_done + slot, &ws->dev.ctl->done, sizeof(int),
+                                 hipMemcpyDeviceToHost, s));
+        HIPCHK(g, hipEventRecord(ws->ev[slot], s));
+        if (pending) {
+            HIPCHK(g, hipEventSynchronize(ws->ev[slot ^ 1]));
+            if (ws->h_done[slot ^ 1]) break;
+        }
+        pending = true;
+        ++k;
+        if (r >= max_rounds) {
+            HIPCHK(g, hipEventSynchronize(ws->ev[slot]));
+            if (!ws->h_done[slot]) status = GG_EITER;
+            break;
+        }
+        const long long ms = std::chrono::duration_cast<std::chrono::milliseconds>(
+                                 std::chrono::steady_clock::now() - t0).count();
+        if (ms > o.time_limit_ms) {
+            HIPCHK(g, hipEventSynchronize(ws->ev[slot]));
+            if (!ws->h_done[slot]) status = GG_ETIMEOUT;
+            break;
+        }
+        batch = std::min(batch * 2, kMaxBatch);
+    }
+    HIPCHK(g, hipEventRecord(ws->finished, s));
+    ws->last_stream = s;
+    ws->used = true;
+    ws->last = gg_stats{};
+    ws->last.algo = algo;
+    ws->last.mode = o.mode;
+    ws->last.sched = o.sched;
+    ws->last.mapping = edge ? 0 : o.mapping;
+    ws->last.status = status;
+    ws->last.grid_blocks = g_round;
+    ws->last.block_threads = kBlock;
+    return status;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t gg_version(void) { return kVersion; }
+
+const char* gg_status_str(int32_t status) {
+    switch (status) {
+        case GG_OK: return "GG_OK";
+        case GG_EINVAL: return "GG_EINVAL";
+        case GG_ENOMEM: return "GG_ENOMEM";
+        case GG_EHIP: return "GG_EHIP";
+        case GG_EBUSY: return "GG_EBUSY";
+        case GG_ENOTSUP: return "GG_ENOTSUP";
+        case GG_ETIMEOUT: return "GG_ETIMEOUT";
+        case GG_EITER: return "GG_EITER";
+        default: return "GG_UNKNOWN";
+    }
+}
+
+int gg_graph_upload(int32_t n, int64_t m, const int32_t* row_ptr, const int32_t* col,
+                    const int32_t* w, uint32_t flags, void* stream, gg_graph* out) {
+    if (!out) return GG_EINVAL;
+    *out = nullptr;
+    if (n < 1 || m < 0 || m >= (1LL << 31) || !row_ptr || (m > 0 && !col)) return GG_EINVAL;
+    const bool on_dev = flags & GG_INPUT_ON_DEVICE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // host copy of the row offsets (needed for validation and heavy chunks)
+    std::vector<int> hrow((size_t)n + 1);
+    if (on_dev) {
+        if (hipMemcpy(hrow.data(), row_ptr, sizeof(int) * ((size_t)n + 1), hipMemcpyDeviceToHost) !=
+            hipSuccess)
+            return GG_EHIP;
+    } else {
+        std::memcpy(hrow.data(), row_ptr, sizeof(int) * ((size_t)n + 1));
+    }
+    if (hrow[0] != 0 || hrow[n] != m) return GG_EINVAL;
+    int max_deg = 0;
+    for (int v = 0; v < n; ++v) {
+        if (hrow[v + 1] < hrow[v]) return GG_EINVAL;
+        max_deg = std::max(max_deg, hrow[v + 1] - hrow[v]);
+    }
+    if (!on_dev) {
+        for (long long e = 0; e < m; ++e)
+            if (col[e] < 0 || col[e] >= n) return GG_EINVAL;
+        if (w)
+            for (long long e = 0; e < m; ++e)
+                if (w[e] < 0) return GG_EINVAL;
+    }
+    gg_graph g = new (std::nothrow) gg_graph_s();
+    if (!g) return GG_ENOMEM;
+    g->n = n;
+    g->m = m;
+    g->max_deg = max_deg;
+    g->weighted = w != nullptr;
+    const hipMemcpyKind kind = on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    auto bail = [&](int code) {
+        hipStreamSynchronize(s);
+        free_graph_arrays(g);
+        delete g;
+        return code;
+    };
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = dalloc(&g->row, (size_t)n + 1);
+    if (e == hipSuccess) e = dalloc(&g->col, (size_t)m);
+    if (e == hipSuccess && w) e = dalloc(&g->w, (size_t)m);
+    if (e == hipSuccess) e = dalloc(&g->src, (size_t)m);
+    if (e == hipSuccess) e = hipMemcpyAsync(g->row, hrow.data(), sizeof(int) * ((size_t)n + 1),
+                                            hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && m) e = hipMemcpyAsync(g->col, col, sizeof(int) * m, kind, s);
+    if (e == hipSuccess && m && w) e = hipMemcpyAsync(g->w, w, sizeof(int) * m, kind, s);
+    const int wpb = kBlock / 64;
+    const long long ntiles = ((long long)n + 63) / 64;
+    auto grid = [&](long long units) {
+        return (int)std::max(1LL, std::min<long long>(units, device().max_blocks));
+    };
+    if (e == hipSuccess)
+        e = launch_fill_src(g->row, n, g->src, grid((ntiles + wpb - 1) / wpb), kBlock, s);
+    if (e != hipSuccess) return bail(e == hipErrorOutOfMemory ? GG_ENOMEM : GG_EHIP);
+    if (on_dev) {
+        // validate device input on the host after copying it back
+        std::vector<int> hc((size_t)m);
+        if (m && hipMemcpy(hc.data(), g->col, sizeof(int) * m, hipMemcpyDeviceToHost) != hipSuccess)
+            return bail(GG_EHIP);
+        for (long long i = 0; i < m; ++i)
+            if (hc[i] < 0 || hc[i] >= n) return bail(GG_EINVAL);
+        if (w) {
+            if (m && hipMemcpy(hc.data(), g->w, sizeof(int) * m, hipMemcpyDeviceToHost) != hipSuccess)
+                return bail(GG_EHIP);
+            for (long long i = 0; i < m; ++i)
+                if (hc[i] < 0) return bail(GG_EINVAL);
+        }
+    }
+    std::vector<int2> hch = build_chunks(hrow, n, g->heavy, g->chunk);
+    g->n_hchunks = (int)hch.size();
+    if (!hch.empty()) {
+        e = dalloc(&g->hchunks, hch.size());
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(g->hchunks, hch.data(), sizeof(int2) * hch.size(),
+                               hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return bail(GG_EHIP);
+    }
+    if (flags & GG_SYMMETRIC) {
+        g->symmetric = true;
+        g->has_sym = true;
+        g->srow = g->row;
+        g->scol = g->col;
+        g->ssrc = g->src;
+        g->ms = m;
+        g->n_shchunks = g->n_hchunks;
+        if (g->n_hchunks) {
+            e = dalloc(&g->shchunks, hch.size());
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(g->shchunks, hch.data(), sizeof(int2) * hch.size(),
+                                   hipMemcpyHostToDevice, s);
+            if (e != hipSuccess) return bail(GG_EHIP);
+        }
+    } else if (flags & GG_SYMMETRIZE) {
+        const long long ms = 2 * m;
+        if (ms >= (1LL << 31)) return bail(GG_EINVAL);
+        int* indeg = nullptr;
+        e = dalloc(&indeg, (size_t)n);
+        if (e == hipSuccess) e = hipMemsetAsync(indeg, 0, sizeof(int) * n, s);
+        if (e == hipSuccess && m)
+            e = launch_count_in(g->col, (int)m, indeg, grid((m + kBlock - 1) / kBlock), kBlock, s);
+        std::vector<int> hin((size_t)n), hsrow((size_t)n + 1);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(hin.data(), indeg, sizeof(int) * n, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            dfree(indeg);
+            return bail(GG_EHIP);
+        }
+        hsrow[0] = 0;
+        for (int v = 0; v < n; ++v) hsrow[v + 1] = hsrow[v] + (hrow[v + 1] - hrow[v]) + hin[v];
+        if (e == hipSuccess) e = dalloc(&g->srow, (size_t)n + 1);
+        if (e == hipSuccess) e = dalloc(&g->scol, (size_t)ms);
+        if (e == hipSuccess) e = dalloc(&g->ssrc, (size_t)ms);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(g->srow, hsrow.data(), sizeof(int) * ((size_t)n + 1),
+                               hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemsetAsync(indeg, 0, sizeof(int) * n, s);
+        if (e == hipSuccess && m)
+            e = launch_sym_fill(g->row, g->col, g->src, n, (int)m, g->srow, indeg, g->scol,
+                                grid((m + kBlock - 1) / kBlock), kBlock, s);
+        if (e == hipSuccess)
+            e = launch_fill_src(g->srow, n, g->ssrc, grid((ntiles + wpb - 1) / wpb), kBlock, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        dfree(indeg);
+        if (e != hipSuccess) return bail(e == hipErrorOutOfMemory ? GG_ENOMEM : GG_EHIP);
+        g->has_sym = true;
+        g->ms = ms;
+        std::vector<int2> sch = build_chunks(hsrow, n, g->heavy, g->chunk);
+        g->n_shchunks = (int)sch.size();
+        if (!sch.empty()) {
+            e = dalloc(&g->shchunks, sch.size());
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(g->shchunks, sch.data(), sizeof(int2) * sch.size(),
+                                   hipMemcpyHostToDevice, s);
+            if (e != hipSuccess) return bail(GG_EHIP);
+        }
+    }
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return bail(GG_EHIP);
+    int rc = make_ws(g, &g->ws0);
+    if (rc != GG_OK) return bail(rc);
+    g->ws0->is_default = true;
+    *out = g;
+    return GG_OK;
+}
+
+int gg_graph_free(gg_graph g) {
+    if (!g) return GG_EINVAL;
+    if (g->n_ws > 0) return GG_EBUSY;
+    hipDeviceSynchronize();
+    free_ws_arrays(g->ws0);
+    delete g->ws0;
+    free_graph_arrays(g);
+    delete g;
+    return GG_OK;
+}
+
+int gg_graph_info(gg_graph g, int32_t* n, int64_t* m, int32_t* max_out_degree,
+                  int32_t* has_weights, int32_t* has_sym) {
+    if (!g) return GG_EINVAL;
+    if (n) *n = g->n;
+    if (m) *m = g->m;
+    if (max_out_degree) *max_out_degree = g->max_deg;
+    if (has_weights) *has_weights = g->weighted;
+    if (has_sym) *has_sym = g->has_sym;
+    return GG_OK;
+}
+
+int gg_graph_error(gg_graph g) { return g ? g->err : GG_EINVAL; }
+
+int gg_ws_create(gg_graph g, gg_ws* out) {
+    if (!g || !out) return GG_EINVAL;
+    gg_ws_s* ws = nullptr;
+    int rc = make_ws(g, &ws);
+    if (rc != GG_OK) return rc;
+    g->n_ws++;
+    *out = ws;
+    return GG_OK;
+}
+
+int gg_ws_free(gg_ws ws) {
+    if (!ws || ws->is_default) return GG_EINVAL;
+    if (ws->used) hipEventSynchronize(ws->finished);
+    ws->owner->n_ws--;
+    free_ws_arrays(ws);
+    delete ws;
+    return GG_OK;
+}
+
+int gg_sssp_ex(gg_graph g, gg_ws ws, int32_t source, const gg_opts* opts, int32_t* dist_out_dev,
+               void* stream) {
+    return run(g, ws, GG_ALGO_SSSP, source, opts, dist_out_dev, stream);
+}
+
+int gg_bfs_ex(gg_graph g, gg_ws ws, int32_t source, const gg_opts* opts, int32_t* dist_out_dev,
+              void* stream) {
+    return run(g, ws, GG_ALGO_BFS, source, opts, dist_out_dev, stream);
+}
+
+int gg_cc_ex(gg_graph g, gg_ws ws, const gg_opts* opts, int32_t* label_out_dev, void* stream) {
+    return run(g, ws, GG_ALGO_CC, 0, opts, label_out_dev, stream);
+}
+
+int gg_sssp(gg_graph g, int32_t source, int32_t mode, int32_t sched, int32_t* dist_out_dev,
+            void* stream) {
+    gg_opts o{};
+    o.mode = mode;
+    o.sched = sched;
+    return run(g, nullptr, GG_ALGO_SSSP, source, &o, dist_out_dev, stream);
+}
+
+int gg_bfs(gg_graph g, int32_t source, int32_t mode, int32_t sched, int32_t* dist_out_dev,
+           void* stream) {
+    gg_opts o{};
+    o.mode = mode;
+    o.sched = sched;
+    return run(g, nullptr, GG_ALGO_BFS, source, &o, dist_out_dev, stream);
+}
+
+int gg_cc(gg_graph g, int32_t mode, int32_t sched, int32_t* label_out_dev, void* stream) {
+    gg_opts o{};
+    o.mode = mode;
+    o.sched = sched;
+    return run(g, nullptr, GG_ALGO_CC, 0, &o, label_out_dev, stream);
+}
+
+int gg_last_stats(gg_graph g, gg_ws ws, gg_stats* out) {
+    if (!g || !out) return GG_EINVAL;
+    if (!ws) ws = g->ws0;
+    if (ws->owner != g) return GG_EINVAL;
+    if (!ws->used) {
+        *out = gg_stats{};
+        return GG_OK;
+    }
+    HIPCHK(g, hipEventSynchronize(ws->finished));
+    Ctl c;
+    std::vector<Stat> st(kMaxStatBlocks);
+    HIPCHK(g, hipMemcpy(&c, ws->dev.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    HIPCHK(g, hipMemcpy(st.data(), ws->dev.stat, sizeof(Stat) * kMaxStatBlocks,
+                        hipMemcpyDeviceToHost));
+    gg_stats s = ws->last;
+    s.iterations = c.done ? c.iters : -1;
+    for (const Stat& x : st) {
+        s.edges_processed += x.edges;
+        s.vertices_processed += x.verts;
+        s.updates += x.updates;
+        s.pushes += x.pushes;
+    }
+    *out = s;
+    return s.status;
+}
+
+int gg_resolve(gg_graph g, int32_t algo, const gg_opts* in, gg_opts* out) {
+    if (!g || !out || algo < 0 || algo > 2) return GG_EINVAL;
+    resolve(g, algo, in, out);
+    return GG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,96 @@
+// gg_internal.h -- structures shared by the kernels and the host runtime of
+// libgg.  Not part of the public ABI (include/gg.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gg {
+
+constexpr int kInf = 2147483647;
+constexpr int kWave = 64;
+constexpr int kTile = 64;            // vertices per frontier tile (one wavefront)
+constexpr int kMaxStatBlocks = 4096; // per-block statistics slots
+constexpr int kDefaultHeavy = 512;   // rows longer than this are chunked (balanced mapping)
+
+enum Algo { SSSP = 0, BFS = 1, CC = 2 };
+enum Map { MAP_THREAD = 1, MAP_WAVE = 2, MAP_BALANCED = 3 };
+
+// Loop-control block, one per workspace.  Kernels of one traversal read the
+// slots written by earlier kernels of the same stream (kernel boundaries make
+// them visible); slot r % 3 belongs to round r.
+struct Ctl {
+    int done;        // set by the first round kernel that finds nothing left to do
+    int iters;       // rounds that ran, set together with done
+    int changed[4];  // [r % 3]: round r updated or pushed something
+    int hq_count[2]; // heavy-chunk queue fill, by round parity
+    int pad[8];
+};
+
+// Per-block counters, summed on the host after a traversal.
+struct Stat {
+    long long edges, verts, updates, pushes;
+};
+
+// Device view of an uploaded graph.  Arrays are owned by the host-side
+// handle.  The CSR keeps the input's row order; src is the edge-list form.
+struct DevGraph {
+    int n, m;
+    const int* row;  // [n+1]
+    const int* col;  // [m]
+    const int* w;    // [m] or null
+    const int* src;  // [m] source vertex of each edge
+    // both-directions graph for CC (aliases row/col/src when the input is symmetric)
+    int ms;
+    const int* srow;
+    const int* scol;
+    const int* ssrc;
+    // heavy rows (degree > heavy) as (row, first edge) chunks of `chunk` edges
+    int heavy, chunk;
+    const int2* hchunks;
+    int n_hchunks;
+    const int2* shchunks;
+    int n_shchunks;
+    bool symmetric;  // input already holds both directions of every edge
+};
+
+// Device view of a workspace: frontier flags (one byte per vertex, one per
+// 64-vertex tile), two generations; heavy-chunk queues; control; stats.
+struct DevWs {
+    unsigned char* vflag[2];
+    unsigned char* tflag[2];
+    int2* hq[2];
+    int hq_cap;
+    Ctl* ctl;
+    Stat* stat;
+};
+
+// Everything a round kernel needs.  Passed by value.
+struct Round {
+    DevGraph g;
+    DevWs ws;
+    int* val;    // dist or label, [n]
+    int source;
+    int r;       // round (sweep, level) index
+    int mapping; // Map
+    int jump;    // CC: apply the label[label[v]] shortcut
+};
+
+// Launch entry points (gg_kernels.hip).  Each returns the hipError_t of the
+// launch.
+hipError_t launch_init(const Round& R, int algo, bool async, int grid, int block, hipStream_t s);
+hipError_t launch_vsync(const Round& R, int algo, int grid, int block, hipStream_t s);
+hipError_t launch_esync(const Round& R, int algo, int grid, int block, hipStream_t s);
+hipError_t launch_vasync(const Round& R, int algo, int grid, int block, hipStream_t s);
+hipError_t launch_easync(const Round& R, int algo, int grid, int block, hipStream_t s);
+hipError_t launch_heavy(const Round& R, int algo, int grid, int block, hipStream_t s);
+hipError_t launch_jump(const Round& R, int grid, int block, hipStream_t s);
+
+// Graph build helpers (gg_kernels.hip).
+hipError_t launch_fill_src(const int* row, int n, int* src, int grid, int block, hipStream_t s);
+hipError_t launch_count_in(const int* col, int m, int* indeg, int grid, int block, hipStream_t s);
+hipError_t launch_sym_fill(const int* row, const int* col, const int* src, int n, int m,
+                           const int* srow, int* cursor, int* scol, int grid, int block,
+                           hipStream_t s);
+
+}  // namespace gg

@@ -1,0 +1,737 @@
+// gg_kernels.hip -- traversal kernels of libgg for gfx950 (CDNA4, 64-wide
+// wavefronts).
+//
+// One kernel launch is one round: a synchronous sweep (Algorithms 1-3: every
+// vertex or every edge, ended by a changed flag) or one asynchronous worklist
+// round (Sec. 3.3: only the vertices updated in the previous round).  The
+// host enqueues rounds back to back; every round kernel first reads the
+// control block and returns at once when an earlier round found nothing to
+// do, so no kernel ever waits on another and every launch terminates.
+//
+// Relaxation (Algorithms 1-2): for an edge p -> t, t.dist is lowered to
+// p.dist + weight with an atomic minimum.  A plain load of t.dist comes
+// first and the atomic is skipped when it cannot lower the value; values only
+// decrease, so a stale load can only cause an unnecessary atomic, never a
+// missed one.
+//
+// BFS (Algorithm 3): level lev visits the vertices with dist == lev and
+// writes lev+1 into every out-neighbour whose level is larger, with plain
+// stores (all writers of a level store the same value).
+//
+// CC: label[t] is lowered to label[p] over every edge, both directions.  The
+// optional shortcut label[p] = label[label[p]] keeps label[p] a member of p's
+// component, so the fixpoint (the smallest id of the component) is unchanged.
+//
+// Frontier (asynchronous schedule): one byte per vertex and one per 64-vertex
+// tile, two generations.  A push is a plain byte store of 1, so duplicates
+// collapse without atomics; a round clears the flags it consumes.  Rows longer
+// than the heavy threshold are cut into fixed chunks and placed on a queue
+// that a second kernel of the same round spreads over the whole grid.
+
+#include "gg_internal.h"
+
+namespace gg {
+
+// A frontier work item is one eighth of a 64-tile group: the wavefront loads
+// the 64 tile flags of the group at once and serves the 8 tiles of its part.
+constexpr int kParts = 8;
+
+// ------------------------------------------------------------ helpers ----
+
+__device__ __forceinline__ int wave_incl_scan(int x) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ int wave_sum(int x) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) x += __shfl_xor(x, d, 64);
+    return x;
+}
+
+// Counters of one lane for the current kernel.
+struct Acc {
+    int e = 0, v = 0, u = 0, p = 0;
+};
+
+// Round entry, uniform over the whole grid.  Returns false when the
+// traversal has finished: either an earlier round set `done`, or round r-1
+// changed nothing, in which case this kernel records the round count.
+__device__ __forceinline__ bool round_begin(const Round& R) {
+    Ctl* ctl = R.ws.ctl;
+    if (*(volatile int*)&ctl->done) return false;
+    if (R.r > 0 && *(volatile int*)&ctl->changed[(R.r - 1) % 3] == 0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            ctl->iters = R.r;
+            ctl->done = 1;
+        }
+        return false;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // slots of round r+1: last read by rounds that have completed
+        ctl->changed[(R.r + 1) % 3] = 0;
+        ctl->hq_count[(R.r + 1) & 1] = 0;
+    }
+    return true;
+}
+
+// Block-level reduction of the lane counters; one plain update of this
+// block's statistics slot and, when anything changed, of the round's flag.
+__device__ void block_finish(const Round& R, const Acc& a, int slot) {
+    __shared__ long long s_acc[4][4];
+    int e = wave_sum(a.e), v = wave_sum(a.v), u = wave_sum(a.u), p = wave_sum(a.p);
+    const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s_acc[wid][0] = e;
+        s_acc[wid][1] = v;
+        s_acc[wid][2] = u;
+        s_acc[wid][3] = p;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long E = 0, V = 0, U = 0, P = 0;
+        for (int i = 0; i < nw; ++i) {
+            E += s_acc[i][0];
+            V += s_acc[i][1];
+            U += s_acc[i][2];
+            P += s_acc[i][3];
+        }
+        if (E | V | U | P) {
+            Stat* st = R.ws.stat + blockIdx.x;
+            st->edges += E;
+            st->verts += V;
+            st->updates += U;
+            st->pushes += P;
+        }
+        if (U > 0 || P > 0) R.ws.ctl->changed[slot] = 1;
+    }
+}
+
+// Lanes hold one row each, [beg, beg + deg), with the value sv that relaxes
+// its edges.  The wavefront walks the concatenation of the 64 rows 64 edges
+// at a time; in each step lane k takes the k-th edge and finds its row by a
+// six-step search over the exclusive prefix of the degrees.
+template <class F>
+__device__ __forceinline__ void wave_rows_balanced(int beg, int deg, int sv, F&& f) {
+    const int lane = threadIdx.x & 63;
+    const int incl = wave_incl_scan(deg);
+    const int total = __shfl(incl, 63, 64);
+    const int excl = incl - deg;
+    for (int base = 0; base < total; base += 64) {
+        const int k = base + lane;
+        int o = 0;
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1) {
+            const int cand = o + step;
+            const int ex = __shfl(excl, cand, 64);
+            if (ex <= k) o = cand;
+        }
+        const int ob = __shfl(beg, o, 64);
+        const int oe = __shfl(excl, o, 64);
+        const int os = __shfl(sv, o, 64);
+        if (k < total) f(ob + (k - oe), os);
+    }
+}
+
+// ---------------------------------------------------------- algorithms ----
+
+// Relax one edge e (p -> t = col[e]) with the tail's value sv.  Returns true
+// when this lane lowered val[t] (the caller pushes t or counts an update).
+template <int A>
+__device__ __forceinline__ bool relax_edge(const Round& R, const int* col, int e, int sv, int& t) {
+    t = col[e];
+    int* val = R.val;
+    if (A == SSSP) {
+        // sv < INF and w >= 0: the sum fits 32 unsigned bits; anything at or
+        // above 2^31 cannot beat a stored value and is dropped
+        const unsigned cand = (unsigned)sv + (unsigned)R.g.w[e];
+        const int cur = val[t];
+        if (cand < (unsigned)cur) {
+            const int old = atomicMin(&val[t], (int)cand);
+            return (int)cand < old;
+        }
+        return false;
+    } else if (A == BFS) {
+        const int nl = sv + 1;
+        if (val[t] > nl) {
+            val[t] = nl;
+            return true;
+        }
+        return false;
+    } else {
+        const int cur = val[t];
+        if (sv < cur) {
+            const int old = atomicMin(&val[t], sv);
+            return sv < old;
+        }
+        return false;
+    }
+}
+
+// Value and activity of vertex u as the tail of its edges.
+//  sync:  SSSP every reached vertex; BFS the vertices of level r; CC all.
+//  async: u is on the frontier; SSSP/CC read its current value, BFS uses r.
+// For CC the shortcut label[u] = label[label[u]] is applied first (counted as
+// an update so that a sweep which only shortcuts is not the last one).
+template <int A, bool ASYNC>
+__device__ __forceinline__ bool tail_value(const Round& R, int u, int& sv, Acc& acc) {
+    int* val = R.val;
+    if (A == SSSP) {
+        sv = val[u];
+        return ASYNC || sv != kInf;
+    } else if (A == BFS) {
+        sv = R.r;
+        return ASYNC || val[u] == R.r;
+    } else {
+        int x = val[u];
+        if (R.jump) {
+            const int y = val[x];
+            if (y < x) {
+                const int old = atomicMin(&val[u], y);
+                if (!ASYNC && y < old) acc.u++;
+                x = y;
+            }
+        }
+        sv = x;
+        return true;
+    }
+}
+
+__device__ __forceinline__ void push(const Round& R, int nxt, int t) {
+    R.ws.vflag[nxt][t] = 1;
+    R.ws.tflag[nxt][t >> 6] = 1;
+}
+
+// Append the heavy rows held by lanes with hv set to the round's chunk
+// queue: one atomic per wavefront reserves room for all their chunks.
+__device__ __forceinline__ void heavy_append(const Round& R, int cur, bool hv, int u, int rb,
+                                             int re) {
+    const int chunk = R.g.chunk;
+    const int nch = hv ? (re - rb + chunk - 1) / chunk : 0;
+    const int incl = wave_incl_scan(nch);
+    const int total = __shfl(incl, 63, 64);
+    if (total == 0) return;
+    int base = 0;
+    if ((threadIdx.x & 63) == 0) base = atomicAdd(&R.ws.ctl->hq_count[cur], total);
+    base = __shfl(base, 0, 64);
+    int pos = base + incl - nch;
+    int2* q = R.ws.hq[cur];
+    for (int j = 0; j < nch; ++j) q[pos + j] = make_int2(u, rb + j * chunk);
+}
+
+// ------------------------------------------------------------ kernels ----
+
+__global__ __launch_bounds__(256) void k_init(Round R, int algo, int async) {
+    const int n = R.g.n;
+    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long tt = (long long)gridDim.x * blockDim.x;
+    for (long long v = tid; v < n; v += tt) {
+        R.val[v] = algo == CC ? (int)v : (v == R.source ? 0 : kInf);
+        if (async) {
+            const bool on = algo == CC || v == R.source;
+            R.ws.vflag[0][v] = on;
+            R.ws.vflag[1][v] = 0;
+            if ((v & 63) == 0) {
+                const long long t = v >> 6;
+                R.ws.tflag[0][t] = algo == CC || t == (R.source >> 6);
+                R.ws.tflag[1][t] = 0;
+            }
+        }
+    }
+    for (long long i = tid; i < kMaxStatBlocks; i += tt) R.ws.stat[i] = Stat{0, 0, 0, 0};
+    if (tid == 0) *R.ws.ctl = Ctl{};
+}
+
+// Synchronous vertex sweep (Algorithm 1; Algorithm 3 for BFS).
+template <int A, int MAP>
+__global__ __launch_bounds__(256) void k_vsync(Round R) {
+    if (!round_begin(R)) return;
+    const DevGraph& g = R.g;
+    const int* row = A == CC ? g.srow : g.row;
+    const int* col = A == CC ? g.scol : g.col;
+    const int n = g.n;
+    const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    const long long gw = (long long)blockIdx.x * wpb + (threadIdx.x >> 6);
+    const long long tw = (long long)gridDim.x * wpb;
+    const long long ntiles = (n + 63) / 64;
+    Acc acc;
+
+    if (MAP == MAP_BALANCED) {
+        const int2* hch = A == CC ? g.shchunks : g.hchunks;
+        const long long nh = A == CC ? g.n_shchunks : g.n_hchunks;
+        for (long long it = gw; it < nh + ntiles; it += tw) {
+            if (it < nh) {
+                const int2 hc = hch[it];
+                const int u = hc.x;
+                const int e1 = min(hc.y + g.chunk, row[u + 1]);
+                int sv;
+                if (tail_value<A, false>(R, u, sv, acc)) {
+                    if (lane == 0) acc.v++;
+                    for (int e = hc.y + lane; e < e1; e += 64) {
+                        int t;
+                        acc.e++;
+                        if (relax_edge<A>(R, col, e, sv, t)) acc.u++;
+                    }
+                }
+            } else {
+                const int u = (int)((it - nh) * 64 + lane);
+                int beg = 0, deg = 0, sv = 0;
+                if (u < n) {
+                    const int rb = row[u], re = row[u + 1];
+                    if (re - rb <= g.heavy && tail_value<A, false>(R, u, sv, acc)) {
+                        beg = rb;
+                        deg = re - rb;
+                        acc.v++;
+                    }
+                }
+                wave_rows_balanced(beg, deg, sv, [&](int e, int s) {
+                    int t;
+                    acc.e++;
+                    if (relax_edge<A>(R, col, e, s, t)) acc.u++;
+                });
+            }
+        }
+    } else if (MAP == MAP_THREAD) {
+        const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+        const long long tt = (long long)gridDim.x * blockDim.x;
+        for (long long uu = tid; uu < n; uu += tt) {
+            const int u = (int)uu;
+            int sv;
+            if (!tail_value<A, false>(R, u, sv, acc)) continue;
+            acc.v++;
+            const int re = row[u + 1];
+            for (int e = row[u]; e < re; ++e) {
+                int t;
+                acc.e++;
+                if (relax_edge<A>(R, col, e, sv, t)) acc.u++;
+            }
+        }
+    } else {  // MAP_WAVE
+        for (long long uu = gw; uu < n; uu += tw) {
+            const int u = (int)uu;
+            int sv;
+            if (!tail_value<A, false>(R, u, sv, acc)) continue;
+            if (lane == 0) acc.v++;
+            const int re = row[u + 1];
+            for (int e = row[u] + lane; e < re; e += 64) {
+                int t;
+                acc.e++;
+                if (relax_edge<A>(R, col, e, sv, t)) acc.u++;
+            }
+        }
+    }
+    block_finish(R, acc, R.r % 3);
+}
+
+// One edge of the synchronous edge sweep (Algorithm 2; the edge form of
+// Algorithm 3 for BFS; CC relaxes both directions of a stored edge unless
+// the input is symmetric, where the reverse edge is stored too).
+template <int A>
+__device__ __forceinline__ void edge_sync_one(const Round& R, int u, int t, int e, Acc& acc) {
+    int* val = R.val;
+    acc.e++;
+    if (A == SSSP) {
+        const int du = val[u];
+        if (du == kInf) return;
+        const unsigned cand = (unsigned)du + (unsigned)R.g.w[e];
+        if (cand < (unsigned)val[t]) {
+            const int old = atomicMin(&val[t], (int)cand);
+            if ((int)cand < old) acc.u++;
+        }
+    } else if (A == BFS) {
+        const int lev = R.r;
+        if (val[u] == lev && val[t] > lev + 1) {
+            val[t] = lev + 1;
+            acc.u++;
+        }
+    } else {
+        const int lu = val[u], lt = val[t];
+        if (lu < lt) {
+            const int old = atomicMin(&val[t], lu);
+            if (lu < old) acc.u++;
+        } else if (lt < lu && !R.g.symmetric) {
+            const int old = atomicMin(&val[u], lt);
+            if (lt < old) acc.u++;
+        }
+    }
+}
+
+template <int A>
+__global__ __launch_bounds__(256) void k_esync(Round R) {
+    if (!round_begin(R)) return;
+    const DevGraph& g = R.g;
+    const int m = g.m;
+    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long tt = (long long)gridDim.x * blockDim.x;
+    const int m4 = m & ~3;
+    Acc acc;
+    for (long long e = tid * 4; e < m4; e += tt * 4) {
+        const int4 s = *reinterpret_cast<const int4*>(g.src + e);
+        const int4 c = *reinterpret_cast<const int4*>(g.col + e);
+        edge_sync_one<A>(R, s.x, c.x, (int)e, acc);
+        edge_sync_one<A>(R, s.y, c.y, (int)e + 1, acc);
+        edge_sync_one<A>(R, s.z, c.z, (int)e + 2, acc);
+        edge_sync_one<A>(R, s.w, c.w, (int)e + 3, acc);
+    }
+    for (long long e = m4 + tid; e < m; e += tt) edge_sync_one<A>(R, g.src[e], g.col[e], (int)e, acc);
+    block_finish(R, acc, R.r % 3);
+}
+
+// Asynchronous vertex round: the frontier of round r is the set of flagged
+// vertices; each wavefront scans 64 tile flags at a time and serves the
+// flagged tiles it finds.
+template <int A, int MAP>
+__global__ __launch_bounds__(256) void k_vasync(Round R) {
+    if (!round_begin(R)) return;
+    const DevGraph& g = R.g;
+    const int* row = A == CC ? g.srow : g.row;
+    const int* col = A == CC ? g.scol : g.col;
+    const int n = g.n;
+    const int cur = R.r & 1, nxt = cur ^ 1;
+    unsigned char* vf = R.ws.vflag[cur];
+    unsigned char* tf = R.ws.tflag[cur];
+    const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    const long long gw = (long long)blockIdx.x * wpb + (threadIdx.x >> 6);
+    const long long tw = (long long)gridDim.x * wpb;
+    const long long ntiles = (n + 63) / 64;
+    const long long nitems = (ntiles + 63) / 64 * kParts;
+    Acc acc;
+    for (long long it = gw; it < nitems; it += tw) {
+        const long long st = it / kParts;
+        const int part = (int)(it % kParts);
+        const long long t = st * 64 + lane;
+        const bool mine = lane / (64 / kParts) == part;
+        const bool tfl = mine && t < ntiles && tf[t] != 0;
+        unsigned long long tm = __ballot(tfl);
+        if (tfl) tf[t] = 0;
+        while (tm) {
+            const int b = __ffsll(tm) - 1;
+            tm &= tm - 1;
+            const int u = (int)((st * 64 + b) * 64 + lane);
+            const bool on = u < n && vf[u] != 0;
+            if (on) vf[u] = 0;
+            int rb = 0, re = 0, sv = 0;
+            if (on) {
+                rb = row[u];
+                re = row[u + 1];
+                tail_value<A, true>(R, u, sv, acc);
+                acc.v++;
+            }
+            if (MAP == MAP_BALANCED) {
+                const bool hv = on && re - rb > g.heavy;
+                heavy_append(R, cur, hv, u, rb, re);
+                wave_rows_balanced(on && !hv ? rb : 0, on && !hv ? re - rb : 0, sv,
+                                   [&](int e, int s) {
+                                       int t2;
+                                       acc.e++;
+                                       if (relax_edge<A>(R, col, e, s, t2)) {
+                                           push(R, nxt, t2);
+                                           acc.p++;
+                                       }
+                                   });
+            } else if (MAP == MAP_THREAD) {
+                if (on)
+                    for (int e = rb; e < re; ++e) {
+                        int t2;
+                        acc.e++;
+                        if (relax_edge<A>(R, col, e, sv, t2)) {
+                            push(R, nxt, t2);
+                            acc.p++;
+                        }
+                    }
+            } else {  // MAP_WAVE: the wavefront serves its flagged rows in turn
+                unsigned long long am = __ballot(on);
+                while (am) {
+                    const int o = __ffsll(am) - 1;
+                    am &= am - 1;
+                    const int ob = __shfl(rb, o, 64), oe = __shfl(re, o, 64);
+                    const int os = __shfl(sv, o, 64);
+                    for (int e = ob + lane; e < oe; e += 64) {
+                        int t2;
+                        acc.e++;
+                        if (relax_edge<A>(R, col, e, os, t2)) {
+                            push(R, nxt, t2);
+                            acc.p++;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    block_finish(R, acc, R.r % 3);
+}
+
+// Asynchronous edge round: for every flagged tile the wavefront walks the
+// tile's edge-list range lane by lane (one lane per edge, source from the
+// edge list) and relaxes the edges whose source is on the frontier.  Runs of
+// light rows are walked; heavy flagged rows go to the chunk queue.
+template <int A>
+__global__ __launch_bounds__(256) void k_easync(Round R) {
+    if (!round_begin(R)) return;
+    const DevGraph& g = R.g;
+    const int* row = A == CC ? g.srow : g.row;
+    const int* col = A == CC ? g.scol : g.col;
+    const int* src = A == CC ? g.ssrc : g.src;
+    const int n = g.n;
+    const int cur = R.r & 1, nxt = cur ^ 1;
+    unsigned char* vf = R.ws.vflag[cur];
+    unsigned char* tf = R.ws.tflag[cur];
+    const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    const long long gw = (long long)blockIdx.x * wpb + (threadIdx.x >> 6);
+    const long long tw = (long long)gridDim.x * wpb;
+    const long long ntiles = (n + 63) / 64;
+    const long long nitems = (ntiles + 63) / 64 * kParts;
+    Acc acc;
+    for (long long it = gw; it < nitems; it += tw) {
+        const long long st = it / kParts;
+        const int part = (int)(it % kParts);
+        const long long t = st * 64 + lane;
+        const bool mine = lane / (64 / kParts) == part;
+        const bool tfl = mine && t < ntiles && tf[t] != 0;
+        unsigned long long tm = __ballot(tfl);
+        if (tfl) tf[t] = 0;
+        while (tm) {
+            const int b = __ffsll(tm) - 1;
+            tm &= tm - 1;
+            const int base_v = (int)((st * 64 + b) * 64);
+            const int u = base_v + lane;
+            const bool in = u < n;
+            const bool on = in && vf[u] != 0;
+            if (on) vf[u] = 0;
+            int rb = 0, re = 0, sv = 0;
+            if (in) {
+                rb = row[u];
+                re = row[u + 1];
+            }
+            if (on) {
+                tail_value<A, true>(R, u, sv, acc);
+                acc.v++;
+            }
+            const bool light = in && re - rb <= g.heavy;
+            heavy_append(R, cur, on && !light, u, rb, re);
+            const unsigned long long am = __ballot(on && light);
+            if (am == 0) continue;
+            // walk maximal runs of light rows that contain a flagged row
+            unsigned long long lm = __ballot(light);
+            while (lm) {
+                const int a = __ffsll(lm) - 1;
+                const unsigned long long rest = ~(lm >> a);
+                const int len = rest == 0 ? 64 - a : __ffsll(rest) - 1;
+                const unsigned long long run = (len == 64 ? ~0ull : ((1ull << len) - 1)) << a;
+                lm &= ~run;
+                if ((am & run) == 0) continue;
+                const int e0 = __shfl(rb, a, 64);
+                const int e1 = __shfl(re, a + len - 1, 64);
+                for (int eb = e0; eb < e1; eb += 64) {
+                    const int e = eb + lane;
+                    int bit = 0;
+                    bool act = false;
+                    if (e < e1) {
+                        bit = src[e] - base_v;
+                        act = (am >> bit) & 1;
+                    }
+                    // the tail's value is held by the lane of that vertex
+                    const int os = __shfl(sv, bit, 64);
+                    if (act) {
+                        int t2;
+                        acc.e++;
+                        if (relax_edge<A>(R, col, e, os, t2)) {
+                            push(R, nxt, t2);
+                            acc.p++;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    block_finish(R, acc, R.r % 3);
+}
+
+// Heavy chunks queued by the light kernel of the same round.
+template <int A>
+__global__ __launch_bounds__(256) void k_heavy(Round R) {
+    Ctl* ctl = R.ws.ctl;
+    if (*(volatile int*)&ctl->done) return;
+    const DevGraph& g = R.g;
+    const int* row = A == CC ? g.srow : g.row;
+    const int* col = A == CC ? g.scol : g.col;
+    const int cur = R.r & 1, nxt = cur ^ 1;
+    const int cnt = *(volatile int*)&ctl->hq_count[cur];
+    const int2* q = R.ws.hq[cur];
+    const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    const long long gw = (long long)blockIdx.x * wpb + (threadIdx.x >> 6);
+    const long long tw = (long long)gridDim.x * wpb;
+    Acc acc;
+    for (long long it = gw; it < cnt; it += tw) {
+        const int2 c = q[it];
+        const int u = c.x;
+        const int e1 = min(c.y + g.chunk, row[u + 1]);
+        int sv = A == BFS ? R.r : R.val[u];
+        for (int e = c.y + lane; e < e1; e += 64) {
+            int t2;
+            acc.e++;
+            if (relax_edge<A>(R, col, e, sv, t2)) {
+                push(R, nxt, t2);
+                acc.p++;
+            }
+        }
+    }
+    block_finish(R, acc, R.r % 3);
+}
+
+// CC shortcut pass used after an edge sweep: label[v] = label[label[v]].
+__global__ __launch_bounds__(256) void k_jump(Round R) {
+    if (*(volatile int*)&R.ws.ctl->done) return;
+    const int n = R.g.n;
+    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long tt = (long long)gridDim.x * blockDim.x;
+    Acc acc;
+    for (long long v = tid; v < n; v += tt) {
+        const int x = R.val[v];
+        const int y = R.val[x];
+        if (y < x) {
+            const int old = atomicMin(&R.val[v], y);
+            if (y < old) acc.u++;
+        }
+    }
+    block_finish(R, acc, R.r % 3);
+}
+
+// ------------------------------------------------------- graph build ----
+
+__global__ __launch_bounds__(256) void k_fill_src(const int* row, int n, int* src) {
+    const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    const long long gw = (long long)blockIdx.x * wpb + (threadIdx.x >> 6);
+    const long long tw = (long long)gridDim.x * wpb;
+    const long long ntiles = (n + 63) / 64;
+    for (long long t = gw; t < ntiles; t += tw) {
+        const int u = (int)(t * 64 + lane);
+        int rb = 0, deg = 0;
+        if (u < n) {
+            rb = row[u];
+            deg = row[u + 1] - rb;
+        }
+        wave_rows_balanced(rb, deg, u, [&](int e, int s) { src[e] = s; });
+    }
+}
+
+__global__ __launch_bounds__(256) void k_count_in(const int* col, int m, int* indeg) {
+    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long tt = (long long)gridDim.x * blockDim.x;
+    for (long long e = tid; e < m; e += tt) atomicAdd(&indeg[col[e]], 1);
+}
+
+// Both-directions CSR: row u holds u's out-edges (input order) followed by
+// the tails of its in-edges (order unspecified).
+__global__ __launch_bounds__(256) void k_sym_fill(const int* row, const int* col, const int* src,
+                                                  int m, const int* srow, int* cursor, int* scol) {
+    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long tt = (long long)gridDim.x * blockDim.x;
+    for (long long e = tid; e < m; e += tt) {
+        const int u = src[e], v = col[e];
+        scol[srow[u] + (int)(e - row[u])] = v;
+        const int pos = srow[v] + (row[v + 1] - row[v]) + atomicAdd(&cursor[v], 1);
+        scol[pos] = u;
+    }
+}
+
+// ----------------------------------------------------- launch wrappers ----
+
+#define GG_LAUNCH(kernel, grid, block, s, ...)                                   \
+    do {                                                                         \
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, s, __VA_ARGS__);  \
+        return hipGetLastError();                                                \
+    } while (0)
+
+hipError_t launch_init(const Round& R, int algo, bool async, int grid, int block, hipStream_t s) {
+    GG_LAUNCH(k_init, grid, block, s, R, algo, async ? 1 : 0);
+}
+
+template <int A>
+static hipError_t vsync_a(const Round& R, int grid, int block, hipStream_t s) {
+    switch (R.mapping) {
+        case MAP_THREAD: GG_LAUNCH((k_vsync<A, MAP_THREAD>), grid, block, s, R);
+        case MAP_WAVE: GG_LAUNCH((k_vsync<A, MAP_WAVE>), grid, block, s, R);
+        default: GG_LAUNCH((k_vsync<A, MAP_BALANCED>), grid, block, s, R);
+    }
+}
+
+hipError_t launch_vsync(const Round& R, int algo, int grid, int block, hipStream_t s) {
+    switch (algo) {
+        case SSSP: return vsync_a<SSSP>(R, grid, block, s);
+        case BFS: return vsync_a<BFS>(R, grid, block, s);
+        default: return vsync_a<CC>(R, grid, block, s);
+    }
+}
+
+hipError_t launch_esync(const Round& R, int algo, int grid, int block, hipStream_t s) {
+    switch (algo) {
+        case SSSP: GG_LAUNCH(k_esync<SSSP>, grid, block, s, R);
+        case BFS: GG_LAUNCH(k_esync<BFS>, grid, block, s, R);
+        default: GG_LAUNCH(k_esync<CC>, grid, block, s, R);
+    }
+}
+
+template <int A>
+static hipError_t vasync_a(const Round& R, int grid, int block, hipStream_t s) {
+    switch (R.mapping) {
+        case MAP_THREAD: GG_LAUNCH((k_vasync<A, MAP_THREAD>), grid, block, s, R);
+        case MAP_WAVE: GG_LAUNCH((k_vasync<A, MAP_WAVE>), grid, block, s, R);
+        default: GG_LAUNCH((k_vasync<A, MAP_BALANCED>), grid, block, s, R);
+    }
+}
+
+hipError_t launch_vasync(const Round& R, int algo, int grid, int block, hipStream_t s) {
+    switch (algo) {
+        case SSSP: return vasync_a<SSSP>(R, grid, block, s);
+        case BFS: return vasync_a<BFS>(R, grid, block, s);
+        default: return vasync_a<CC>(R, grid, block, s);
+    }
+}
+
+hipError_t launch_easync(const Round& R, int algo, int grid, int block, hipStream_t s) {
+    switch (algo) {
+        case SSSP: GG_LAUNCH(k_easync<SSSP>, grid, block, s, R);
+        case BFS: GG_LAUNCH(k_easync<BFS>, grid, block, s, R);
+        default: GG_LAUNCH(k_easync<CC>, grid, block, s, R);
+    }
+}
+
+hipError_t launch_heavy(const Round& R, int algo, int grid, int block, hipStream_t s) {
+    switch (algo) {
+        case SSSP: GG_LAUNCH(k_heavy<SSSP>, grid, block, s, R);
+        case BFS: GG_LAUNCH(k_heavy<BFS>, grid, block, s, R);
+        default: GG_LAUNCH(k_heavy<CC>, grid, block, s, R);
+    }
+}
+
+hipError_t launch_jump(const Round& R, int grid, int block, hipStream_t s) {
+    GG_LAUNCH(k_jump, grid, block, s, R);
+}
+
+hipError_t launch_fill_src(const int* row, int n, int* src, int grid, int block, hipStream_t s) {
+    GG_LAUNCH(k_fill_src, grid, block, s, row, n, src);
+}
+
+hipError_t launch_count_in(const int* col, int m, int* indeg, int grid, int block, hipStream_t s) {
+    GG_LAUNCH(k_count_in, grid, block, s, col, m, indeg);
+}
+
+hipError_t launch_sym_fill(const int* row, const int* col, const int* src, int n, int m,
+                           const int* srow, int* cursor, int* scol, int grid, int block,
+                           hipStream_t s) {
+    (void)n;
+    GG_LAUNCH(k_sym_fill, grid, block, s, row, col, src, m, srow, cursor, scol);
+}
+
+}  // namespace gg

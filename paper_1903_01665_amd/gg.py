@@ -1,0 +1,240 @@
+"""Thin ctypes binding of libgg (the C ABI declared in include/gg.h).
+
+Argument marshalling only: every step of a traversal runs in the HIP kernels
+of ``libgg.so``.  PyTorch provides device memory (int32 tensors on cuda:0) and
+the current HIP stream.  There is no fallback: if ``libgg.so`` is missing or a
+call fails, an exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgg.so")
+INF = 2**31 - 1
+
+# enums of gg.h
+VERTEX, EDGE, MODE_AUTO = 0, 1, 2
+SYNC, ASYNC, SCHED_AUTO = 0, 1, 2
+MAP_AUTO, MAP_THREAD, MAP_WAVE, MAP_BALANCED = 0, 1, 2, 3
+ALGO_SSSP, ALGO_BFS, ALGO_CC = 0, 1, 2
+SYMMETRIZE, INPUT_ON_DEVICE, SYMMETRIC = 1, 2, 4
+OPT_CC_NO_JUMP = 1
+
+STATUS = {0: "GG_OK", -1: "GG_EINVAL", -2: "GG_ENOMEM", -3: "GG_EHIP", -4: "GG_EBUSY",
+          -5: "GG_ENOTSUP", -6: "GG_ETIMEOUT", -7: "GG_EITER"}
+
+# every symbol include/gg.h declares
+EXPORTS = ["gg_graph_upload", "gg_graph_free", "gg_graph_info", "gg_graph_error", "gg_sssp",
+           "gg_bfs", "gg_cc", "gg_ws_create", "gg_ws_free", "gg_sssp_ex", "gg_bfs_ex",
+           "gg_cc_ex", "gg_last_stats", "gg_resolve", "gg_status_str", "gg_version"]
+
+
+class GGError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {STATUS.get(code, code)}")
+        self.code = code
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("sched", ctypes.c_int32), ("mapping", ctypes.c_int32),
+                ("block_threads", ctypes.c_int32), ("max_blocks", ctypes.c_int32),
+                ("heavy_threshold", ctypes.c_int32), ("time_limit_ms", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("algo", ctypes.c_int32), ("mode", ctypes.c_int32), ("sched", ctypes.c_int32),
+                ("mapping", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("iterations", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
+                ("block_threads", ctypes.c_int32), ("edges_processed", ctypes.c_int64),
+                ("vertices_processed", ctypes.c_int64), ("updates", ctypes.c_int64),
+                ("pushes", ctypes.c_int64), ("reserved", ctypes.c_int64 * 4)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libgg.so (raises when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    i32, i64, u32, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p
+    P = ctypes.POINTER
+    L.gg_graph_upload.argtypes = [i32, i64, vp, vp, vp, u32, vp, P(vp)]
+    L.gg_graph_free.argtypes = [vp]
+    L.gg_graph_info.argtypes = [vp, P(i32), P(i64), P(i32), P(i32), P(i32)]
+    L.gg_graph_error.argtypes = [vp]
+    L.gg_sssp.argtypes = [vp, i32, i32, i32, vp, vp]
+    L.gg_bfs.argtypes = [vp, i32, i32, i32, vp, vp]
+    L.gg_cc.argtypes = [vp, i32, i32, vp, vp]
+    L.gg_ws_create.argtypes = [vp, P(vp)]
+    L.gg_ws_free.argtypes = [vp]
+    L.gg_sssp_ex.argtypes = [vp, vp, i32, P(Opts), vp, vp]
+    L.gg_bfs_ex.argtypes = [vp, vp, i32, P(Opts), vp, vp]
+    L.gg_cc_ex.argtypes = [vp, vp, P(Opts), vp, vp]
+    L.gg_last_stats.argtypes = [vp, vp, P(Stats)]
+    L.gg_resolve.argtypes = [vp, i32, P(Opts), P(Opts)]
+    L.gg_status_str.argtypes = [i32]
+    L.gg_status_str.restype = ctypes.c_char_p
+    L.gg_version.argtypes = []
+    for f in EXPORTS:
+        if f != "gg_status_str":
+            getattr(L, f).restype = ctypes.c_int32
+    if L.gg_version() != 1:
+        raise RuntimeError("libgg.so version mismatch")
+    _lib = L
+    return L
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise GGError(rc, what)
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _arr(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+def make_opts(mode=MODE_AUTO, sched=SCHED_AUTO, mapping=MAP_AUTO, max_blocks=0, flags=0,
+              time_limit_ms=0) -> Opts:
+    o = Opts()
+    o.mode, o.sched, o.mapping = mode, sched, mapping
+    o.max_blocks, o.flags, o.time_limit_ms = max_blocks, flags, time_limit_ms
+    return o
+
+
+class Workspace:
+    """Per-query scratch so that several traversals of one graph overlap."""
+
+    def __init__(self, graph: "Graph"):
+        self.graph = graph
+        h = ctypes.c_void_p()
+        _check(lib().gg_ws_create(graph.handle, ctypes.byref(h)), "gg_ws_create")
+        self.handle = h
+
+    def free(self):
+        if self.handle:
+            _check(lib().gg_ws_free(self.handle), "gg_ws_free")
+            self.handle = None
+
+
+class Graph:
+    """A graph resident in HBM (CSR, edge list, optional both-directions CSR)."""
+
+    def __init__(self, n, row_ptr, col, w=None, symmetrize=False, symmetric=False, stream=None):
+        L = lib()
+        self.n = int(n)
+        self._row, prow = _arr(row_ptr)
+        self._col, pcol = _arr(col if len(col) else np.zeros(1, np.int32))
+        m = int(self._row[-1])
+        pw = None
+        if w is not None:
+            self._w, pw = _arr(w if len(w) else np.zeros(1, np.int32))
+        flags = (SYMMETRIZE if symmetrize else 0) | (SYMMETRIC if symmetric else 0)
+        h = ctypes.c_void_p()
+        _check(L.gg_graph_upload(self.n, m, prow, pcol, pw, flags, _stream_ptr(stream),
+                                 ctypes.byref(h)), "gg_graph_upload")
+        self.handle = h
+        self.m = m
+        del self._row, self._col
+        if w is not None:
+            del self._w
+
+    @classmethod
+    def from_host(cls, hg, symmetrize=False, stream=None):
+        """Upload a :class:`paper_1903_01665_amd.gen.HostGraph`."""
+        return cls(hg.n, hg.row_ptr, hg.col, hg.w, symmetrize=symmetrize and not hg.symmetric,
+                   symmetric=hg.symmetric, stream=stream)
+
+    def info(self):
+        n, m, d, hw, hs = (ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(),
+                           ctypes.c_int32())
+        _check(lib().gg_graph_info(self.handle, ctypes.byref(n), ctypes.byref(m),
+                                   ctypes.byref(d), ctypes.byref(hw), ctypes.byref(hs)),
+               "gg_graph_info")
+        return {"n": n.value, "m": m.value, "max_out_degree": d.value,
+                "weighted": bool(hw.value), "has_sym": bool(hs.value)}
+
+    def free(self):
+        if getattr(self, "handle", None):
+            _check(lib().gg_graph_free(self.handle), "gg_graph_free")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None) and _lib is not None:
+                _lib.gg_graph_free(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+    # -- traversals ---------------------------------------------------------
+    def _out(self, out):
+        import torch
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        if out.dtype != torch.int32 or not out.is_cuda or out.numel() < self.n or \
+                not out.is_contiguous():
+            raise ValueError("output must be a contiguous int32 cuda tensor of >= n elements")
+        return out
+
+    def _run(self, fn, what, args, opts, out, ws, stream):
+        out = self._out(out)
+        o = opts if opts is not None else make_opts()
+        wsh = ws.handle if ws is not None else None
+        rc = fn(self.handle, wsh, *args, ctypes.byref(o), ctypes.c_void_p(out.data_ptr()),
+                _stream_ptr(stream))
+        _check(rc, what)
+        return out
+
+    def sssp(self, source, mode=MODE_AUTO, sched=SCHED_AUTO, mapping=MAP_AUTO, out=None,
+             ws=None, stream=None, opts=None):
+        o = opts or make_opts(mode, sched, mapping)
+        return self._run(lib().gg_sssp_ex, "gg_sssp", [int(source)], o, out, ws, stream)
+
+    def bfs(self, source, mode=MODE_AUTO, sched=SCHED_AUTO, mapping=MAP_AUTO, out=None,
+            ws=None, stream=None, opts=None):
+        o = opts or make_opts(mode, sched, mapping)
+        return self._run(lib().gg_bfs_ex, "gg_bfs", [int(source)], o, out, ws, stream)
+
+    def cc(self, mode=MODE_AUTO, sched=SCHED_AUTO, mapping=MAP_AUTO, out=None, ws=None,
+           stream=None, opts=None):
+        o = opts or make_opts(mode, sched, mapping)
+        return self._run(lib().gg_cc_ex, "gg_cc", [], o, out, ws, stream)
+
+    def stats(self, ws=None) -> dict:
+        s = Stats()
+        rc = lib().gg_last_stats(self.handle, ws.handle if ws is not None else None,
+                                 ctypes.byref(s))
+        d = s.as_dict()
+        d["rc"] = rc
+        return d
+
+    def resolve(self, algo, opts=None) -> Opts:
+        out = Opts()
+        _check(lib().gg_resolve(self.handle, algo, ctypes.byref(opts or make_opts()),
+                                ctypes.byref(out)), "gg_resolve")
+        return out
+
+
+def status_str(code: int) -> str:
+    return lib().gg_status_str(code).decode()

@@ -1,0 +1,221 @@
+"""GPU parity: every variant of the HIP path against the CPU oracle, bit-exact.
+
+All calls go through the C ABI (libgg.so) via the ctypes binding.  Values are
+int32 and exact, so the bar is element-by-element equality.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import golden_files, path_graph, random_graph, read_golden, star
+from paper_1903_01665_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+VERTEX, EDGE, SYNC, ASYNC = 0, 1, 0, 1
+THREAD, WAVE, BALANCED = 1, 2, 3
+VARIANTS = [(VERTEX, SYNC, THREAD), (VERTEX, SYNC, WAVE), (VERTEX, SYNC, BALANCED),
+            (VERTEX, ASYNC, THREAD), (VERTEX, ASYNC, WAVE), (VERTEX, ASYNC, BALANCED),
+            (EDGE, SYNC, 0), (EDGE, ASYNC, 0)]
+VNAME = {v: f"{'vertex' if v[0] == 0 else 'edge'}-{'sync' if v[1] == 0 else 'async'}"
+            f"{['', '-thread', '-wave', '-balanced'][v[2]]}" for v in VARIANTS}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gg():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1903_01665_amd import gg as _gg
+    _gg.lib()
+    return _gg
+
+
+def expected(hg, source):
+    out = {"bfs": oracle.bfs(hg.n, hg.row_ptr, hg.col, source),
+           "cc": oracle.cc(hg.n, hg.row_ptr, hg.col)}
+    if hg.w is not None:
+        out["sssp"] = oracle.sssp(hg.n, hg.row_ptr, hg.col, hg.w, source)
+    return out
+
+
+def check_graph(gg, hg, source, name, variants=VARIANTS, algos=("sssp", "bfs", "cc"),
+                want=None):
+    want = want or expected(hg, source)
+    g = gg.Graph.from_host(hg, symmetrize=True)
+    try:
+        for v in variants:
+            for algo in algos:
+                if algo == "sssp" and hg.w is None:
+                    continue
+                say(f"[gpu] {name} n={hg.n} m={hg.m} {algo} {VNAME[v]}")
+                if algo == "cc":
+                    got = g.cc(*v)
+                else:
+                    got = getattr(g, algo)(source, *v)
+                got = got.cpu().numpy()[: hg.n]
+                st = g.stats()
+                assert st["rc"] == 0, (name, algo, VNAME[v], st)
+                assert st["iterations"] >= 1
+                bad = np.flatnonzero(got != want[algo])
+                assert bad.size == 0, (f"{name} {algo} {VNAME[v]}: {bad.size} mismatches, first "
+                                       f"v={bad[0]} got={got[bad[0]]} want={want[algo][bad[0]]}")
+    finally:
+        g.free()
+
+
+@pytest.mark.parametrize("fname", golden_files())
+def test_golden(gg, fname):
+    hg, s, want = read_golden(fname)
+    check_graph(gg, hg, s, fname, want=want)
+
+
+def test_random_tiny_graphs(gg):
+    rng = np.random.default_rng(20190304)
+    for i in range(24):
+        n = int(rng.integers(1, 300))
+        m = int(rng.integers(0, 6 * n + 1))
+        hg = random_graph(rng, n, m, 0, 9, name=f"tiny{i}")
+        check_graph(gg, hg, int(rng.integers(0, n)), hg.name)
+
+
+def test_no_edges_and_single_vertex(gg):
+    check_graph(gg, gen.from_edges(1, [], [], []), 0, "n1")
+    check_graph(gg, gen.from_edges(1, [0], [0], [4]), 0, "n1-loop")
+    check_graph(gg, gen.from_edges(130, [], [], []), 77, "m0")
+
+
+def test_heavy_rows_are_chunked(gg):
+    # hubs above the heavy threshold (512) in both directions, plus a tail
+    rng = np.random.default_rng(5)
+    src, dst = [], []
+    for hub, deg in [(0, 3000), (1, 700), (65, 1500)]:
+        src += [hub] * deg
+        dst += list(rng.integers(0, 4000, size=deg))
+    src += list(rng.integers(0, 4000, size=6000))
+    dst += list(rng.integers(0, 4000, size=6000))
+    w = rng.integers(1, 50, size=len(src))
+    hg = gen.from_edges(4000, src, dst, w, name="hubs")
+    check_graph(gg, hg, 0, "hubs")
+    check_graph(gg, hg, 3999, "hubs-s3999")
+    hg = star(600, [[5, 3], [1]] + [[7]] * 598)
+    check_graph(gg, hg, 0, "star600")
+
+
+def test_long_path(gg):
+    hg = path_graph(1500, np.arange(1, 1500) % 7 + 1)
+    check_graph(gg, hg, 0, "path1500")
+
+
+def test_er16k(gg):
+    hg = gen.workload("er16k")
+    check_graph(gg, hg, 0, "er16k")
+
+
+def test_rmat14(gg):
+    hg = gen.workload("rmat14")
+    s = int(gen.pick_sources(hg, 1, stream=gen.STREAM["sources"])[0])
+    check_graph(gg, hg, s, "rmat14")
+
+
+def test_grid96(gg):
+    hg = gen.workload("grid96")
+    check_graph(gg, hg, 0, "grid96")
+
+
+def test_repeat_and_launch_shapes(gg):
+    """Same answer over repeats, workspaces and grid caps (race check)."""
+    hg = gen.workload("rmat13")
+    s = int(gen.pick_sources(hg, 1, stream=gen.STREAM["sources"])[0])
+    want = expected(hg, s)
+    g = gg.Graph.from_host(hg, symmetrize=True)
+    ws = gg.Workspace(g)
+    try:
+        for rep in range(3):
+            for cap in (1, 7, 64, 0):
+                for v in VARIANTS:
+                    o = gg.make_opts(*v, max_blocks=cap)
+                    say(f"[gpu] rmat13 rep={rep} cap={cap} {VNAME[v]}")
+                    use = ws if rep % 2 else None
+                    np.testing.assert_array_equal(
+                        g.sssp(s, opts=o, ws=use).cpu().numpy(), want["sssp"])
+                    np.testing.assert_array_equal(
+                        g.bfs(s, opts=o, ws=use).cpu().numpy(), want["bfs"])
+                    np.testing.assert_array_equal(
+                        g.cc(opts=o, ws=use).cpu().numpy(), want["cc"])
+    finally:
+        ws.free()
+        g.free()
+
+
+def test_cc_without_shortcut(gg):
+    hg = gen.workload("grid48")
+    want = oracle.cc(hg.n, hg.row_ptr, hg.col)
+    g = gg.Graph.from_host(hg)
+    try:
+        for v in VARIANTS:
+            say(f"[gpu] grid48 cc no-jump {VNAME[v]}")
+            o = gg.make_opts(*v, flags=gg.OPT_CC_NO_JUMP)
+            np.testing.assert_array_equal(g.cc(opts=o).cpu().numpy(), want)
+    finally:
+        g.free()
+
+
+def test_cc_needs_symmetric_arrays_except_edge_sync(gg):
+    hg = gen.workload("er300x900")
+    g = gg.Graph(hg.n, hg.row_ptr, hg.col, hg.w)  # no GG_SYMMETRIZE
+    try:
+        want = oracle.cc(hg.n, hg.row_ptr, hg.col)
+        np.testing.assert_array_equal(g.cc().cpu().numpy(), want)  # AUTO -> edge sync
+        np.testing.assert_array_equal(g.cc(EDGE, SYNC).cpu().numpy(), want)
+        for mode, sched in [(VERTEX, SYNC), (VERTEX, ASYNC), (EDGE, ASYNC)]:
+            with pytest.raises(gg.GGError) as e:
+                g.cc(mode, sched)
+            assert e.value.code == -5
+    finally:
+        g.free()
+
+
+def test_bad_calls(gg):
+    import torch
+    hg = gen.workload("er300x900")
+    g = gg.Graph(hg.n, hg.row_ptr, hg.col, None)  # unweighted
+    try:
+        with pytest.raises(gg.GGError) as e:
+            g.sssp(0)
+        assert e.value.code == -1
+        for s in (-1, hg.n):
+            with pytest.raises(gg.GGError):
+                g.bfs(s)
+        with pytest.raises(ValueError):
+            g.bfs(0, out=torch.empty(hg.n - 1, dtype=torch.int32, device="cuda"))
+    finally:
+        g.free()
+
+
+def test_two_streams_two_workspaces(gg):
+    import torch
+    hg = gen.workload("rmat12")
+    srcs = gen.pick_sources(hg, 2, stream=7)
+    want = [oracle.sssp(hg.n, hg.row_ptr, hg.col, hg.w, int(s)) for s in srcs]
+    g = gg.Graph.from_host(hg, symmetrize=True)
+    ws = [gg.Workspace(g), gg.Workspace(g)]
+    st = [torch.cuda.Stream(), torch.cuda.Stream()]
+    try:
+        outs = []
+        for i in range(2):
+            with torch.cuda.stream(st[i]):
+                outs.append(g.sssp(int(srcs[i]), ws=ws[i], stream=st[i]))
+        torch.cuda.synchronize()
+        for i in range(2):
+            np.testing.assert_array_equal(outs[i].cpu().numpy(), want[i])
+    finally:
+        for w in ws:
+            w.free()
+        g.free()
