@@ -1,0 +1,264 @@
+"""Benchmark: GTEPS of SSSP + BFS + CC on one MI355X.
+
+One step is one pass of the hot path over the resident graph: SSSP and BFS
+from one source and CC over the whole graph, each in the variant the library
+picks (AUTO).  The source rotates over 8 seeded sources with out-degree > 0.
+
+value      traversed edges of all steps / wall time of the timed steps (GTEPS);
+           traversed edges: out-edges of every reached vertex for SSSP/BFS,
+           every edge of the both-directions graph for CC.
+roofline   for the kernel with the most device time in a profiled repeat of
+           the steps: algorithmic bytes (per-unit figures x the work counters
+           of those launches) / summed launch time (HIP events on the stream
+           the kernels run on), against 8 TB/s HBM.
+cpu_baseline  the oracle (Dijkstra, FIFO BFS, union-find CC) on the same
+           graph and first source, single-threaded, timed on this host.
+
+Prints one JSON line.  ``--gpus N`` with N > 1 exits: this build uses one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+INF = 2**31 - 1
+ALGOS = ("sssp", "bfs", "cc")
+VARIANTS = {"vertex-sync": (0, 0, 3), "vertex-async": (0, 1, 3), "edge-sync": (1, 0, 0),
+            "edge-async": (1, 1, 0)}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# ------------------------------------------------------- algorithmic bytes --
+# Bytes the method itself must move per unit of executed work (int32 = 4 B).
+# round kernels:
+#   vertex sync   8 B per vertex scanned (row offset + value; every vertex,
+#                 every sweep); per edge 12 B SSSP (col, w, head value) or
+#                 8 B BFS/CC (col, head value); 4 B per update
+#   edge sync     per edge 20 B SSSP (src, col, w, two values), 16 B BFS/CC
+#                 (src, col, two values); 4 B per update
+#   vertex async  1 B per tile flag scanned; 16 B per frontier vertex (flag,
+#                 row pair, value); per edge 12 B SSSP / 8 B BFS, CC;
+#                 2 B per push (vertex and tile flag bytes)
+#   edge async    as vertex async, plus the 4 B edge-list source per edge
+# heavy kernels: per edge 12 / 8 B, per push 2 B
+# aux kernels:   init 4 B per vertex (+2 B of flags when async); CC shortcut
+#                8 B per vertex per launch
+def algorithmic_bytes(algo, mode, sched, kind, n, prof_kind, launches):
+    E = prof_kind["edges_processed"]
+    V = prof_kind["vertices_processed"]
+    U = prof_kind["updates"]
+    P = prof_kind["pushes"]
+    per_edge = 12 if algo == "sssp" else 8
+    if kind == "round":
+        if sched == 0 and mode == 0:
+            return 8 * n * launches + per_edge * E + 4 * U
+        if sched == 0 and mode == 1:
+            return (20 if algo == "sssp" else 16) * E + 4 * U
+        ntiles = (n + 63) // 64
+        extra = 4 * E if mode == 1 else 0
+        return ntiles * launches + 16 * V + per_edge * E + extra + 2 * P
+    if kind == "heavy":
+        return per_edge * E + 2 * P
+    return (4 + (2 if sched == 1 else 0)) * n + 8 * n * max(0, launches - 1)
+
+
+def traversed_edges(deg, dist):
+    return int(deg[dist < INF].sum())
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="rmat22")
+    ap.add_argument("--no-variants", action="store_true", help="skip the per-variant table")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--reps", type=int, default=3, help="repeats per variant in the table")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1903_01665_amd import gen, gg
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    gg.lib()
+
+    t = time.time()
+    hg = gen.workload(args.workload)
+    deg = hg.degrees()
+    log(f"[bench] {args.workload}: n={hg.n} m={hg.m} generated in {time.time() - t:.1f}s")
+    sources = [int(s) for s in gen.pick_sources(hg, 8, stream=gen.STREAM["sources"])]
+    t = time.time()
+    g = gg.Graph.from_host(hg, symmetrize=True)
+    torch.cuda.synchronize()
+    upload_s = time.time() - t
+    m_sym = hg.m if hg.symmetric else 2 * hg.m
+    log(f"[bench] uploaded in {upload_s:.2f}s; sources {sources}")
+
+    outs = {a: torch.empty(hg.n, dtype=torch.int32, device="cuda") for a in ALGOS}
+    auto = gg.make_opts()
+    chosen = {a: g.resolve(i, auto) for i, a in enumerate(ALGOS)}
+
+    def step(i, opts=None):
+        s = sources[i % len(sources)]
+        g.sssp(s, out=outs["sssp"], opts=opts)
+        g.bfs(s, out=outs["bfs"], opts=opts)
+        g.cc(out=outs["cc"], opts=opts)
+
+    # traversed edges per source (from the GPU results of a warm-up pass)
+    m_trav = {}
+    for i, s in enumerate(sources):
+        step(i)
+        torch.cuda.synchronize()
+        m_trav[s] = (traversed_edges(deg, outs["sssp"].cpu().numpy()),
+                     traversed_edges(deg, outs["bfs"].cpu().numpy()))
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+
+    # ------------------------------------------------------------ timed --
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(i)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    edges = sum(m_trav[sources[i % len(sources)]][0] + m_trav[sources[i % len(sources)]][1]
+                + m_sym for i in range(args.steps))
+    gteps = edges / elapsed / 1e9
+    log(f"[bench] {args.steps} steps in {elapsed * 1e3:.1f} ms -> {gteps:.2f} GTEPS")
+
+    # ----------------------------------------- profiled repeat: roofline --
+    per_kernel = []
+    for i in range(args.steps):
+        s = sources[i % len(sources)]
+        for ai, a in enumerate(ALGOS):
+            o = gg.make_opts(flags=gg.OPT_PROFILE)
+            if a == "cc":
+                g.cc(out=outs[a], opts=o)
+            else:
+                getattr(g, a)(s, out=outs[a], opts=o)
+            p = g.profile()
+            c = chosen[a]
+            for kind in gg.KINDS:
+                pk = p[kind]
+                if pk["launches"] == 0:
+                    continue
+                b = algorithmic_bytes(a, c.mode, c.sched, kind, hg.n, pk, pk["launches"])
+                per_kernel.append((a, kind, pk["launches"], pk["total_ms"], b))
+    agg = {}
+    for a, kind, L, ms, b in per_kernel:
+        x = agg.setdefault((a, kind), [0, 0.0, 0])
+        x[0] += L
+        x[1] += ms
+        x[2] += b
+    (da, dk), (dl, dms, db) = max(agg.items(), key=lambda kv: kv[1][1])
+    c = chosen[da]
+    mname = ["vertex", "edge"][c.mode] + "-" + ["sync", "async"][c.sched]
+    achieved = db / (dms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": f"{da} {mname} {dk} kernel", "launches": dl,
+                "avg_launch_us": round(dms * 1e3 / dl, 2),
+                "algorithmic_bytes_per_launch": int(db / dl)}
+    kernel_table = {f"{a}/{k}": {"launches": L, "ms": round(ms, 3),
+                                 "GBps": round(b / (ms * 1e-3) / 1e9, 1) if ms > 0 else None}
+                    for (a, k), (L, ms, b) in agg.items()}
+    log(f"[bench] dominant: {roofline['kernel']} {achieved:.0f} GB/s over {dl} launches")
+
+    # ------------------------------------------------ per-variant table --
+    variants = {}
+    if not args.no_variants:
+        s = sources[0]
+        for a in ALGOS:
+            for vname, (mode, sched, mp) in VARIANTS.items():
+                o = gg.make_opts(mode, sched, mp)
+                times = []
+                for _ in range(args.reps):
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    if a == "cc":
+                        g.cc(out=outs[a], opts=o)
+                    else:
+                        getattr(g, a)(s, out=outs[a], opts=o)
+                    torch.cuda.synchronize()
+                    times.append(time.perf_counter() - t1)
+                st = g.stats()
+                tm = float(np.median(times))
+                me = m_sym if a == "cc" else m_trav[s][0 if a == "sssp" else 1]
+                variants[f"{a}/{vname}"] = {"ms": round(tm * 1e3, 3),
+                                            "GTEPS": round(me / tm / 1e9, 3),
+                                            "iterations": st["iterations"],
+                                            "edges_processed": st["edges_processed"]}
+                log(f"[bench] {a:4s} {vname:13s} {tm * 1e3:9.3f} ms "
+                    f"{me / tm / 1e9:7.2f} GTEPS it={st['iterations']}")
+
+    # ------------------------------------------------- CPU oracle leg --
+    cpu = None
+    verified = None
+    if not args.no_cpu:
+        import oracle
+
+        s = sources[0]
+        t1 = time.perf_counter()
+        d = oracle.sssp(hg.n, hg.row_ptr, hg.col, hg.w, s)
+        t2 = time.perf_counter()
+        b = oracle.bfs(hg.n, hg.row_ptr, hg.col, s)
+        t3 = time.perf_counter()
+        lab = oracle.cc(hg.n, hg.row_ptr, hg.col)
+        t4 = time.perf_counter()
+        ce = m_trav[s][0] + m_trav[s][1] + m_sym
+        cpu = {"value": round(ce / (t4 - t1) / 1e9, 4), "unit": "GTEPS", "cores": 1,
+               "kind": "oracle",
+               "sample": f"full {args.workload} graph, source {s}: Dijkstra + FIFO BFS + "
+                         f"union-find CC, one thread",
+               "seconds": {"sssp": round(t2 - t1, 3), "bfs": round(t3 - t2, 3),
+                           "cc": round(t4 - t3, 3)}}
+        step(0)
+        torch.cuda.synchronize()
+        verified = bool(np.array_equal(outs["sssp"].cpu().numpy(), d) and
+                        np.array_equal(outs["bfs"].cpu().numpy(), b) and
+                        np.array_equal(outs["cc"].cpu().numpy(), lab))
+        log(f"[bench] oracle {t4 - t1:.2f}s ({cpu['value']} GTEPS); GPU results match: {verified}")
+
+    line = {
+        "metric": "GTEPS (SSSP+BFS+CC)", "value": round(gteps, 3), "unit": "GTEPS",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(elapsed * 1e3 / args.steps, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": args.workload, "n": hg.n, "m": hg.m, "m_sym": m_sym,
+                   "step": "sssp+bfs+cc, AUTO variants",
+                   "variant": {a: {"mode": ["vertex", "edge"][chosen[a].mode],
+                                   "sched": ["sync", "async"][chosen[a].sched],
+                                   "mapping": chosen[a].mapping} for a in ALGOS},
+                   "sources": sources, "upload_s": round(upload_s, 2),
+                   "verified_vs_oracle": verified},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": kernel_table,
+        "variants": variants,
+    }
+    print(json.dumps(line), flush=True)
+    g.free()
+
+
+if __name__ == "__main__":
+    main()

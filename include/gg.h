@@ -98,6 +98,8 @@ typedef struct {
 #define GG_OPT_CC_NO_JUMP 1u /* CC: plain label propagation, without the label[label[v]]
                                 shortcut (the result is the same; the shortcut only
                                 shortens high-diameter graphs) */
+#define GG_OPT_PROFILE 2u    /* record a HIP event pair around every kernel launch of the
+                                call (on the caller's stream); read with gg_last_profile */
 
 /* Statistics of the last traversal run on a workspace. */
 typedef struct {
@@ -111,6 +113,22 @@ typedef struct {
     int64_t pushes;                     /* worklist insertions */
     int64_t reserved[4];
 } gg_stats;
+
+/* Per-kernel-kind timing and work of the last traversal run with
+ * GG_OPT_PROFILE.  Kinds: 0 = round kernels (sweeps / worklist rounds),
+ * 1 = heavy-row chunk kernels, 2 = auxiliary kernels (init, CC shortcut). */
+#define GG_KINDS 3
+typedef struct {
+    int32_t launches;
+    float total_ms;   /* sum of per-launch event times */
+    int64_t edges_processed, vertices_processed, updates, pushes;
+} gg_kind_profile;
+
+typedef struct {
+    int32_t profiled; /* 0 when the last run was not profiled */
+    int32_t rounds;   /* round kernels launched (including those past the end) */
+    gg_kind_profile kind[GG_KINDS];
+} gg_profile;
 
 /* Upload a graph given in CSR: row_ptr[n+1] (row_ptr[0] == 0,
  * non-decreasing, row_ptr[n] == m), col[m] in [0, n), w[m] >= 0 or NULL for
@@ -174,6 +192,10 @@ int gg_cc_ex(gg_graph g, gg_ws ws, const gg_opts* opts, int32_t* label_out_dev, 
  * for that traversal to finish.  Returns the traversal's device-side status
  * (GG_ETIMEOUT, GG_EITER) if it failed, GG_OK otherwise. */
 int gg_last_stats(gg_graph g, gg_ws ws, gg_stats* out);
+
+/* Timing of the last traversal on a workspace (NULL = default) run with
+ * GG_OPT_PROFILE.  Waits for the traversal to finish. */
+int gg_last_profile(gg_graph g, gg_ws ws, gg_profile* out);
 
 /* Resolve AUTO fields of opts for an algorithm on this graph, as a call
  * would (the autotuner's table, else built-in rules). */

@@ -81,6 +81,12 @@ struct gg_ws_s {
     bool used = false;
     gg_stats last{};
     bool is_default = false;
+    // GG_OPT_PROFILE: an event pair and a kind per launch of the last call
+    std::vector<hipEvent_t> pev;
+    std::vector<int> pkind;
+    int nlaunch = 0;
+    bool profiled = false;
+    int rounds = 0;
 };
 
 struct gg_graph_s {
@@ -145,6 +151,9 @@ void free_ws_arrays(gg_ws_s* ws) {
     if (ws->h_done) hipHostFree(ws->h_done);
     for (auto& e : ws->ev)
         if (e) hipEventDestroy(e);
+    for (auto& e : ws->pev)
+        if (e) hipEventDestroy(e);
+    ws->pev.clear();
     if (ws->finished) hipEventDestroy(ws->finished);
     ws->vflag_mem = nullptr;
     ws->hq_mem = nullptr;
@@ -166,7 +175,7 @@ int make_ws(gg_graph g, gg_ws_s** out) {
     if (e == hipSuccess) e = dalloc(&ws->vflag_mem, (size_t)(2 * (vbytes + tbytes)));
     if (e == hipSuccess) e = dalloc(&ws->hq_mem, (size_t)(2 * std::max(cap, 1LL)));
     if (e == hipSuccess) e = dalloc(&ws->dev.ctl, 1);
-    if (e == hipSuccess) e = dalloc(&ws->dev.stat, kMaxStatBlocks);
+    if (e == hipSuccess) e = dalloc(&ws->dev.stat, (size_t)kKinds * kMaxStatBlocks);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&ws->h_done), 4 * sizeof(int));
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ws->ev[0], hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ws->ev[1], hipEventDisableTiming);
@@ -301,7 +310,34 @@ int run(gg_graph g, gg_ws ws, int algo, int source, const gg_opts* opts, int* ou
     const bool need_jump = cc && edge && !async && R.jump;
     const int g_jump = grid((n + kBlock - 1) / kBlock);
 
-    HIPCHK(g, launch_init(R, algo, async, g_init, kBlock, s));
+    const bool prof = (o.flags & GG_OPT_PROFILE) != 0;
+    ws->profiled = prof;
+    ws->nlaunch = 0;
+    // every launch goes through here so that profiling brackets it
+    auto launch = [&](int kind, auto&& fn) -> hipError_t {
+        hipError_t e = hipSuccess;
+        const int i = ws->nlaunch;
+        if (prof) {
+            while ((int)ws->pev.size() < 2 * (i + 1)) {
+                hipEvent_t ev;
+                e = hipEventCreate(&ev);
+                if (e != hipSuccess) return e;
+                ws->pev.push_back(ev);
+            }
+            if ((int)ws->pkind.size() < i + 1) ws->pkind.resize(i + 1);
+            e = hipEventRecord(ws->pev[2 * i], s);
+            if (e != hipSuccess) return e;
+        }
+        e = fn();
+        if (prof && e == hipSuccess) {
+            e = hipEventRecord(ws->pev[2 * i + 1], s);
+            ws->pkind[i] = kind;
+            ws->nlaunch = i + 1;
+        }
+        return e;
+    };
+
+    HIPCHK(g, launch(KIND_AUX, [&] { return launch_init(R, algo, async, g_init, kBlock, s); }));
 
     // bound on rounds: every productive round fixes at least one more vertex
     const long long max_rounds = n + 2;
@@ -314,13 +350,16 @@ int run(gg_graph g, gg_ws ws, int algo, int source, const gg_opts* opts, int* ou
         const long long r_end = std::min(r + batch, max_rounds);
         for (; r < r_end; ++r) {
             R.r = (int)r;
-            hipError_t e;
-            if (!async && !edge) e = launch_vsync(R, algo, g_round, kBlock, s);
-            else if (!async) e = launch_esync(R, algo, g_round, kBlock, s);
-            else if (!edge) e = launch_vasync(R, algo, g_round, kBlock, s);
-            else e = launch_easync(R, algo, g_round, kBlock, s);
-            if (e == hipSuccess && need_heavy) e = launch_heavy(R, algo, g_heavy, kBlock, s);
-            if (e == hipSuccess && need_jump) e = launch_jump(R, g_jump, kBlock, s);
+            hipError_t e = launch(KIND_ROUND, [&] {
+                if (!async && !edge) return launch_vsync(R, algo, g_round, kBlock, s);
+                if (!async) return launch_esync(R, algo, g_round, kBlock, s);
+                if (!edge) return launch_vasync(R, algo, g_round, kBlock, s);
+                return launch_easync(R, algo, g_round, kBlock, s);
+            });
+            if (e == hipSuccess && need_heavy)
+                e = launch(KIND_HEAVY, [&] { return launch_heavy(R, algo, g_heavy, kBlock, s); });
+            if (e == hipSuccess && need_jump)
+                e = launch(KIND_AUX, [&] { return launch_jump(R, g_jump, kBlock, s); });
             HIPCHK(g, e);
         }
         const int slot = k & 1;
@@ -348,6 +387,7 @@ int run(gg_graph g, gg_ws ws, int algo, int source, const gg_opts* opts, int* ou
         batch = std::min(batch * 2, kMaxBatch);
     }
     HIPCHK(g, hipEventRecord(ws->finished, s));
+    ws->rounds = (int)r;
     ws->last_stream = s;
     ws->used = true;
     ws->last = gg_stats{};
@@ -623,9 +663,9 @@ int gg_last_stats(gg_graph g, gg_ws ws, gg_stats* out) {
     }
     HIPCHK(g, hipEventSynchronize(ws->finished));
     Ctl c;
-    std::vector<Stat> st(kMaxStatBlocks);
+    std::vector<Stat> st((size_t)kKinds * kMaxStatBlocks);
     HIPCHK(g, hipMemcpy(&c, ws->dev.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
-    HIPCHK(g, hipMemcpy(st.data(), ws->dev.stat, sizeof(Stat) * kMaxStatBlocks,
+    HIPCHK(g, hipMemcpy(st.data(), ws->dev.stat, sizeof(Stat) * st.size(),
                         hipMemcpyDeviceToHost));
     gg_stats s = ws->last;
     s.iterations = c.done ? c.iters : -1;
@@ -637,6 +677,36 @@ int gg_last_stats(gg_graph g, gg_ws ws, gg_stats* out) {
     }
     *out = s;
     return s.status;
+}
+
+int gg_last_profile(gg_graph g, gg_ws ws, gg_profile* out) {
+    if (!g || !out) return GG_EINVAL;
+    if (!ws) ws = g->ws0;
+    if (ws->owner != g) return GG_EINVAL;
+    *out = gg_profile{};
+    if (!ws->used || !ws->profiled) return GG_OK;
+    HIPCHK(g, hipEventSynchronize(ws->finished));
+    std::vector<Stat> st((size_t)kKinds * kMaxStatBlocks);
+    HIPCHK(g, hipMemcpy(st.data(), ws->dev.stat, sizeof(Stat) * st.size(),
+                        hipMemcpyDeviceToHost));
+    out->profiled = 1;
+    out->rounds = ws->rounds;
+    for (int i = 0; i < ws->nlaunch; ++i) {
+        float ms = 0.f;
+        HIPCHK(g, hipEventElapsedTime(&ms, ws->pev[2 * i], ws->pev[2 * i + 1]));
+        gg_kind_profile& k = out->kind[ws->pkind[i]];
+        k.launches++;
+        k.total_ms += ms;
+    }
+    for (int kind = 0; kind < kKinds; ++kind)
+        for (int b = 0; b < kMaxStatBlocks; ++b) {
+            const Stat& x = st[(size_t)kind * kMaxStatBlocks + b];
+            out->kind[kind].edges_processed += x.edges;
+            out->kind[kind].vertices_processed += x.verts;
+            out->kind[kind].updates += x.updates;
+            out->kind[kind].pushes += x.pushes;
+        }
+    return GG_OK;
 }
 
 int gg_resolve(gg_graph g, int32_t algo, const gg_opts* in, gg_opts* out) {

@@ -12,6 +12,8 @@ constexpr int kWave = 64;
 constexpr int kTile = 64;            // vertices per frontier tile (one wavefront)
 constexpr int kMaxStatBlocks = 4096; // per-block statistics slots
 constexpr int kDefaultHeavy = 512;   // rows longer than this are chunked (balanced mapping)
+constexpr int kKinds = 3;            // statistics kinds: round, heavy chunks, auxiliary
+enum Kind { KIND_ROUND = 0, KIND_HEAVY = 1, KIND_AUX = 2 };
 
 enum Algo { SSSP = 0, BFS = 1, CC = 2 };
 enum Map { MAP_THREAD = 1, MAP_WAVE = 2, MAP_BALANCED = 3 };
@@ -27,7 +29,8 @@ struct Ctl {
     int pad[8];
 };
 
-// Per-block counters, summed on the host after a traversal.
+// Per-block counters, summed on the host after a traversal; one array of
+// kMaxStatBlocks slots per kernel kind.
 struct Stat {
     long long edges, verts, updates, pushes;
 };

@@ -82,7 +82,7 @@ __device__ __forceinline__ bool round_begin(const Round& R) {
 
 // Block-level reduction of the lane counters; one plain update of this
 // block's statistics slot and, when anything changed, of the round's flag.
-__device__ void block_finish(const Round& R, const Acc& a, int slot) {
+__device__ void block_finish(const Round& R, const Acc& a, int slot, int kind) {
     __shared__ long long s_acc[4][4];
     int e = wave_sum(a.e), v = wave_sum(a.v), u = wave_sum(a.u), p = wave_sum(a.p);
     const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -102,7 +102,7 @@ __device__ void block_finish(const Round& R, const Acc& a, int slot) {
             P += s_acc[i][3];
         }
         if (E | V | U | P) {
-            Stat* st = R.ws.stat + blockIdx.x;
+            Stat* st = R.ws.stat + kind * kMaxStatBlocks + blockIdx.x;
             st->edges += E;
             st->verts += V;
             st->updates += U;
@@ -243,7 +243,7 @@ __global__ __launch_bounds__(256) void k_init(Round R, int algo, int async) {
             }
         }
     }
-    for (long long i = tid; i < kMaxStatBlocks; i += tt) R.ws.stat[i] = Stat{0, 0, 0, 0};
+    for (long long i = tid; i < kKinds * kMaxStatBlocks; i += tt) R.ws.stat[i] = Stat{0, 0, 0, 0};
     if (tid == 0) *R.ws.ctl = Ctl{};
 }
 
@@ -326,7 +326,7 @@ __global__ __launch_bounds__(256) void k_vsync(Round R) {
             }
         }
     }
-    block_finish(R, acc, R.r % 3);
+    block_finish(R, acc, R.r % 3, KIND_ROUND);
 }
 
 // One edge of the synchronous edge sweep (Algorithm 2; the edge form of
@@ -380,7 +380,7 @@ __global__ __launch_bounds__(256) void k_esync(Round R) {
         edge_sync_one<A>(R, s.w, c.w, (int)e + 3, acc);
     }
     for (long long e = m4 + tid; e < m; e += tt) edge_sync_one<A>(R, g.src[e], g.col[e], (int)e, acc);
-    block_finish(R, acc, R.r % 3);
+    block_finish(R, acc, R.r % 3, KIND_ROUND);
 }
 
 // Asynchronous vertex round: the frontier of round r is the set of flagged
@@ -465,7 +465,7 @@ __global__ __launch_bounds__(256) void k_vasync(Round R) {
             }
         }
     }
-    block_finish(R, acc, R.r % 3);
+    block_finish(R, acc, R.r % 3, KIND_ROUND);
 }
 
 // Asynchronous edge round: for every flagged tile the wavefront walks the
@@ -552,7 +552,7 @@ __global__ __launch_bounds__(256) void k_easync(Round R) {
             }
         }
     }
-    block_finish(R, acc, R.r % 3);
+    block_finish(R, acc, R.r % 3, KIND_ROUND);
 }
 
 // Heavy chunks queued by the light kernel of the same round.
@@ -585,7 +585,7 @@ __global__ __launch_bounds__(256) void k_heavy(Round R) {
             }
         }
     }
-    block_finish(R, acc, R.r % 3);
+    block_finish(R, acc, R.r % 3, KIND_HEAVY);
 }
 
 // CC shortcut pass used after an edge sweep: label[v] = label[label[v]].
@@ -603,7 +603,7 @@ __global__ __launch_bounds__(256) void k_jump(Round R) {
             if (y < old) acc.u++;
         }
     }
-    block_finish(R, acc, R.r % 3);
+    block_finish(R, acc, R.r % 3, KIND_AUX);
 }
 
 // ------------------------------------------------------- graph build ----

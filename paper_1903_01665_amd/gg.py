@@ -23,6 +23,8 @@ MAP_AUTO, MAP_THREAD, MAP_WAVE, MAP_BALANCED = 0, 1, 2, 3
 ALGO_SSSP, ALGO_BFS, ALGO_CC = 0, 1, 2
 SYMMETRIZE, INPUT_ON_DEVICE, SYMMETRIC = 1, 2, 4
 OPT_CC_NO_JUMP = 1
+OPT_PROFILE = 2
+KINDS = ("round", "heavy", "aux")
 
 STATUS = {0: "GG_OK", -1: "GG_EINVAL", -2: "GG_ENOMEM", -3: "GG_EHIP", -4: "GG_EBUSY",
           -5: "GG_ENOTSUP", -6: "GG_ETIMEOUT", -7: "GG_EITER"}
@@ -30,7 +32,8 @@ STATUS = {0: "GG_OK", -1: "GG_EINVAL", -2: "GG_ENOMEM", -3: "GG_EHIP", -4: "GG_E
 # every symbol include/gg.h declares
 EXPORTS = ["gg_graph_upload", "gg_graph_free", "gg_graph_info", "gg_graph_error", "gg_sssp",
            "gg_bfs", "gg_cc", "gg_ws_create", "gg_ws_free", "gg_sssp_ex", "gg_bfs_ex",
-           "gg_cc_ex", "gg_last_stats", "gg_resolve", "gg_status_str", "gg_version"]
+           "gg_cc_ex", "gg_last_stats", "gg_last_profile", "gg_resolve", "gg_status_str",
+           "gg_version"]
 
 
 class GGError(RuntimeError):
@@ -56,6 +59,22 @@ class Stats(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class KindProfile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int32), ("total_ms", ctypes.c_float),
+                ("edges_processed", ctypes.c_int64), ("vertices_processed", ctypes.c_int64),
+                ("updates", ctypes.c_int64), ("pushes", ctypes.c_int64)]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("profiled", ctypes.c_int32), ("rounds", ctypes.c_int32),
+                ("kind", KindProfile * 3)]
+
+    def as_dict(self):
+        return {"profiled": bool(self.profiled), "rounds": self.rounds,
+                **{KINDS[i]: {k: getattr(self.kind[i], k) for k, _ in KindProfile._fields_}
+                   for i in range(3)}}
 
 
 _lib = None
@@ -84,6 +103,7 @@ def lib():
     L.gg_bfs_ex.argtypes = [vp, vp, i32, P(Opts), vp, vp]
     L.gg_cc_ex.argtypes = [vp, vp, P(Opts), vp, vp]
     L.gg_last_stats.argtypes = [vp, vp, P(Stats)]
+    L.gg_last_profile.argtypes = [vp, vp, P(Profile)]
     L.gg_resolve.argtypes = [vp, i32, P(Opts), P(Opts)]
     L.gg_status_str.argtypes = [i32]
     L.gg_status_str.restype = ctypes.c_char_p
@@ -228,6 +248,12 @@ class Graph:
         d = s.as_dict()
         d["rc"] = rc
         return d
+
+    def profile(self, ws=None) -> dict:
+        p = Profile()
+        _check(lib().gg_last_profile(self.handle, ws.handle if ws is not None else None,
+                                     ctypes.byref(p)), "gg_last_profile")
+        return p.as_dict()
 
     def resolve(self, algo, opts=None) -> Opts:
         out = Opts()
