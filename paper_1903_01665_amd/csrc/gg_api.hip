@@ -73,7 +73,7 @@ struct gg_ws_s {
     gg_graph owner = nullptr;
     DevWs dev{};
     unsigned char* vflag_mem = nullptr;
-    int2* hq_mem = nullptr;
+    int epoch = 0;  // round stamps of the next traversal start here
     int* h_done = nullptr;  // pinned, 2 slots
     hipEvent_t ev[2] = {nullptr, nullptr};
     hipEvent_t finished = nullptr;
@@ -104,7 +104,7 @@ struct gg_graph_s {
     int2 *hchunks = nullptr, *shchunks = nullptr;
     int n_hchunks = 0, n_shchunks = 0;
     long long ms = 0;
-    int heavy = kDefaultHeavy, chunk = kDefaultHeavy;
+    int heavy = kDefaultHeavy, chunk = kChunk;
     gg_ws_s* ws0 = nullptr;
 };
 
@@ -145,7 +145,7 @@ int grid_for(long long items_per_block_unit, long long units) {
 void free_ws_arrays(gg_ws_s* ws) {
     if (!ws) return;
     if (ws->vflag_mem) hipFree(ws->vflag_mem);
-    if (ws->hq_mem) hipFree(ws->hq_mem);
+    if (ws->dev.hstamp) hipFree(ws->dev.hstamp);
     if (ws->dev.ctl) hipFree(ws->dev.ctl);
     if (ws->dev.stat) hipFree(ws->dev.stat);
     if (ws->h_done) hipHostFree(ws->h_done);
@@ -156,7 +156,7 @@ void free_ws_arrays(gg_ws_s* ws) {
     ws->pev.clear();
     if (ws->finished) hipEventDestroy(ws->finished);
     ws->vflag_mem = nullptr;
-    ws->hq_mem = nullptr;
+    ws->dev.hstamp = nullptr;
     ws->dev.ctl = nullptr;
     ws->dev.stat = nullptr;
     ws->h_done = nullptr;
@@ -170,10 +170,10 @@ int make_ws(gg_graph g, gg_ws_s** out) {
     // vertex flags padded to whole 64-tile groups so no index needs a bound
     const long long vbytes = ((ntiles + 63) / 64) * 64 * 64;
     const long long tbytes = ((ntiles + 63) / 64) * 64;
-    const long long cap = std::max(g->n_hchunks, g->n_shchunks);
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = dalloc(&ws->vflag_mem, (size_t)(2 * (vbytes + tbytes)));
-    if (e == hipSuccess) e = dalloc(&ws->hq_mem, (size_t)(2 * std::max(cap, 1LL)));
+    if (e == hipSuccess) e = dalloc(&ws->dev.hstamp, (size_t)g->n);
+    if (e == hipSuccess) e = hipMemset(ws->dev.hstamp, 0xff, sizeof(int) * (size_t)g->n);
     if (e == hipSuccess) e = dalloc(&ws->dev.ctl, 1);
     if (e == hipSuccess) e = dalloc(&ws->dev.stat, (size_t)kKinds * kMaxStatBlocks);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&ws->h_done), 4 * sizeof(int));
@@ -191,9 +191,6 @@ int make_ws(gg_graph g, gg_ws_s** out) {
     ws->dev.vflag[1] = ws->vflag_mem + vbytes;
     ws->dev.tflag[0] = ws->vflag_mem + 2 * vbytes;
     ws->dev.tflag[1] = ws->vflag_mem + 2 * vbytes + tbytes;
-    ws->dev.hq[0] = ws->hq_mem;
-    ws->dev.hq[1] = ws->hq_mem + std::max(cap, 1LL);
-    ws->dev.hq_cap = (int)cap;
     std::memset(ws->h_done, 0, 4 * sizeof(int));
     *out = ws;
     return GG_OK;
@@ -306,7 +303,7 @@ int run(gg_graph g, gg_ws ws, int algo, int source, const gg_opts* opts, int* ou
         g_round = grid((ngroups * 8 + wpb - 1) / wpb);
     }
     const bool need_heavy = async && (edge || o.mapping == GG_MAP_BALANCED) && nh > 0;
-    const int g_heavy = grid((std::max(g->n_hchunks, g->n_shchunks) + wpb - 1) / wpb);
+    const int g_heavy = grid((nh + wpb - 1) / wpb);
     const bool need_jump = cc && edge && !async && R.jump;
     const int g_jump = grid((n + kBlock - 1) / kBlock);
 
@@ -337,6 +334,15 @@ int run(gg_graph g, gg_ws ws, int algo, int source, const gg_opts* opts, int* ou
         return e;
     };
 
+    // round stamps of heavy frontier rows must not repeat across traversals
+    // of this workspace; restart them (and clear the stamps) long before the
+    // 32-bit range ends
+    if (ws->epoch > (1 << 30)) {
+        HIPCHK(g, hipMemsetAsync(ws->dev.hstamp, 0xff, sizeof(int) * (size_t)g->n, s));
+        ws->epoch = 0;
+    }
+    const int epoch = ws->epoch;
+    R.stamp = epoch;
     HIPCHK(g, launch(KIND_AUX, [&] { return launch_init(R, algo, async, g_init, kBlock, s); }));
 
     // bound on rounds: every productive round fixes at least one more vertex
@@ -350,6 +356,7 @@ int run(gg_graph g, gg_ws ws, int algo, int source, const gg_opts* opts, int* ou
         const long long r_end = std::min(r + batch, max_rounds);
         for (; r < r_end; ++r) {
             R.r = (int)r;
+            R.stamp = epoch + (int)r;
             hipError_t e = launch(KIND_ROUND, [&] {
                 if (!async && !edge) return launch_vsync(R, algo, g_round, kBlock, s);
                 if (!async) return launch_esync(R, algo, g_round, kBlock, s);
@@ -387,6 +394,7 @@ int run(gg_graph g, gg_ws ws, int algo, int source, const gg_opts* opts, int* ou
         batch = std::min(batch * 2, kMaxBatch);
     }
     HIPCHK(g, hipEventRecord(ws->finished, s));
+    ws->epoch = epoch + (int)r + 1;
     ws->rounds = (int)r;
     ws->last_stream = s;
     ws->used = true;

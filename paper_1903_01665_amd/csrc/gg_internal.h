@@ -11,7 +11,8 @@ constexpr int kInf = 2147483647;
 constexpr int kWave = 64;
 constexpr int kTile = 64;            // vertices per frontier tile (one wavefront)
 constexpr int kMaxStatBlocks = 4096; // per-block statistics slots
-constexpr int kDefaultHeavy = 512;   // rows longer than this are chunked (balanced mapping)
+constexpr int kDefaultHeavy = 64;    // rows longer than this are chunked (balanced mapping)
+constexpr int kChunk = 256;          // edges per heavy-row chunk
 constexpr int kKinds = 3;            // statistics kinds: round, heavy chunks, auxiliary
 enum Kind { KIND_ROUND = 0, KIND_HEAVY = 1, KIND_AUX = 2 };
 
@@ -25,8 +26,7 @@ struct Ctl {
     int done;        // set by the first round kernel that finds nothing left to do
     int iters;       // rounds that ran, set together with done
     int changed[4];  // [r % 3]: round r updated or pushed something
-    int hq_count[2]; // heavy-chunk queue fill, by round parity
-    int pad[8];
+    int pad[10];
 };
 
 // Per-block counters, summed on the host after a traversal; one array of
@@ -58,12 +58,12 @@ struct DevGraph {
 };
 
 // Device view of a workspace: frontier flags (one byte per vertex, one per
-// 64-vertex tile), two generations; heavy-chunk queues; control; stats.
+// 64-vertex tile), two generations; the round stamp of heavy frontier rows;
+// control; stats.
 struct DevWs {
     unsigned char* vflag[2];
     unsigned char* tflag[2];
-    int2* hq[2];
-    int hq_cap;
+    int* hstamp;  // [n]: stamp of the last round that had the row on its frontier
     Ctl* ctl;
     Stat* stat;
 };
@@ -75,6 +75,7 @@ struct Round {
     int* val;    // dist or label, [n]
     int source;
     int r;       // round (sweep, level) index
+    int stamp;   // r + a per-workspace epoch that grows across traversals
     int mapping; // Map
     int jump;    // CC: apply the label[label[v]] shortcut
 };

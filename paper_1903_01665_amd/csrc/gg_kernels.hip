@@ -32,9 +32,12 @@
 
 namespace gg {
 
-// A frontier work item is one eighth of a 64-tile group: the wavefront loads
-// the 64 tile flags of the group at once and serves the 8 tiles of its part.
-constexpr int kParts = 8;
+// A frontier work item is one 32nd of a 64-tile group: the wavefront loads
+// the 64 tile flags of the group at once and serves the 2 tiles of its part.
+constexpr int kParts = 32;
+
+// Edges each lane keeps in flight in the relaxation loops.
+constexpr int kBatch = 4;
 
 // ------------------------------------------------------------ helpers ----
 
@@ -75,7 +78,6 @@ __device__ __forceinline__ bool round_begin(const Round& R) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         // slots of round r+1: last read by rounds that have completed
         ctl->changed[(R.r + 1) % 3] = 0;
-        ctl->hq_count[(R.r + 1) & 1] = 0;
     }
     return true;
 }
@@ -173,6 +175,103 @@ __device__ __forceinline__ bool relax_edge(const Round& R, const int* col, int e
     }
 }
 
+// Relax U edges per lane with the loads of all of them in flight before the
+// first compare: column indices (and weights), then head values, then the
+// atomics.  Reading every head value before any atomic of the batch is safe
+// because values only decrease.  ok[j] masks the lanes that own an edge.
+template <int A, int U, bool PUSH>
+__device__ __forceinline__ void relax_batch(const Round& R, const int* col, const int (&e)[U],
+                                            const int (&sv)[U], const bool (&ok)[U], int nxt,
+                                            Acc& acc) {
+    int* val = R.val;
+    int t[U], wt[U], cur[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) t[j] = ok[j] ? col[e[j]] : 0;
+    if (A == SSSP) {
+#pragma unroll
+        for (int j = 0; j < U; ++j) wt[j] = ok[j] ? R.g.w[e[j]] : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) cur[j] = ok[j] ? val[t[j]] : 0;
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+        if (!ok[j]) continue;
+        acc.e++;
+        bool hit = false;
+        if (A == SSSP) {
+            const unsigned cand = (unsigned)sv[j] + (unsigned)wt[j];
+            if (cand < (unsigned)cur[j]) hit = (int)cand < atomicMin(&val[t[j]], (int)cand);
+        } else if (A == BFS) {
+            const int nl = sv[j] + 1;
+            if (cur[j] > nl) {
+                val[t[j]] = nl;
+                hit = true;
+            }
+        } else {
+            if (sv[j] < cur[j]) hit = sv[j] < atomicMin(&val[t[j]], sv[j]);
+        }
+        if (hit) {
+            if (PUSH) {
+                R.ws.vflag[nxt][t[j]] = 1;
+                R.ws.tflag[nxt][t[j] >> 6] = 1;
+                acc.p++;
+            } else {
+                acc.u++;
+            }
+        }
+    }
+}
+
+// The edges [e0, e1) of one row, all with tail value sv, relaxed by the
+// whole wavefront kBatch x 64 edges per step.
+template <int A, bool PUSH>
+__device__ __forceinline__ void wave_relax_range(const Round& R, const int* col, int e0, int e1,
+                                                 int sv, int nxt, Acc& acc) {
+    const int lane = threadIdx.x & 63;
+    for (int eb = e0; eb < e1; eb += 64 * kBatch) {
+        int e[kBatch], s[kBatch];
+        bool ok[kBatch];
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+            e[j] = eb + j * 64 + lane;
+            ok[j] = e[j] < e1;
+            s[j] = sv;
+        }
+        relax_batch<A, kBatch, PUSH>(R, col, e, s, ok, nxt, acc);
+    }
+}
+
+// Lanes hold one row each, [beg, beg + deg), with tail value sv.  The
+// wavefront walks the concatenation of the 64 rows kBatch x 64 edges per
+// step; edge k of a step belongs to the row found by a six-step search over
+// the exclusive prefix of the degrees.
+template <int A, bool PUSH>
+__device__ __forceinline__ void wave_relax_rows(const Round& R, const int* col, int beg, int deg,
+                                                int sv, int nxt, Acc& acc) {
+    const int lane = threadIdx.x & 63;
+    const int incl = wave_incl_scan(deg);
+    const int total = __shfl(incl, 63, 64);
+    const int excl = incl - deg;
+    for (int base = 0; base < total; base += 64 * kBatch) {
+        int e[kBatch], s[kBatch];
+        bool ok[kBatch];
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+            const int k = base + j * 64 + lane;
+            int o = 0;
+#pragma unroll
+            for (int step = 32; step > 0; step >>= 1) {
+                const int cand = o + step;
+                if (__shfl(excl, cand, 64) <= k) o = cand;
+            }
+            e[j] = __shfl(beg, o, 64) + (k - __shfl(excl, o, 64));
+            s[j] = __shfl(sv, o, 64);
+            ok[j] = k < total;
+        }
+        relax_batch<A, kBatch, PUSH>(R, col, e, s, ok, nxt, acc);
+    }
+}
+
 // Value and activity of vertex u as the tail of its edges.
 //  sync:  SSSP every reached vertex; BFS the vertices of level r; CC all.
 //  async: u is on the frontier; SSSP/CC read its current value, BFS uses r.
@@ -205,23 +304,6 @@ __device__ __forceinline__ bool tail_value(const Round& R, int u, int& sv, Acc& 
 __device__ __forceinline__ void push(const Round& R, int nxt, int t) {
     R.ws.vflag[nxt][t] = 1;
     R.ws.tflag[nxt][t >> 6] = 1;
-}
-
-// Append the heavy rows held by lanes with hv set to the round's chunk
-// queue: one atomic per wavefront reserves room for all their chunks.
-__device__ __forceinline__ void heavy_append(const Round& R, int cur, bool hv, int u, int rb,
-                                             int re) {
-    const int chunk = R.g.chunk;
-    const int nch = hv ? (re - rb + chunk - 1) / chunk : 0;
-    const int incl = wave_incl_scan(nch);
-    const int total = __shfl(incl, 63, 64);
-    if (total == 0) return;
-    int base = 0;
-    if ((threadIdx.x & 63) == 0) base = atomicAdd(&R.ws.ctl->hq_count[cur], total);
-    base = __shfl(base, 0, 64);
-    int pos = base + incl - nch;
-    int2* q = R.ws.hq[cur];
-    for (int j = 0; j < nch; ++j) q[pos + j] = make_int2(u, rb + j * chunk);
 }
 
 // ------------------------------------------------------------ kernels ----
@@ -273,11 +355,7 @@ __global__ __launch_bounds__(256) void k_vsync(Round R) {
                 int sv;
                 if (tail_value<A, false>(R, u, sv, acc)) {
                     if (lane == 0) acc.v++;
-                    for (int e = hc.y + lane; e < e1; e += 64) {
-                        int t;
-                        acc.e++;
-                        if (relax_edge<A>(R, col, e, sv, t)) acc.u++;
-                    }
+                    wave_relax_range<A, false>(R, col, hc.y, e1, sv, 0, acc);
                 }
             } else {
                 const int u = (int)((it - nh) * 64 + lane);
@@ -290,11 +368,7 @@ __global__ __launch_bounds__(256) void k_vsync(Round R) {
                         acc.v++;
                     }
                 }
-                wave_rows_balanced(beg, deg, sv, [&](int e, int s) {
-                    int t;
-                    acc.e++;
-                    if (relax_edge<A>(R, col, e, s, t)) acc.u++;
-                });
+                wave_relax_rows<A, false>(R, col, beg, deg, sv, 0, acc);
             }
         }
     } else if (MAP == MAP_THREAD) {
@@ -371,13 +445,50 @@ __global__ __launch_bounds__(256) void k_esync(Round R) {
     const long long tt = (long long)gridDim.x * blockDim.x;
     const int m4 = m & ~3;
     Acc acc;
+    int* val = R.val;
     for (long long e = tid * 4; e < m4; e += tt * 4) {
-        const int4 s = *reinterpret_cast<const int4*>(g.src + e);
-        const int4 c = *reinterpret_cast<const int4*>(g.col + e);
-        edge_sync_one<A>(R, s.x, c.x, (int)e, acc);
-        edge_sync_one<A>(R, s.y, c.y, (int)e + 1, acc);
-        edge_sync_one<A>(R, s.z, c.z, (int)e + 2, acc);
-        edge_sync_one<A>(R, s.w, c.w, (int)e + 3, acc);
+        const int4 s4 = *reinterpret_cast<const int4*>(g.src + e);
+        const int4 c4 = *reinterpret_cast<const int4*>(g.col + e);
+        const int u[4] = {s4.x, s4.y, s4.z, s4.w};
+        const int t[4] = {c4.x, c4.y, c4.z, c4.w};
+        int wt[4] = {0, 0, 0, 0};
+        if (A == SSSP) {
+            const int4 w4 = *reinterpret_cast<const int4*>(g.w + e);
+            wt[0] = w4.x;
+            wt[1] = w4.y;
+            wt[2] = w4.z;
+            wt[3] = w4.w;
+        }
+        // every value of the four edges is loaded before the first atomic;
+        // a head value is loaded only when the tail can relax the edge
+        int vu[4], vt[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) vu[j] = val[u[j]];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const bool need = A == SSSP ? vu[j] != kInf : A == BFS ? vu[j] == R.r : true;
+            vt[j] = need ? val[t[j]] : 0;
+        }
+        acc.e += 4;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (A == SSSP) {
+                if (vu[j] == kInf) continue;
+                const unsigned cand = (unsigned)vu[j] + (unsigned)wt[j];
+                if (cand < (unsigned)vt[j] && (int)cand < atomicMin(&val[t[j]], (int)cand)) acc.u++;
+            } else if (A == BFS) {
+                if (vu[j] == R.r && vt[j] > R.r + 1) {
+                    val[t[j]] = R.r + 1;
+                    acc.u++;
+                }
+            } else {
+                if (vu[j] < vt[j]) {
+                    if (vu[j] < atomicMin(&val[t[j]], vu[j])) acc.u++;
+                } else if (vt[j] < vu[j] && !g.symmetric) {
+                    if (vt[j] < atomicMin(&val[u[j]], vt[j])) acc.u++;
+                }
+            }
+        }
     }
     for (long long e = m4 + tid; e < m; e += tt) edge_sync_one<A>(R, g.src[e], g.col[e], (int)e, acc);
     block_finish(R, acc, R.r % 3, KIND_ROUND);
@@ -425,17 +536,11 @@ __global__ __launch_bounds__(256) void k_vasync(Round R) {
                 acc.v++;
             }
             if (MAP == MAP_BALANCED) {
+                // heavy rows are served by the chunk kernel of this round
                 const bool hv = on && re - rb > g.heavy;
-                heavy_append(R, cur, hv, u, rb, re);
-                wave_rows_balanced(on && !hv ? rb : 0, on && !hv ? re - rb : 0, sv,
-                                   [&](int e, int s) {
-                                       int t2;
-                                       acc.e++;
-                                       if (relax_edge<A>(R, col, e, s, t2)) {
-                                           push(R, nxt, t2);
-                                           acc.p++;
-                                       }
-                                   });
+                if (hv) R.ws.hstamp[u] = R.stamp;
+                wave_relax_rows<A, true>(R, col, on && !hv ? rb : 0, on && !hv ? re - rb : 0, sv,
+                                         nxt, acc);
             } else if (MAP == MAP_THREAD) {
                 if (on)
                     for (int e = rb; e < re; ++e) {
@@ -516,7 +621,8 @@ __global__ __launch_bounds__(256) void k_easync(Round R) {
                 acc.v++;
             }
             const bool light = in && re - rb <= g.heavy;
-            heavy_append(R, cur, on && !light, u, rb, re);
+            // heavy rows are served by the chunk kernel of this round
+            if (on && !light) R.ws.hstamp[u] = R.stamp;
             const unsigned long long am = __ballot(on && light);
             if (am == 0) continue;
             // walk maximal runs of light rows that contain a flagged row
@@ -530,24 +636,21 @@ __global__ __launch_bounds__(256) void k_easync(Round R) {
                 if ((am & run) == 0) continue;
                 const int e0 = __shfl(rb, a, 64);
                 const int e1 = __shfl(re, a + len - 1, 64);
-                for (int eb = e0; eb < e1; eb += 64) {
-                    const int e = eb + lane;
-                    int bit = 0;
-                    bool act = false;
-                    if (e < e1) {
-                        bit = src[e] - base_v;
-                        act = (am >> bit) & 1;
+                for (int eb = e0; eb < e1; eb += 64 * kBatch) {
+                    int e[kBatch], bit[kBatch], os[kBatch];
+                    bool act[kBatch];
+#pragma unroll
+                    for (int j = 0; j < kBatch; ++j) {
+                        e[j] = eb + j * 64 + lane;
+                        bit[j] = e[j] < e1 ? src[e[j]] - base_v : 0;
                     }
-                    // the tail's value is held by the lane of that vertex
-                    const int os = __shfl(sv, bit, 64);
-                    if (act) {
-                        int t2;
-                        acc.e++;
-                        if (relax_edge<A>(R, col, e, os, t2)) {
-                            push(R, nxt, t2);
-                            acc.p++;
-                        }
+#pragma unroll
+                    for (int j = 0; j < kBatch; ++j) {
+                        act[j] = e[j] < e1 && ((am >> bit[j]) & 1);
+                        // the tail's value is held by the lane of that vertex
+                        os[j] = __shfl(sv, bit[j], 64);
                     }
+                    relax_batch<A, kBatch, true>(R, col, e, os, act, nxt, acc);
                 }
             }
         }
@@ -555,7 +658,9 @@ __global__ __launch_bounds__(256) void k_easync(Round R) {
     block_finish(R, acc, R.r % 3, KIND_ROUND);
 }
 
-// Heavy chunks queued by the light kernel of the same round.
+// Heavy rows of the frontier: the light kernel of the same round stamped
+// them; every wavefront walks the static chunk list and serves the chunks
+// whose row carries this round's stamp.
 template <int A>
 __global__ __launch_bounds__(256) void k_heavy(Round R) {
     Ctl* ctl = R.ws.ctl;
@@ -563,27 +668,20 @@ __global__ __launch_bounds__(256) void k_heavy(Round R) {
     const DevGraph& g = R.g;
     const int* row = A == CC ? g.srow : g.row;
     const int* col = A == CC ? g.scol : g.col;
-    const int cur = R.r & 1, nxt = cur ^ 1;
-    const int cnt = *(volatile int*)&ctl->hq_count[cur];
-    const int2* q = R.ws.hq[cur];
-    const int lane = threadIdx.x & 63;
+    const int2* chunks = A == CC ? g.shchunks : g.hchunks;
+    const long long nch = A == CC ? g.n_shchunks : g.n_hchunks;
+    const int nxt = (R.r & 1) ^ 1;
     const int wpb = blockDim.x >> 6;
     const long long gw = (long long)blockIdx.x * wpb + (threadIdx.x >> 6);
     const long long tw = (long long)gridDim.x * wpb;
     Acc acc;
-    for (long long it = gw; it < cnt; it += tw) {
-        const int2 c = q[it];
+    for (long long it = gw; it < nch; it += tw) {
+        const int2 c = chunks[it];
         const int u = c.x;
+        if (R.ws.hstamp[u] != R.stamp) continue;
         const int e1 = min(c.y + g.chunk, row[u + 1]);
-        int sv = A == BFS ? R.r : R.val[u];
-        for (int e = c.y + lane; e < e1; e += 64) {
-            int t2;
-            acc.e++;
-            if (relax_edge<A>(R, col, e, sv, t2)) {
-                push(R, nxt, t2);
-                acc.p++;
-            }
-        }
+        const int sv = A == BFS ? R.r : R.val[u];
+        wave_relax_range<A, true>(R, col, c.y, e1, sv, nxt, acc);
     }
     block_finish(R, acc, R.r % 3, KIND_HEAVY);
 }
@@ -647,10 +745,25 @@ __global__ __launch_bounds__(256) void k_sym_fill(const int* row, const int* col
 
 // ----------------------------------------------------- launch wrappers ----
 
-#define GG_LAUNCH(kernel, grid, block, s, ...)                                   \
-    do {                                                                         \
-        hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), 0, s, __VA_ARGS__);  \
-        return hipGetLastError();                                                \
+// Blocks of `block` threads of kernel f that fit on the device at once.  A
+// grid-stride kernel launched with more blocks than this would run its last
+// blocks in a second wave, so every launch is clamped to it.
+static int resident_cap(const void* f, int block) {
+    int occ = 0, dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1 << 30;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 1 << 30;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, block, 0) != hipSuccess || occ < 1)
+        return 1 << 30;
+    return occ * cus;
+}
+
+#define GG_LAUNCH(kernel, grid, block, s, ...)                                       \
+    do {                                                                             \
+        static const int cap_ = resident_cap(reinterpret_cast<const void*>(kernel), (block)); \
+        const int g_ = (grid) < cap_ ? (grid) : cap_;                                \
+        hipLaunchKernelGGL(kernel, dim3(g_), dim3(block), 0, s, __VA_ARGS__);        \
+        return hipGetLastError();                                                    \
     } while (0)
 
 hipError_t launch_init(const Round& R, int algo, bool async, int grid, int block, hipStream_t s) {
