@@ -29,7 +29,7 @@ namespace {
 
 constexpr int kVersion = 1;
 constexpr int kBlock = 256;
-constexpr int kMaxBatch = 64;
+constexpr int kMaxBatch = 16;
 constexpr int kDefaultTimeLimitMs = 60000;
 
 struct Dev {
@@ -74,7 +74,7 @@ struct gg_ws_s {
     DevWs dev{};
     unsigned char* vflag_mem = nullptr;
     int epoch = 0;  // round stamps of the next traversal start here
-    int* h_done = nullptr;  // pinned, 2 slots
+    int* h_done = nullptr;  // pinned word written by the kernel that finds the end
     hipEvent_t ev[2] = {nullptr, nullptr};
     hipEvent_t finished = nullptr;
     hipStream_t last_stream = nullptr;
@@ -191,7 +191,7 @@ int make_ws(gg_graph g, gg_ws_s** out) {
     ws->dev.vflag[1] = ws->vflag_mem + vbytes;
     ws->dev.tflag[0] = ws->vflag_mem + 2 * vbytes;
     ws->dev.tflag[1] = ws->vflag_mem + 2 * vbytes + tbytes;
-    std::memset(ws->h_done, 0, 4 * sizeof(int));
+    ws->h_done[0] = -1;
     *out = ws;
     return GG_OK;
 }
@@ -303,7 +303,7 @@ int run(gg_graph g, gg_ws ws, int algo, int source, const gg_opts* opts, int* ou
         g_round = grid((ngroups * 8 + wpb - 1) / wpb);
     }
     const bool need_heavy = async && (edge || o.mapping == GG_MAP_BALANCED) && nh > 0;
-    const int g_heavy = grid((nh + wpb - 1) / wpb);
+    const int g_heavy = grid((nh + 64LL * wpb - 1) / (64LL * wpb));
     const bool need_jump = cc && edge && !async && R.jump;
     const int g_jump = grid((n + kBlock - 1) / kBlock);
 
@@ -343,6 +343,8 @@ int run(gg_graph g, gg_ws ws, int algo, int source, const gg_opts* opts, int* ou
     }
     const int epoch = ws->epoch;
     R.stamp = epoch;
+    R.epoch = epoch;
+    R.host_done = ws->h_done;
     HIPCHK(g, launch(KIND_AUX, [&] { return launch_init(R, algo, async, g_init, kBlock, s); }));
 
     // bound on rounds: every productive round fixes at least one more vertex
@@ -370,25 +372,26 @@ int run(gg_graph g, gg_ws ws, int algo, int source, const gg_opts* opts, int* ou
             HIPCHK(g, e);
         }
         const int slot = k & 1;
-        HIPCHK(g, hipMemcpyAsync(ws->h_done + slot, &ws->dev.ctl->done, sizeof(int),
-                                 hipMemcpyDeviceToHost, s));
         HIPCHK(g, hipEventRecord(ws->ev[slot], s));
+        auto finished = [&] { return __atomic_load_n(ws->h_done, __ATOMIC_ACQUIRE) == epoch; };
         if (pending) {
+            // the previous batch has run once its event completes; the end may
+            // have been reported by a kernel of it (or of the current batch)
             HIPCHK(g, hipEventSynchronize(ws->ev[slot ^ 1]));
-            if (ws->h_done[slot ^ 1]) break;
+            if (finished()) break;
         }
         pending = true;
         ++k;
         if (r >= max_rounds) {
             HIPCHK(g, hipEventSynchronize(ws->ev[slot]));
-            if (!ws->h_done[slot]) status = GG_EITER;
+            if (!finished()) status = GG_EITER;
             break;
         }
         const long long ms = std::chrono::duration_cast<std::chrono::milliseconds>(
                                  std::chrono::steady_clock::now() - t0).count();
         if (ms > o.time_limit_ms) {
             HIPCHK(g, hipEventSynchronize(ws->ev[slot]));
-            if (!ws->h_done[slot]) status = GG_ETIMEOUT;
+            if (!finished()) status = GG_ETIMEOUT;
             break;
         }
         batch = std::min(batch * 2, kMaxBatch);

@@ -76,6 +76,8 @@ struct Round {
     int source;
     int r;       // round (sweep, level) index
     int stamp;   // r + a per-workspace epoch that grows across traversals
+    int epoch;   // stamp of round 0 of this traversal
+    int* host_done; // pinned host word: set to `epoch` by the kernel that finds the end
     int mapping; // Map
     int jump;    // CC: apply the label[label[v]] shortcut
 };

@@ -65,6 +65,9 @@ struct Acc {
 // Round entry, uniform over the whole grid.  Returns false when the
 // traversal has finished: either an earlier round set `done`, or round r-1
 // changed nothing, in which case this kernel records the round count.
+// The kernel that finds the end also tells the host, by storing this
+// traversal's epoch into a pinned host word (older traversals store older
+// epochs, so a late kernel of an earlier traversal cannot end this one).
 __device__ __forceinline__ bool round_begin(const Round& R) {
     Ctl* ctl = R.ws.ctl;
     if (*(volatile int*)&ctl->done) return false;
@@ -72,6 +75,7 @@ __device__ __forceinline__ bool round_begin(const Round& R) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             ctl->iters = R.r;
             ctl->done = 1;
+            __hip_atomic_store(R.host_done, R.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         }
         return false;
     }
@@ -674,14 +678,30 @@ __global__ __launch_bounds__(256) void k_heavy(Round R) {
     const int wpb = blockDim.x >> 6;
     const long long gw = (long long)blockIdx.x * wpb + (threadIdx.x >> 6);
     const long long tw = (long long)gridDim.x * wpb;
+    const int lane = threadIdx.x & 63;
     Acc acc;
-    for (long long it = gw; it < nch; it += tw) {
-        const int2 c = chunks[it];
-        const int u = c.x;
-        if (R.ws.hstamp[u] != R.stamp) continue;
-        const int e1 = min(c.y + g.chunk, row[u + 1]);
-        const int sv = A == BFS ? R.r : R.val[u];
-        wave_relax_range<A, true>(R, col, c.y, e1, sv, nxt, acc);
+    // 64 chunk stamps are checked at once, then the wavefront serves the
+    // chunks that match in turn.  The 64 chunks of one check are spread over
+    // the list with the stride of the whole grid, so that the chunks of one
+    // long row (which sit next to each other) land on different wavefronts.
+    for (long long k0 = 0; gw + k0 * tw < nch; k0 += 64) {
+        const long long it = gw + (k0 + lane) * tw;
+        int2 c = make_int2(0, 0);
+        bool on = false;
+        if (it < nch) {
+            c = chunks[it];
+            on = R.ws.hstamp[c.x] == R.stamp;
+        }
+        unsigned long long am = __ballot(on);
+        while (am) {
+            const int o = __ffsll(am) - 1;
+            am &= am - 1;
+            const int u = __shfl(c.x, o, 64);
+            const int e0 = __shfl(c.y, o, 64);
+            const int e1 = min(e0 + g.chunk, row[u + 1]);
+            const int sv = A == BFS ? R.r : R.val[u];
+            wave_relax_range<A, true>(R, col, e0, e1, sv, nxt, acc);
+        }
     }
     block_finish(R, acc, R.r % 3, KIND_HEAVY);
 }
