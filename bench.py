@@ -74,6 +74,32 @@ def algorithmic_bytes(algo, mode, sched, kind, n, prof_kind, launches):
     return (4 + (2 if sched == 1 else 0)) * n + 8 * n * max(0, launches - 1)
 
 
+def kernel_symbol(algo, kind, mode, sched, mapping):
+    """HIP symbol of the kernel that runs (algo, kind) in a variant."""
+    a = {"sssp": 0, "bfs": 1, "cc": 2}[algo]
+    if kind == "heavy":
+        return f"void gg::k_heavy<{a}>(gg::Round)"
+    if kind == "aux":
+        return "gg::k_init(gg::Round, int, int)"
+    if mode == 1:
+        return f"void gg::k_{'esync' if sched == 0 else 'easync'}<{a}>(gg::Round)"
+    return f"void gg::k_{'vsync' if sched == 0 else 'vasync'}<{a}, {mapping}>(gg::Round)"
+
+
+def measured_traffic(symbol, workload):
+    """HBM bytes per dispatch from the committed counter summary, or None when
+    the summary is for another workload or the kernels changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.json")
+    src = os.path.join(ROOT, "paper_1903_01665_amd", "csrc", "gg_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    t = json.load(open(path))
+    if t.get("kernels_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    return t["bytes_per_dispatch"].get(symbol)
+
+
 def traversed_edges(deg, dist):
     return int(deg[dist < INF].sum())
 
@@ -87,6 +113,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true", help="skip the per-variant table")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--reps", type=int, default=3, help="repeats per variant in the table")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported",
@@ -101,6 +129,18 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     gg.lib()
+
+    if args.calib_copy_mib:
+        # a plain copy of known size: reading its FETCH_SIZE / WRITE_SIZE
+        # counters scales the counters of the traversal kernels
+        nbytes = args.calib_copy_mib << 20
+        a = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {args.calib_copy_mib} MiB done (3 dispatches)")
+        del a, b
 
     t = time.time()
     hg = gen.workload(args.workload)
@@ -174,9 +214,13 @@ def main():
     c = chosen[da]
     mname = ["vertex", "edge"][c.mode] + "-" + ["sync", "async"][c.sched]
     achieved = db / (dms * 1e-3) / 1e9
+    sym = kernel_symbol(da, dk, c.mode, c.sched, c.mapping)
+    traffic = measured_traffic(sym, args.workload)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": f"{da} {mname} {dk} kernel", "launches": dl,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else int(traffic),
+                "traffic_unit": "bytes/launch",
+                "kernel": f"{da} {mname} {dk} kernel", "symbol": sym, "launches": dl,
                 "avg_launch_us": round(dms * 1e3 / dl, 2),
                 "algorithmic_bytes_per_launch": int(db / dl)}
     kernel_table = {f"{a}/{k}": {"launches": L, "ms": round(ms, 3),
