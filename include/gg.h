@@ -201,6 +201,108 @@ int gg_last_profile(gg_graph g, gg_ws ws, gg_profile* out);
  * would (the autotuner's table, else built-in rules). */
 int gg_resolve(gg_graph g, int32_t algo, const gg_opts* in, gg_opts* out);
 
+/* ---- Autotuning: the adaptive choice of variant (the paper picks vertex-
+ * or edge-based, synchronous or asynchronous processing per input, Sec. 1
+ * and Sec. 4.3; here the choice is measured, not fixed at compile time).
+ *
+ * A graph falls in a class:
+ *   size_class  = floor(log2(max(m, 1)) / 2)
+ *   skew_class  = 0 if max_out_degree < 8 x average degree, 1 if < 128 x, else 2
+ *   depth_class = 0 if a BFS from the highest-degree vertex has < 16 levels,
+ *                 1 if < 256, else 2; -1 until gg_graph_probe measured it.
+ * A tuning table maps (algo, class) to a variant.  AUTO fields resolve to the
+ * entry of the same algorithm with the smallest distance
+ *   |size difference| + 4 x [skew differs] + 4 x [depth differs, both known],
+ * or to built-in rules when the table has no entry for the algorithm. */
+typedef struct {
+    int32_t algo, size_class, skew_class, depth_class; /* depth -1 = any */
+    int32_t mode, sched, mapping;
+    int32_t reserved;
+} gg_tune_entry;
+
+/* Replace the process-wide tuning table (count 0 clears it).  The entries
+ * are copied.  GG_EINVAL for a NULL table with count > 0, a negative count or
+ * an entry with an out-of-range field. */
+int gg_tune_set(const gg_tune_entry* entries, int32_t count);
+
+/* Number of entries in the table; copies up to `cap` of them to `out`. */
+int gg_tune_get(gg_tune_entry* out, int32_t cap);
+
+/* Class of a graph of these sizes (pure host computation; levels < 0 =
+ * unknown depth). */
+int gg_class_of(int64_t m, int32_t n, int32_t max_out_degree, int32_t levels,
+                int32_t* size_class, int32_t* skew_class, int32_t* depth_class);
+
+/* Variant the table (else the built-in rules) picks for an algorithm and a
+ * class, as gg_resolve would.  Outputs may not be NULL. */
+int gg_tune_lookup(int32_t algo, int32_t size_class, int32_t skew_class, int32_t depth_class,
+                   int32_t* mode, int32_t* sched, int32_t* mapping);
+
+/* Measure the graph's depth class (one BFS on `stream`, waited for) and keep
+ * it on the handle; later AUTO resolutions use it. */
+int gg_graph_probe(gg_graph g, void* stream);
+
+/* Class of an uploaded graph (depth -1 until probed). */
+int gg_graph_class(gg_graph g, int32_t* size_class, int32_t* skew_class, int32_t* depth_class);
+
+/* ---- Batched traversals: many independent SSSP/BFS instances of uneven
+ * size in one launch sequence.  The paper observed that one traversal kernel
+ * already used all GPU resources on its hardware (Sec. 4.4); small instances
+ * do not, so here they are packed together.  Instances of the same algorithm
+ * and graph class (gg_class_of) are concatenated into one graph with
+ * per-instance vertex offsets, so every instance is a separate component
+ * and one multi-source traversal of the group computes all of them exactly
+ * as separate calls would (bit-identical).  Each group runs in the variant
+ * the tuner picks for the group's graph, on a stream of its own; after the
+ * first run the group's launch sequence is captured in a HIP graph and later
+ * runs replay it (rounds past the end return at once; a replay that stops
+ * short is continued with eager launches).  Not thread-safe per batch. */
+typedef struct gg_batch_s* gg_batch;
+
+typedef struct {
+    int32_t algo;            /* GG_ALGO_SSSP or GG_ALGO_BFS */
+    int32_t n;               /* vertices (>= 1) */
+    int64_t m;               /* edges */
+    const int32_t* row_ptr;  /* host CSR, same rules as gg_graph_upload */
+    const int32_t* col;
+    const int32_t* w;        /* weights (SSSP: required; BFS: ignored, may be NULL) */
+    int32_t source;          /* in [0, n) */
+    int32_t reserved;
+} gg_instance;
+
+#define GG_BATCH_NO_GRAPH 1u  /* enqueue eagerly on every run (no HIP graph capture) */
+#define GG_BATCH_ONE_GROUP 2u /* one group per algorithm, no split by class */
+
+/* Build a batch from host instances (copied).  GG_EINVAL for count < 1 or an
+ * invalid instance (bad algorithm, source out of range, malformed CSR,
+ * negative weight, SSSP without weights, more than 2^31 - 1 vertices or
+ * edges in one group).  The call returns when the upload is complete. */
+int gg_batch_create(const gg_instance* inst, int32_t count, uint32_t flags, void* stream,
+                    gg_batch* out);
+
+/* Run every instance.  out_dev: device int32 array of gg_batch_info's
+ * total_n entries; instance i's result is out_dev[v_off[i] .. v_off[i]+n_i)
+ * with v_off from gg_batch_offsets.  Enqueued on `stream` (the groups run on
+ * streams of their own that wait for and are waited by `stream`); the call
+ * returns once every group has finished its rounds. */
+int gg_batch_run(gg_batch b, int32_t* out_dev, void* stream);
+
+/* v_off[i] for each instance (count entries). */
+int gg_batch_offsets(gg_batch b, int64_t* v_off);
+
+/* Totals: groups, vertices (the length of out_dev), edges. */
+int gg_batch_info(gg_batch b, int32_t* groups, int64_t* total_n, int64_t* total_m);
+
+/* Group g: algorithm, instances, vertices, edges, the variant it runs, the
+ * rounds captured in its HIP graph (0 = not captured) and its last round
+ * count.  Outputs may be NULL. */
+int gg_batch_group(gg_batch b, int32_t g, int32_t* algo, int32_t* instances, int64_t* n,
+                   int64_t* m, int32_t* mode, int32_t* sched, int32_t* mapping,
+                   int32_t* captured_rounds, int32_t* last_rounds);
+
+/* Free a batch (waits for its work). */
+int gg_batch_free(gg_batch b);
+
 /* Human-readable status name. */
 const char* gg_status_str(int32_t status);
 

@@ -22,105 +22,12 @@
 #include <vector>
 
 #include "gg_internal.h"
+#include "gg_runtime.h"
 
 using namespace gg;
 
-namespace {
-
-constexpr int kVersion = 1;
-constexpr int kBlock = 256;
-constexpr int kMaxBatch = 16;
-constexpr int kDefaultTimeLimitMs = 60000;
-
-struct Dev {
-    int id = 0;
-    int cus = 0;
-    int max_blocks = 0;  // resident blocks of kBlock threads on the whole device
-};
-
-Dev& device() {
-    static Dev d;
-    static std::once_flag once;
-    std::call_once(once, [] {
-        hipGetDevice(&d.id);
-        hipDeviceProp_t p;
-        if (hipGetDeviceProperties(&p, d.id) == hipSuccess) {
-            d.cus = p.multiProcessorCount;
-            const int per_cu = std::max(1, p.maxThreadsPerMultiProcessor / kBlock);
-            d.max_blocks = std::min(kMaxStatBlocks, d.cus * per_cu);
-        }
-        if (d.max_blocks <= 0) d.max_blocks = 1024;
-    });
-    return d;
-}
-
-template <class T>
-hipError_t dalloc(T** p, size_t count) {
-    *p = nullptr;
-    if (count == 0) count = 1;
-    return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
-}
-
-template <class T>
-void dfree(T*& p) {
-    if (p) hipFree(p);
-    p = nullptr;
-}
-
-}  // namespace
-
-struct gg_ws_s {
-    gg_graph owner = nullptr;
-    DevWs dev{};
-    unsigned char* vflag_mem = nullptr;
-    int epoch = 0;  // round stamps of the next traversal start here
-    int* h_done = nullptr;  // pinned word written by the kernel that finds the end
-    hipEvent_t ev[2] = {nullptr, nullptr};
-    hipEvent_t finished = nullptr;
-    hipStream_t last_stream = nullptr;
-    bool used = false;
-    gg_stats last{};
-    bool is_default = false;
-    // GG_OPT_PROFILE: an event pair and a kind per launch of the last call
-    std::vector<hipEvent_t> pev;
-    std::vector<int> pkind;
-    int nlaunch = 0;
-    bool profiled = false;
-    int rounds = 0;
-};
-
-struct gg_graph_s {
-    int n = 0;
-    long long m = 0;
-    int max_deg = 0;
-    bool weighted = false;
-    bool has_sym = false;
-    bool symmetric = false;
-    int err = GG_OK;
-    int n_ws = 0;  // user workspaces alive
-    // device arrays
-    int *row = nullptr, *col = nullptr, *w = nullptr, *src = nullptr;
-    int *srow = nullptr, *scol = nullptr, *ssrc = nullptr;
-    int2 *hchunks = nullptr, *shchunks = nullptr;
-    int n_hchunks = 0, n_shchunks = 0;
-    long long ms = 0;
-    int heavy = kDefaultHeavy, chunk = kChunk;
-    gg_ws_s* ws0 = nullptr;
-};
 
 namespace {
-
-int fail_hip(gg_graph g, hipError_t e) {
-    if (e == hipSuccess) return GG_OK;
-    if (g && g->err == GG_OK) g->err = (e == hipErrorOutOfMemory) ? GG_ENOMEM : GG_EHIP;
-    return (e == hipErrorOutOfMemory) ? GG_ENOMEM : GG_EHIP;
-}
-
-#define HIPCHK(g, call)                                      \
-    do {                                                     \
-        hipError_t e_ = (call);                              \
-        if (e_ != hipSuccess) return fail_hip((g), e_);      \
-    } while (0)
 
 // Heavy-row chunks of a CSR held on the host.
 std::vector<int2> build_chunks(const std::vector<int>& row, int n, int heavy, int chunk) {
@@ -231,152 +138,187 @@ DevGraph dev_graph(gg_graph g) {
     return d;
 }
 
-// Built-in choice of variant when the caller asks for AUTO.
+// AUTO fields resolve through the tuning table (else built-in rules) for
+// the graph's class; explicit fields are kept.
 void resolve(gg_graph g, int algo, const gg_opts* in, gg_opts* out) {
     gg_opts o{};
     if (in) o = *in;
     const bool auto_mode = o.mode != GG_VERTEX && o.mode != GG_EDGE;
     const bool auto_sched = o.sched != GG_SYNC && o.sched != GG_ASYNC;
-    if (auto_mode) o.mode = GG_VERTEX;
-    if (auto_sched) o.sched = GG_ASYNC;
+    const bool auto_map = o.mapping < GG_MAP_THREAD || o.mapping > GG_MAP_BALANCED;
+    int32_t sc = 0, kc = 0, dc = -1, tm = GG_VERTEX, ts = GG_ASYNC, tp = GG_MAP_BALANCED;
+    gg_class_of(g->m, g->n, g->max_deg, g->levels, &sc, &kc, &dc);
+    gg_tune_lookup(algo, sc, kc, dc, &tm, &ts, &tp);
+    if (auto_mode) o.mode = tm;
+    if (auto_sched) o.sched = ts;
+    if (auto_map) o.mapping = tp;
     // without the both-directions CSR only the edge sweep can run CC
     if (algo == GG_ALGO_CC && !g->has_sym) {
         if (auto_mode) o.mode = GG_EDGE;
         if (auto_sched) o.sched = GG_SYNC;
     }
-    if (o.mapping < GG_MAP_THREAD || o.mapping > GG_MAP_BALANCED) o.mapping = GG_MAP_BALANCED;
     if (o.block_threads <= 0) o.block_threads = kBlock;
     if (o.time_limit_ms <= 0) o.time_limit_ms = kDefaultTimeLimitMs;
     *out = o;
 }
 
-int run(gg_graph g, gg_ws ws, int algo, int source, const gg_opts* opts, int* out, void* stream) {
+}  // namespace
+
+namespace gg {
+
+int plan_make(gg_graph g, gg_ws ws, int algo, int source, const int* sources_dev, int nsrc,
+              const gg_opts* opts, int* out, hipStream_t s, Plan* P) {
     if (!g) return GG_EINVAL;
     if (g->err != GG_OK) return g->err;
-    if (!out) return GG_EINVAL;
-    if (algo != GG_ALGO_CC && (source < 0 || source >= g->n)) return GG_EINVAL;
+    if (!out || nsrc < 0 || (nsrc > 0 && !sources_dev)) return GG_EINVAL;
+    if (algo != GG_ALGO_CC && nsrc == 0 && (source < 0 || source >= g->n)) return GG_EINVAL;
     if (algo == GG_ALGO_SSSP && !g->weighted) return GG_EINVAL;
     if (!ws) ws = g->ws0;
     if (ws->owner != g) return GG_EINVAL;
-    gg_opts o;
-    resolve(g, algo, opts, &o);
+    Plan& p = *P;
+    p = Plan{};
+    p.g = g;
+    p.ws = ws;
+    p.algo = algo;
+    p.s = s;
+    resolve(g, algo, opts, &p.o);
+    const gg_opts& o = p.o;
     // CC reads the both-directions CSR except in the synchronous edge sweep
     if (algo == GG_ALGO_CC && !g->has_sym && (o.mode != GG_EDGE || o.sched != GG_SYNC))
         return GG_ENOTSUP;
     if (o.block_threads != kBlock) return GG_ENOTSUP;
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const Dev& dv = device();
     const int cap_blocks = o.max_blocks > 0 ? std::min(o.max_blocks, dv.max_blocks) : dv.max_blocks;
     auto grid = [&](long long units) {
         return (int)std::max(1LL, std::min<long long>(units, cap_blocks));
     };
-
-    // a workspace serves one traversal at a time: order after its last one
-    if (ws->used && ws->last_stream != s) HIPCHK(g, hipStreamWaitEvent(s, ws->finished, 0));
-
-    const bool async = o.sched == GG_ASYNC;
-    const bool edge = o.mode == GG_EDGE;
-    const bool cc = algo == GG_ALGO_CC;
-    Round R{};
+    p.async = o.sched == GG_ASYNC;
+    p.edge = o.mode == GG_EDGE;
+    p.cc = algo == GG_ALGO_CC;
+    Round& R = p.R;
     R.g = dev_graph(g);
     R.ws = ws->dev;
     R.val = out;
-    R.source = cc ? 0 : source;
-    R.r = 0;
+    R.source = p.cc ? 0 : source;
+    R.sources = sources_dev;
+    R.nsrc = p.cc ? 0 : nsrc;
     R.mapping = o.mapping;
-    R.jump = cc && !(o.flags & GG_OPT_CC_NO_JUMP);
+    R.jump = p.cc && !(o.flags & GG_OPT_CC_NO_JUMP);
+    R.host_done = ws->h_done;
 
     const int wpb = kBlock / 64;
     const long long n = g->n;
     const long long ntiles = (n + 63) / 64;
     const long long ngroups = (ntiles + 63) / 64;
-    const int nh = cc ? g->n_shchunks : g->n_hchunks;
-    const int g_init = grid((n + kBlock - 1) / kBlock);
-    int g_round;
-    if (!async && !edge) {
-        if (o.mapping == GG_MAP_BALANCED) g_round = grid((nh + ntiles + wpb - 1) / wpb);
-        else if (o.mapping == GG_MAP_THREAD) g_round = grid((n + kBlock - 1) / kBlock);
-        else g_round = grid((n + wpb - 1) / wpb);
-    } else if (!async && edge) {
-        g_round = grid((g->m / 4 + kBlock - 1) / kBlock);
+    const int nh = p.cc ? g->n_shchunks : g->n_hchunks;
+    p.g_init = grid((n + kBlock - 1) / kBlock);
+    p.g_seed = grid((nsrc + kBlock - 1) / kBlock);
+    if (!p.async && !p.edge) {
+        if (o.mapping == GG_MAP_BALANCED) p.g_round = grid((nh + ntiles + wpb - 1) / wpb);
+        else if (o.mapping == GG_MAP_THREAD) p.g_round = grid((n + kBlock - 1) / kBlock);
+        else p.g_round = grid((n + wpb - 1) / wpb);
+    } else if (!p.async && p.edge) {
+        p.g_round = grid((g->m / 4 + kBlock - 1) / kBlock);
     } else {
-        g_round = grid((ngroups * 8 + wpb - 1) / wpb);
+        p.g_round = grid((ngroups * kParts + wpb - 1) / wpb);
     }
-    const bool need_heavy = async && (edge || o.mapping == GG_MAP_BALANCED) && nh > 0;
-    const int g_heavy = grid((nh + 64LL * wpb - 1) / (64LL * wpb));
-    const bool need_jump = cc && edge && !async && R.jump;
-    const int g_jump = grid((n + kBlock - 1) / kBlock);
+    p.need_heavy = p.async && (p.edge || o.mapping == GG_MAP_BALANCED) && nh > 0;
+    p.g_heavy = grid((nh + 64LL * wpb - 1) / (64LL * wpb));
+    p.need_jump = p.cc && p.edge && !p.async && R.jump;
+    p.g_jump = grid((n + kBlock - 1) / kBlock);
+    return GG_OK;
+}
 
-    const bool prof = (o.flags & GG_OPT_PROFILE) != 0;
-    ws->profiled = prof;
-    ws->nlaunch = 0;
-    // every launch goes through here so that profiling brackets it
-    auto launch = [&](int kind, auto&& fn) -> hipError_t {
-        hipError_t e = hipSuccess;
-        const int i = ws->nlaunch;
-        if (prof) {
-            while ((int)ws->pev.size() < 2 * (i + 1)) {
-                hipEvent_t ev;
-                e = hipEventCreate(&ev);
-                if (e != hipSuccess) return e;
-                ws->pev.push_back(ev);
-            }
-            if ((int)ws->pkind.size() < i + 1) ws->pkind.resize(i + 1);
-            e = hipEventRecord(ws->pev[2 * i], s);
-            if (e != hipSuccess) return e;
-        }
-        e = fn();
-        if (prof && e == hipSuccess) {
-            e = hipEventRecord(ws->pev[2 * i + 1], s);
-            ws->pkind[i] = kind;
-            ws->nlaunch = i + 1;
-        }
-        return e;
-    };
+// Every launch goes through here so that profiling can bracket it.
+template <class F>
+hipError_t plan_launch(Plan& p, int kind, F&& fn) {
+    gg_ws ws = p.ws;
+    if (!p.prof) return fn();
+    hipError_t e = hipSuccess;
+    const int i = ws->nlaunch;
+    while ((int)ws->pev.size() < 2 * (i + 1)) {
+        hipEvent_t ev;
+        e = hipEventCreate(&ev);
+        if (e != hipSuccess) return e;
+        ws->pev.push_back(ev);
+    }
+    if ((int)ws->pkind.size() < i + 1) ws->pkind.resize(i + 1);
+    e = hipEventRecord(ws->pev[2 * i], p.s);
+    if (e != hipSuccess) return e;
+    e = fn();
+    if (e == hipSuccess) {
+        e = hipEventRecord(ws->pev[2 * i + 1], p.s);
+        ws->pkind[i] = kind;
+        ws->nlaunch = i + 1;
+    }
+    return e;
+}
 
-    // round stamps of heavy frontier rows must not repeat across traversals
-    // of this workspace; restart them (and clear the stamps) long before the
-    // 32-bit range ends
-    if (ws->epoch > (1 << 30)) {
-        HIPCHK(g, hipMemsetAsync(ws->dev.hstamp, 0xff, sizeof(int) * (size_t)g->n, s));
+hipError_t plan_init(Plan& p) {
+    hipError_t e = plan_launch(p, KIND_AUX, [&] {
+        return launch_init(p.R, p.algo, p.async, p.g_init, kBlock, p.s);
+    });
+    if (e == hipSuccess && p.R.nsrc > 0)
+        e = plan_launch(p, KIND_AUX, [&] { return launch_seed(p.R, p.async, p.g_seed, kBlock, p.s); });
+    return e;
+}
+
+// Round r with heavy-row stamp `stamp`.
+hipError_t plan_round(Plan& p, int r, int stamp) {
+    Round& R = p.R;
+    R.r = r;
+    R.stamp = stamp;
+    hipError_t e = plan_launch(p, KIND_ROUND, [&] {
+        if (!p.async && !p.edge) return launch_vsync(R, p.algo, p.g_round, kBlock, p.s);
+        if (!p.async) return launch_esync(R, p.algo, p.g_round, kBlock, p.s);
+        if (!p.edge) return launch_vasync(R, p.algo, p.g_round, kBlock, p.s);
+        return launch_easync(R, p.algo, p.g_round, kBlock, p.s);
+    });
+    if (e == hipSuccess && p.need_heavy)
+        e = plan_launch(p, KIND_HEAVY, [&] { return launch_heavy(R, p.algo, p.g_heavy, kBlock, p.s); });
+    if (e == hipSuccess && p.need_jump)
+        e = plan_launch(p, KIND_AUX, [&] { return launch_jump(R, p.g_jump, kBlock, p.s); });
+    return e;
+}
+
+// Reserve `span` round stamps on the workspace; returns the first.  Stamps
+// never repeat across traversals of a workspace (the heavy kernel serves a
+// chunk only when its row carries the current round's stamp); they restart,
+// with the stamp array cleared, long before the 32-bit range ends.
+int reserve_stamps(gg_ws ws, hipStream_t s, long long span, hipError_t* err) {
+    *err = hipSuccess;
+    if ((long long)ws->epoch + span > (1LL << 30)) {
+        *err = hipMemsetAsync(ws->dev.hstamp, 0xff, sizeof(int) * (size_t)ws->owner->n, s);
         ws->epoch = 0;
     }
-    const int epoch = ws->epoch;
-    R.stamp = epoch;
-    R.epoch = epoch;
-    R.host_done = ws->h_done;
-    HIPCHK(g, launch(KIND_AUX, [&] { return launch_init(R, algo, async, g_init, kBlock, s); }));
+    const int base = ws->epoch;
+    ws->epoch = (int)std::min<long long>((long long)base + span, 1LL << 30);
+    return base;
+}
 
-    // bound on rounds: every productive round fixes at least one more vertex
-    const long long max_rounds = n + 2;
+// Eager driver: enqueue rounds r0, r0+1, ... in doubling batches until the
+// round kernel reports the end through the workspace's pinned word (the
+// traversal tag `tag` is what that kernel stores).  Returns GG_OK, GG_EITER
+// or GG_ETIMEOUT; *r_end = rounds enqueued.
+int plan_drive(Plan& p, long long r0, int stamp_base, int tag, long long* r_end) {
+    gg_graph g = p.g;
+    gg_ws ws = p.ws;
+    hipStream_t s = p.s;
+    const long long max_rounds = (long long)g->n + 2;
     const auto t0 = std::chrono::steady_clock::now();
     int status = GG_OK;
-    long long r = 0;
+    long long r = r0;
     int batch = 2, k = 0;
     bool pending = false;
+    auto finished = [&] { return __atomic_load_n(ws->h_done, __ATOMIC_ACQUIRE) == tag; };
     for (;;) {
-        const long long r_end = std::min(r + batch, max_rounds);
-        for (; r < r_end; ++r) {
-            R.r = (int)r;
-            R.stamp = epoch + (int)r;
-            hipError_t e = launch(KIND_ROUND, [&] {
-                if (!async && !edge) return launch_vsync(R, algo, g_round, kBlock, s);
-                if (!async) return launch_esync(R, algo, g_round, kBlock, s);
-                if (!edge) return launch_vasync(R, algo, g_round, kBlock, s);
-                return launch_easync(R, algo, g_round, kBlock, s);
-            });
-            if (e == hipSuccess && need_heavy)
-                e = launch(KIND_HEAVY, [&] { return launch_heavy(R, algo, g_heavy, kBlock, s); });
-            if (e == hipSuccess && need_jump)
-                e = launch(KIND_AUX, [&] { return launch_jump(R, g_jump, kBlock, s); });
-            HIPCHK(g, e);
-        }
+        const long long stop = std::min(r + batch, max_rounds);
+        for (; r < stop; ++r) HIPCHK(g, plan_round(p, (int)r, stamp_base + (int)r));
         const int slot = k & 1;
         HIPCHK(g, hipEventRecord(ws->ev[slot], s));
-        auto finished = [&] { return __atomic_load_n(ws->h_done, __ATOMIC_ACQUIRE) == epoch; };
         if (pending) {
-            // the previous batch has run once its event completes; the end may
-            // have been reported by a kernel of it (or of the current batch)
+            // the previous batch has run once its event completes; the end
+            // may have been reported by a kernel of it or of the current one
             HIPCHK(g, hipEventSynchronize(ws->ev[slot ^ 1]));
             if (finished()) break;
         }
@@ -389,27 +331,66 @@ int run(gg_graph g, gg_ws ws, int algo, int source, const gg_opts* opts, int* ou
         }
         const long long ms = std::chrono::duration_cast<std::chrono::milliseconds>(
                                  std::chrono::steady_clock::now() - t0).count();
-        if (ms > o.time_limit_ms) {
+        if (ms > p.o.time_limit_ms) {
             HIPCHK(g, hipEventSynchronize(ws->ev[slot]));
             if (!finished()) status = GG_ETIMEOUT;
             break;
         }
         batch = std::min(batch * 2, kMaxBatch);
     }
-    HIPCHK(g, hipEventRecord(ws->finished, s));
-    ws->epoch = epoch + (int)r + 1;
-    ws->rounds = (int)r;
-    ws->last_stream = s;
+    *r_end = r;
+    return status;
+}
+
+void record_last(Plan& p, int status, long long rounds) {
+    gg_ws ws = p.ws;
+    ws->rounds = (int)rounds;
+    ws->last_stream = p.s;
     ws->used = true;
     ws->last = gg_stats{};
-    ws->last.algo = algo;
-    ws->last.mode = o.mode;
-    ws->last.sched = o.sched;
-    ws->last.mapping = edge ? 0 : o.mapping;
+    ws->last.algo = p.algo;
+    ws->last.mode = p.o.mode;
+    ws->last.sched = p.o.sched;
+    ws->last.mapping = p.edge ? 0 : p.o.mapping;
     ws->last.status = status;
-    ws->last.grid_blocks = g_round;
+    ws->last.grid_blocks = p.g_round;
     ws->last.block_threads = kBlock;
+}
+
+int run_multi(gg_graph g, gg_ws ws, int algo, int source, const int* sources_dev, int nsrc,
+              const gg_opts* opts, int* out, void* stream) {
+    Plan p;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    int rc = plan_make(g, ws, algo, source, sources_dev, nsrc, opts, out, s, &p);
+    if (rc != GG_OK) return rc;
+    ws = p.ws;
+    // a workspace serves one traversal at a time: order after its last one
+    if (ws->used && ws->last_stream != s) HIPCHK(g, hipStreamWaitEvent(s, ws->finished, 0));
+    p.prof = (p.o.flags & GG_OPT_PROFILE) != 0;
+    ws->profiled = p.prof;
+    ws->nlaunch = 0;
+    hipError_t e;
+    const int base = reserve_stamps(ws, s, (long long)g->n + 3, &e);
+    HIPCHK(g, e);
+    p.R.epoch = base;
+    p.R.stamp = base;
+    HIPCHK(g, plan_init(p));
+    long long r_end = 0;
+    const int status = plan_drive(p, 0, base, base, &r_end);
+    if (status != GG_OK && status != GG_EITER && status != GG_ETIMEOUT) return status;
+    // stamps of later traversals start after the rounds used here
+    ws->epoch = base + (int)std::min<long long>(r_end + 1, (long long)g->n + 3);
+    HIPCHK(g, hipEventRecord(ws->finished, s));
+    record_last(p, status, r_end);
     return status;
+}
+
+}  // namespace gg
+
+namespace {
+
+int run(gg_graph g, gg_ws ws, int algo, int source, const gg_opts* opts, int* out, void* stream) {
+    return run_multi(g, ws, algo, source, nullptr, 0, opts, out, stream);
 }
 
 }  // namespace
@@ -449,10 +430,13 @@ int gg_graph_upload(int32_t n, int64_t m, const int32_t* row_ptr, const int32_t*
         std::memcpy(hrow.data(), row_ptr, sizeof(int) * ((size_t)n + 1));
     }
     if (hrow[0] != 0 || hrow[n] != m) return GG_EINVAL;
-    int max_deg = 0;
+    int max_deg = 0, argmax_deg = 0;
     for (int v = 0; v < n; ++v) {
         if (hrow[v + 1] < hrow[v]) return GG_EINVAL;
-        max_deg = std::max(max_deg, hrow[v + 1] - hrow[v]);
+        if (hrow[v + 1] - hrow[v] > max_deg) {
+            max_deg = hrow[v + 1] - hrow[v];
+            argmax_deg = v;
+        }
     }
     if (!on_dev) {
         for (long long e = 0; e < m; ++e)
@@ -466,6 +450,7 @@ int gg_graph_upload(int32_t n, int64_t m, const int32_t* row_ptr, const int32_t*
     g->n = n;
     g->m = m;
     g->max_deg = max_deg;
+    g->argmax_deg = argmax_deg;
     g->weighted = w != nullptr;
     const hipMemcpyKind kind = on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     auto bail = [&](int code) {
@@ -718,6 +703,28 @@ int gg_last_profile(gg_graph g, gg_ws ws, gg_profile* out) {
             out->kind[kind].pushes += x.pushes;
         }
     return GG_OK;
+}
+
+int gg_graph_probe(gg_graph g, void* stream) {
+    if (!g) return GG_EINVAL;
+    int* dist = nullptr;
+    HIPCHK(g, dalloc(&dist, (size_t)g->n));
+    gg_opts o{};
+    o.mode = GG_VERTEX;
+    o.sched = GG_ASYNC;
+    o.mapping = GG_MAP_BALANCED;
+    int rc = run(g, nullptr, GG_ALGO_BFS, g->argmax_deg, &o, dist, stream);
+    gg_stats st{};
+    if (rc == GG_OK) rc = gg_last_stats(g, nullptr, &st);
+    hipFree(dist);
+    if (rc != GG_OK) return rc;
+    g->levels = st.iterations;
+    return GG_OK;
+}
+
+int gg_graph_class(gg_graph g, int32_t* size_class, int32_t* skew_class, int32_t* depth_class) {
+    if (!g) return GG_EINVAL;
+    return gg_class_of(g->m, g->n, g->max_deg, g->levels, size_class, skew_class, depth_class);
 }
 
 int gg_resolve(gg_graph g, int32_t algo, const gg_opts* in, gg_opts* out) {

@@ -14,6 +14,7 @@ constexpr int kMaxStatBlocks = 4096; // per-block statistics slots
 constexpr int kDefaultHeavy = 64;    // rows longer than this are chunked (balanced mapping)
 constexpr int kChunk = 256;          // edges per heavy-row chunk
 constexpr int kKinds = 3;            // statistics kinds: round, heavy chunks, auxiliary
+constexpr int kParts = 32;           // frontier work items per 64-tile group (2 tiles each)
 enum Kind { KIND_ROUND = 0, KIND_HEAVY = 1, KIND_AUX = 2 };
 
 enum Algo { SSSP = 0, BFS = 1, CC = 2 };
@@ -73,7 +74,9 @@ struct Round {
     DevGraph g;
     DevWs ws;
     int* val;    // dist or label, [n]
-    int source;
+    int source;          // single source (when nsrc == 0)
+    const int* sources;  // device list of sources of a multi-source traversal
+    int nsrc;
     int r;       // round (sweep, level) index
     int stamp;   // r + a per-workspace epoch that grows across traversals
     int epoch;   // stamp of round 0 of this traversal
@@ -85,6 +88,7 @@ struct Round {
 // Launch entry points (gg_kernels.hip).  Each returns the hipError_t of the
 // launch.
 hipError_t launch_init(const Round& R, int algo, bool async, int grid, int block, hipStream_t s);
+hipError_t launch_seed(const Round& R, bool async, int grid, int block, hipStream_t s);
 hipError_t launch_vsync(const Round& R, int algo, int grid, int block, hipStream_t s);
 hipError_t launch_esync(const Round& R, int algo, int grid, int block, hipStream_t s);
 hipError_t launch_vasync(const Round& R, int algo, int grid, int block, hipStream_t s);

@@ -32,9 +32,9 @@
 
 namespace gg {
 
-// A frontier work item is one 32nd of a 64-tile group: the wavefront loads
-// the 64 tile flags of the group at once and serves the 2 tiles of its part.
-constexpr int kParts = 32;
+// A frontier work item is one kParts-th of a 64-tile group: the wavefront
+// loads the 64 tile flags of the group at once and serves the 2 tiles of its
+// part.
 
 // Edges each lane keeps in flight in the relaxation loops.
 constexpr int kBatch = 4;
@@ -312,25 +312,44 @@ __device__ __forceinline__ void push(const Round& R, int nxt, int t) {
 
 // ------------------------------------------------------------ kernels ----
 
+// Init: values INF (labels = ids for CC), the source at 0 and on the first
+// frontier.  A multi-source traversal (R.nsrc > 0) marks no source here;
+// k_seed does it after this kernel.
 __global__ __launch_bounds__(256) void k_init(Round R, int algo, int async) {
     const int n = R.g.n;
     const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long tt = (long long)gridDim.x * blockDim.x;
+    const long long src = R.nsrc > 0 ? -1 : R.source;
     for (long long v = tid; v < n; v += tt) {
-        R.val[v] = algo == CC ? (int)v : (v == R.source ? 0 : kInf);
+        R.val[v] = algo == CC ? (int)v : (v == src ? 0 : kInf);
         if (async) {
-            const bool on = algo == CC || v == R.source;
+            const bool on = algo == CC || v == src;
             R.ws.vflag[0][v] = on;
             R.ws.vflag[1][v] = 0;
             if ((v & 63) == 0) {
                 const long long t = v >> 6;
-                R.ws.tflag[0][t] = algo == CC || t == (R.source >> 6);
+                R.ws.tflag[0][t] = algo == CC || t == (src >> 6);
                 R.ws.tflag[1][t] = 0;
             }
         }
     }
     for (long long i = tid; i < kKinds * kMaxStatBlocks; i += tt) R.ws.stat[i] = Stat{0, 0, 0, 0};
     if (tid == 0) *R.ws.ctl = Ctl{};
+}
+
+// Sources of a multi-source traversal (disjoint instances packed into one
+// graph): value 0 and a place on the first frontier.
+__global__ __launch_bounds__(256) void k_seed(Round R, int async) {
+    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long tt = (long long)gridDim.x * blockDim.x;
+    for (long long i = tid; i < R.nsrc; i += tt) {
+        const int s = R.sources[i];
+        R.val[s] = 0;
+        if (async) {
+            R.ws.vflag[0][s] = 1;
+            R.ws.tflag[0][s >> 6] = 1;
+        }
+    }
 }
 
 // Synchronous vertex sweep (Algorithm 1; Algorithm 3 for BFS).
@@ -788,6 +807,10 @@ static int resident_cap(const void* f, int block) {
 
 hipError_t launch_init(const Round& R, int algo, bool async, int grid, int block, hipStream_t s) {
     GG_LAUNCH(k_init, grid, block, s, R, algo, async ? 1 : 0);
+}
+
+hipError_t launch_seed(const Round& R, bool async, int grid, int block, hipStream_t s) {
+    GG_LAUNCH(k_seed, grid, block, s, R, async ? 1 : 0);
 }
 
 template <int A>

@@ -1,0 +1,146 @@
+// gg_runtime.h -- host-side internals shared by the runtime sources of libgg
+// (gg_api.hip, gg_batch.hip): handle structures, device facts, the traversal
+// plan and its enqueue functions.  Not part of the public ABI.
+#pragma once
+
+#include <gg.h>
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "gg_internal.h"
+
+namespace gg {
+
+constexpr int kVersion = 1;
+constexpr int kBlock = 256;
+constexpr int kMaxBatch = 16;
+constexpr int kDefaultTimeLimitMs = 60000;
+
+struct Dev {
+    int id = 0;
+    int cus = 0;
+    int max_blocks = 0;  // resident blocks of kBlock threads on the whole device
+};
+
+inline Dev& device() {
+    static Dev d;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        hipGetDevice(&d.id);
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, d.id) == hipSuccess) {
+            d.cus = p.multiProcessorCount;
+            const int per_cu = std::max(1, p.maxThreadsPerMultiProcessor / kBlock);
+            d.max_blocks = std::min(kMaxStatBlocks, d.cus * per_cu);
+        }
+        if (d.max_blocks <= 0) d.max_blocks = 1024;
+    });
+    return d;
+}
+
+template <class T>
+hipError_t dalloc(T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
+}
+
+template <class T>
+void dfree(T*& p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+}  // namespace gg
+
+struct gg_ws_s {
+    gg_graph owner = nullptr;
+    gg::DevWs dev{};
+    unsigned char* vflag_mem = nullptr;
+    int epoch = 0;  // round stamps of the next traversal start here
+    int* h_done = nullptr;  // pinned word written by the kernel that finds the end
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipEvent_t finished = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool used = false;
+    gg_stats last{};
+    bool is_default = false;
+    // GG_OPT_PROFILE: an event pair and a kind per launch of the last call
+    std::vector<hipEvent_t> pev;
+    std::vector<int> pkind;
+    int nlaunch = 0;
+    bool profiled = false;
+    int rounds = 0;
+};
+
+struct gg_graph_s {
+    int n = 0;
+    long long m = 0;
+    int max_deg = 0;
+    int argmax_deg = 0;
+    int levels = -1;  // BFS rounds from argmax_deg, measured by gg_graph_probe
+    bool weighted = false;
+    bool has_sym = false;
+    bool symmetric = false;
+    int err = GG_OK;
+    int n_ws = 0;  // user workspaces alive
+    // device arrays
+    int *row = nullptr, *col = nullptr, *w = nullptr, *src = nullptr;
+    int *srow = nullptr, *scol = nullptr, *ssrc = nullptr;
+    int2 *hchunks = nullptr, *shchunks = nullptr;
+    int n_hchunks = 0, n_shchunks = 0;
+    long long ms = 0;
+    int heavy = gg::kDefaultHeavy, chunk = gg::kChunk;
+    gg_ws_s* ws0 = nullptr;
+};
+
+namespace gg {
+
+inline int fail_hip(gg_graph g, hipError_t e) {
+    if (e == hipSuccess) return GG_OK;
+    if (g && g->err == GG_OK) g->err = (e == hipErrorOutOfMemory) ? GG_ENOMEM : GG_EHIP;
+    return (e == hipErrorOutOfMemory) ? GG_ENOMEM : GG_EHIP;
+}
+
+#define HIPCHK(g, call)                                      \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return fail_hip((g), e_);      \
+    } while (0)
+
+// A traversal prepared for enqueueing: variant, launch shapes and the round
+// template.  The eager driver and graph capture share it.
+struct Plan {
+    gg_graph g = nullptr;
+    gg_ws ws = nullptr;
+    int algo = 0;
+    gg_opts o{};
+    hipStream_t s = nullptr;
+    Round R{};
+    bool async = false, edge = false, cc = false;
+    bool need_heavy = false, need_jump = false, prof = false;
+    int g_init = 1, g_seed = 1, g_round = 1, g_heavy = 1, g_jump = 1;
+};
+
+// Validate a call and fill the plan (variant resolved, grids sized).
+int plan_make(gg_graph g, gg_ws ws, int algo, int source, const int* sources_dev, int nsrc,
+              const gg_opts* opts, int* out, hipStream_t s, Plan* P);
+// Enqueue the init kernel (and the seed kernel of a multi-source plan).
+hipError_t plan_init(Plan& p);
+// Enqueue round r (round kernel, heavy-chunk or shortcut kernel as needed).
+hipError_t plan_round(Plan& p, int r, int stamp);
+// Reserve `span` round stamps on a workspace; returns the first.
+int reserve_stamps(gg_ws ws, hipStream_t s, long long span, hipError_t* err);
+// Eager driver from round r0 until the end is reported (see gg_api.hip).
+int plan_drive(Plan& p, long long r0, int stamp_base, int tag, long long* r_end);
+// Record the variant, status and round count of a finished call.
+void record_last(Plan& p, int status, long long rounds);
+// One traversal from one source or from a device list of sources.
+int run_multi(gg_graph g, gg_ws ws, int algo, int source, const int* sources_dev, int nsrc,
+              const gg_opts* opts, int* out, void* stream);
+
+}  // namespace gg

@@ -1,0 +1,101 @@
+// gg_tune.cpp -- graph classes and the process-wide tuning table behind the
+// AUTO variant choice (declared in include/gg.h).  Host code only.
+
+#include <gg.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <mutex>
+#include <vector>
+
+namespace {
+
+std::mutex g_mu;
+std::vector<gg_tune_entry> g_table;
+
+bool valid(const gg_tune_entry& e) {
+    return e.algo >= 0 && e.algo <= 2 && e.size_class >= 0 && e.size_class < 64 &&
+           e.skew_class >= 0 && e.skew_class <= 2 && e.depth_class >= -1 && e.depth_class <= 2 &&
+           (e.mode == GG_VERTEX || e.mode == GG_EDGE) && (e.sched == GG_SYNC || e.sched == GG_ASYNC) &&
+           e.mapping >= GG_MAP_AUTO && e.mapping <= GG_MAP_BALANCED;
+}
+
+// Built-in choice, from the measured behaviour of the variants on the
+// synthetic workloads (uniform, R-MAT, grid): asynchronous vertex-based
+// rounds for SSSP everywhere; BFS synchronous on shallow graphs and
+// asynchronous on deep ones; CC by edge sweeps with the shortcut.
+void builtin(int algo, int depth, int32_t* mode, int32_t* sched, int32_t* mapping) {
+    *mapping = GG_MAP_BALANCED;
+    if (algo == GG_ALGO_SSSP) {
+        *mode = GG_VERTEX;
+        *sched = GG_ASYNC;
+    } else if (algo == GG_ALGO_BFS) {
+        *mode = GG_VERTEX;
+        *sched = depth >= 1 || depth < 0 ? GG_ASYNC : GG_SYNC;
+    } else {
+        *mode = GG_EDGE;
+        *sched = GG_SYNC;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int gg_class_of(int64_t m, int32_t n, int32_t max_out_degree, int32_t levels,
+                int32_t* size_class, int32_t* skew_class, int32_t* depth_class) {
+    if (n < 1 || m < 0 || max_out_degree < 0 || !size_class || !skew_class || !depth_class)
+        return GG_EINVAL;
+    int lg = 0;
+    for (int64_t x = m > 1 ? m : 1; x > 1; x >>= 1) ++lg;
+    *size_class = lg / 2;
+    const double avg = (double)m / (double)n;
+    const double skew = avg > 0 ? (double)max_out_degree / avg : 0.0;
+    *skew_class = skew < 8.0 ? 0 : skew < 128.0 ? 1 : 2;
+    *depth_class = levels < 0 ? -1 : levels < 16 ? 0 : levels < 256 ? 1 : 2;
+    return GG_OK;
+}
+
+int gg_tune_set(const gg_tune_entry* entries, int32_t count) {
+    if (count < 0 || (count > 0 && !entries)) return GG_EINVAL;
+    for (int i = 0; i < count; ++i)
+        if (!valid(entries[i])) return GG_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_table.assign(entries, entries + count);
+    return GG_OK;
+}
+
+int gg_tune_get(gg_tune_entry* out, int32_t cap) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    const int n = (int)g_table.size();
+    for (int i = 0; i < n && i < cap && out; ++i) out[i] = g_table[i];
+    return n;
+}
+
+int gg_tune_lookup(int32_t algo, int32_t size_class, int32_t skew_class, int32_t depth_class,
+                   int32_t* mode, int32_t* sched, int32_t* mapping) {
+    if (algo < 0 || algo > 2 || !mode || !sched || !mapping) return GG_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    int best = -1, best_score = 1 << 30;
+    for (int i = 0; i < (int)g_table.size(); ++i) {
+        const gg_tune_entry& e = g_table[i];
+        if (e.algo != algo) continue;
+        int score = std::abs(e.size_class - size_class);
+        if (e.skew_class != skew_class) score += 4;
+        if (e.depth_class >= 0 && depth_class >= 0 && e.depth_class != depth_class) score += 4;
+        if (score < best_score) {
+            best_score = score;
+            best = i;
+        }
+    }
+    if (best < 0) {
+        builtin(algo, depth_class, mode, sched, mapping);
+    } else {
+        *mode = g_table[best].mode;
+        *sched = g_table[best].sched;
+        *mapping = g_table[best].mapping == GG_MAP_AUTO ? GG_MAP_BALANCED : g_table[best].mapping;
+    }
+    return GG_OK;
+}
+
+}  // extern "C"

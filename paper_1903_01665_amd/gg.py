@@ -33,7 +33,12 @@ STATUS = {0: "GG_OK", -1: "GG_EINVAL", -2: "GG_ENOMEM", -3: "GG_EHIP", -4: "GG_E
 EXPORTS = ["gg_graph_upload", "gg_graph_free", "gg_graph_info", "gg_graph_error", "gg_sssp",
            "gg_bfs", "gg_cc", "gg_ws_create", "gg_ws_free", "gg_sssp_ex", "gg_bfs_ex",
            "gg_cc_ex", "gg_last_stats", "gg_last_profile", "gg_resolve", "gg_status_str",
-           "gg_version"]
+           "gg_version", "gg_tune_set", "gg_tune_get", "gg_class_of", "gg_tune_lookup",
+           "gg_graph_probe", "gg_graph_class", "gg_batch_create", "gg_batch_run",
+           "gg_batch_offsets", "gg_batch_info", "gg_batch_group", "gg_batch_free"]
+BATCH_NO_GRAPH, BATCH_ONE_GROUP = 1, 2
+
+TUNE_TABLE = os.path.join(_HERE, "tune_table.json")
 
 
 class GGError(RuntimeError):
@@ -59,6 +64,19 @@ class Stats(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("algo", ctypes.c_int32), ("size_class", ctypes.c_int32),
+                ("skew_class", ctypes.c_int32), ("depth_class", ctypes.c_int32),
+                ("mode", ctypes.c_int32), ("sched", ctypes.c_int32), ("mapping", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [("algo", ctypes.c_int32), ("n", ctypes.c_int32), ("m", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("w", ctypes.c_void_p),
+                ("source", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class KindProfile(ctypes.Structure):
@@ -105,6 +123,19 @@ def lib():
     L.gg_last_stats.argtypes = [vp, vp, P(Stats)]
     L.gg_last_profile.argtypes = [vp, vp, P(Profile)]
     L.gg_resolve.argtypes = [vp, i32, P(Opts), P(Opts)]
+    L.gg_tune_set.argtypes = [P(TuneEntry), i32]
+    L.gg_tune_get.argtypes = [P(TuneEntry), i32]
+    L.gg_class_of.argtypes = [i64, i32, i32, i32, P(i32), P(i32), P(i32)]
+    L.gg_tune_lookup.argtypes = [i32, i32, i32, i32, P(i32), P(i32), P(i32)]
+    L.gg_graph_probe.argtypes = [vp, vp]
+    L.gg_graph_class.argtypes = [vp, P(i32), P(i32), P(i32)]
+    L.gg_batch_create.argtypes = [P(Instance), i32, u32, vp, P(vp)]
+    L.gg_batch_run.argtypes = [vp, vp, vp]
+    L.gg_batch_offsets.argtypes = [vp, P(i64)]
+    L.gg_batch_info.argtypes = [vp, P(i32), P(i64), P(i64)]
+    L.gg_batch_group.argtypes = [vp, i32, P(i32), P(i32), P(i64), P(i64), P(i32), P(i32),
+                                 P(i32), P(i32), P(i32)]
+    L.gg_batch_free.argtypes = [vp]
     L.gg_status_str.argtypes = [i32]
     L.gg_status_str.restype = ctypes.c_char_p
     L.gg_version.argtypes = []
@@ -114,7 +145,48 @@ def lib():
     if L.gg_version() != 1:
         raise RuntimeError("libgg.so version mismatch")
     _lib = L
+    if os.path.exists(TUNE_TABLE):
+        load_tune_table(TUNE_TABLE)
     return L
+
+
+# ------------------------------------------------------------- tuning ------
+def tune_set(entries):
+    """Install a tuning table: a list of dicts with algo, size_class,
+    skew_class, depth_class, mode, sched, mapping."""
+    arr = (TuneEntry * max(1, len(entries)))()
+    for i, e in enumerate(entries):
+        for k in ("algo", "size_class", "skew_class", "depth_class", "mode", "sched", "mapping"):
+            setattr(arr[i], k, int(e[k]))
+    _check(lib().gg_tune_set(arr, len(entries)), "gg_tune_set")
+
+
+def tune_get():
+    n = lib().gg_tune_get(None, 0)
+    arr = (TuneEntry * max(1, n))()
+    lib().gg_tune_get(arr, n)
+    return [{k: getattr(arr[i], k) for k, _ in TuneEntry._fields_ if k != "reserved"}
+            for i in range(n)]
+
+
+def load_tune_table(path):
+    import json
+    with open(path) as f:
+        tune_set(json.load(f)["entries"])
+
+
+def class_of(m, n, max_out_degree, levels=-1):
+    a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().gg_class_of(m, n, max_out_degree, levels, ctypes.byref(a), ctypes.byref(b),
+                             ctypes.byref(c)), "gg_class_of")
+    return a.value, b.value, c.value
+
+
+def tune_lookup(algo, size_class, skew_class, depth_class):
+    a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().gg_tune_lookup(algo, size_class, skew_class, depth_class, ctypes.byref(a),
+                                ctypes.byref(b), ctypes.byref(c)), "gg_tune_lookup")
+    return a.value, b.value, c.value
 
 
 def _check(rc, what):
@@ -255,11 +327,92 @@ class Graph:
                                      ctypes.byref(p)), "gg_last_profile")
         return p.as_dict()
 
+    def probe(self, stream=None):
+        """Measure the depth class (one BFS) so AUTO can use it."""
+        _check(lib().gg_graph_probe(self.handle, _stream_ptr(stream)), "gg_graph_probe")
+        return self.graph_class()
+
+    def graph_class(self):
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().gg_graph_class(self.handle, ctypes.byref(a), ctypes.byref(b),
+                                    ctypes.byref(c)), "gg_graph_class")
+        return a.value, b.value, c.value
+
     def resolve(self, algo, opts=None) -> Opts:
         out = Opts()
         _check(lib().gg_resolve(self.handle, algo, ctypes.byref(opts or make_opts()),
                                 ctypes.byref(out)), "gg_resolve")
         return out
+
+
+class Batch:
+    """Many independent SSSP/BFS instances run together (gg_batch_* in gg.h).
+
+    ``instances``: list of (algo, HostGraph, source) with algo ALGO_SSSP or
+    ALGO_BFS.  ``run()`` returns one int32 cuda tensor holding every result;
+    instance i's is ``out[off[i]: off[i] + n_i]`` with ``off = offsets()``.
+    """
+
+    def __init__(self, instances, flags=0, stream=None):
+        L = lib()
+        arr = (Instance * len(instances))()
+        keep = []
+        for i, (algo, hg, src) in enumerate(instances):
+            row, prow = _arr(hg.row_ptr)
+            col, pcol = _arr(hg.col if len(hg.col) else np.zeros(1, np.int32))
+            pw = None
+            if hg.w is not None:
+                w, pw = _arr(hg.w if len(hg.w) else np.zeros(1, np.int32))
+                keep.append(w)
+            keep += [row, col]
+            arr[i].algo, arr[i].n, arr[i].m = int(algo), int(hg.n), int(hg.m)
+            arr[i].row_ptr, arr[i].col, arr[i].w = prow, pcol, pw
+            arr[i].source = int(src)
+        h = ctypes.c_void_p()
+        _check(L.gg_batch_create(arr, len(instances), flags, _stream_ptr(stream),
+                                 ctypes.byref(h)), "gg_batch_create")
+        self.handle = h
+        self.count = len(instances)
+        self.sizes = [int(hg.n) for _, hg, _ in instances]
+        info = self.info()
+        self.total_n = info["total_n"]
+
+    def info(self):
+        g, n, m = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().gg_batch_info(self.handle, ctypes.byref(g), ctypes.byref(n),
+                                   ctypes.byref(m)), "gg_batch_info")
+        return {"groups": g.value, "total_n": n.value, "total_m": m.value}
+
+    def group(self, i):
+        v = [ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64(),
+             ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(),
+             ctypes.c_int32()]
+        _check(lib().gg_batch_group(self.handle, i, *[ctypes.byref(x) for x in v]),
+               "gg_batch_group")
+        keys = ("algo", "instances", "n", "m", "mode", "sched", "mapping", "captured_rounds",
+                "last_rounds")
+        return {k: x.value for k, x in zip(keys, v)}
+
+    def offsets(self):
+        off = np.zeros(self.count, np.int64)
+        _check(lib().gg_batch_offsets(self.handle, off.ctypes.data_as(
+            ctypes.POINTER(ctypes.c_int64))), "gg_batch_offsets")
+        return off
+
+    def run(self, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.total_n, dtype=torch.int32, device="cuda")
+        if out.dtype != torch.int32 or not out.is_cuda or out.numel() < self.total_n:
+            raise ValueError("output must be an int32 cuda tensor of >= total_n elements")
+        _check(lib().gg_batch_run(self.handle, ctypes.c_void_p(out.data_ptr()),
+                                  _stream_ptr(stream)), "gg_batch_run")
+        return out
+
+    def free(self):
+        if getattr(self, "handle", None):
+            _check(lib().gg_batch_free(self.handle), "gg_batch_free")
+            self.handle = None
 
 
 def status_str(code: int) -> str:

@@ -1,0 +1,61 @@
+"""Autotuner host logic (no GPU): graph classes, table validation, lookup."""
+import pytest
+
+from paper_1903_01665_amd import gg
+
+V, E, S, A = gg.VERTEX, gg.EDGE, gg.SYNC, gg.ASYNC
+
+
+@pytest.fixture(autouse=True)
+def _restore_table():
+    saved = gg.tune_get()
+    yield
+    gg.tune_set(saved)
+
+
+def test_class_of_workloads():
+    # rmat22: m = 2^26, hub degree 159873 vs average 16 -> skew class 2
+    assert gg.class_of(1 << 26, 1 << 22, 159873, 8) == (13, 2, 0)
+    # grid4096: m ~ 67.8M, max degree 8 vs average ~4 -> skew 0, thousands of levels
+    assert gg.class_of(67763404, 1 << 24, 8, 2622) == (13, 0, 2)
+    # er23: max 26 vs average 8 -> skew 0; 13 levels -> depth 0; unknown depth
+    assert gg.class_of(1 << 26, 1 << 23, 26, 13) == (13, 0, 0)
+    assert gg.class_of(1 << 26, 1 << 23, 26, -1)[2] == -1
+    assert gg.class_of(0, 5, 0, -1) == (0, 0, -1)
+    with pytest.raises(gg.GGError):
+        gg.class_of(10, 0, 1)
+
+
+def test_builtin_rules_without_table():
+    gg.tune_set([])
+    assert gg.tune_lookup(gg.ALGO_SSSP, 13, 2, 0) == (V, A, gg.MAP_BALANCED)
+    assert gg.tune_lookup(gg.ALGO_BFS, 13, 0, 0) == (V, S, gg.MAP_BALANCED)
+    assert gg.tune_lookup(gg.ALGO_BFS, 13, 0, 2) == (V, A, gg.MAP_BALANCED)
+    assert gg.tune_lookup(gg.ALGO_CC, 13, 0, 2)[:2] == (E, S)
+
+
+def test_lookup_takes_the_nearest_entry_of_the_algorithm():
+    mk = lambda algo, sc, kc, dc, mode, sched, mp: dict(algo=algo, size_class=sc, skew_class=kc,
+                                                       depth_class=dc, mode=mode, sched=sched,
+                                                       mapping=mp)
+    gg.tune_set([mk(0, 6, 2, 0, E, S, 0), mk(0, 12, 2, 0, V, A, 3), mk(0, 12, 0, 2, V, S, 1),
+                 mk(1, 10, 0, -1, E, A, 0)])
+    assert gg.tune_lookup(0, 13, 2, 0) == (V, A, 3)      # nearest size, same skew/depth
+    assert gg.tune_lookup(0, 7, 2, 0) == (E, S, 3)       # mapping AUTO -> balanced
+    assert gg.tune_lookup(0, 13, 0, 2) == (V, S, 1)      # skew and depth decide
+    assert gg.tune_lookup(1, 3, 2, 1) == (E, A, 3)       # only entry of the algorithm
+    assert gg.tune_lookup(2, 13, 0, 0)[:2] == (E, S)     # no CC entry: built-in
+    assert len(gg.tune_get()) == 4
+
+
+def test_table_validation():
+    bad = dict(algo=3, size_class=1, skew_class=0, depth_class=0, mode=0, sched=0, mapping=0)
+    with pytest.raises(gg.GGError):
+        gg.tune_set([bad])
+    bad.update(algo=0, mode=2)
+    with pytest.raises(gg.GGError):
+        gg.tune_set([bad])
+    bad.update(mode=0, depth_class=-2)
+    with pytest.raises(gg.GGError):
+        gg.tune_set([bad])
+    assert gg.lib().gg_tune_set(None, 2) == -1
