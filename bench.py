@@ -14,6 +14,17 @@ roofline   for the kernel with the most device time in a profiled repeat of
 cpu_baseline  the oracle (Dijkstra, FIFO BFS, union-find CC) on the same
            graph and first source, single-threaded, timed on this host.
 
+Other configurations (``--config``):
+batched    512 independent SSSP/BFS instances over R-MAT graphs (scale 10..18,
+           edge factor 8..32, weights 1..100), run as one batch (grouped by
+           class, tuned variant, HIP-graph replay) and as 512 plain calls;
+           value = GTEPS of the batch.
+serve      Poisson arrivals (2000 queries/s) of SSSP/BFS queries over 32
+           resident R-MAT graphs (scale 12..22, edge factor 16), a new graph
+           uploaded every 5 s; served (continuous batching) and plain (one
+           query at a time) on the same trace; value = GTEPS served, with
+           p50/p99 latency of both.
+
 Prints one JSON line.  ``--gpus N`` with N > 1 exits: this build uses one GPU.
 """
 from __future__ import annotations
@@ -115,11 +126,19 @@ def main():
     ap.add_argument("--reps", type=int, default=3, help="repeats per variant in the table")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--config", default="single", choices=["single", "batched", "serve"])
+    ap.add_argument("--instances", type=int, default=512, help="batched: instance count")
+    ap.add_argument("--duration", type=float, default=12.0, help="serve: trace seconds")
+    ap.add_argument("--rate", type=float, default=2000.0, help="serve: queries per second")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported",
               file=sys.stderr)
         sys.exit(2)
+    if args.config == "batched":
+        return bench_batched(args)
+    if args.config == "serve":
+        return bench_serve(args)
 
     import torch
 
@@ -302,6 +321,137 @@ def main():
     }
     print(json.dumps(line), flush=True)
     g.free()
+
+
+def common_line(args, metric, value, unit, ms_per_step, config, **extra):
+    line = {"metric": metric, "value": round(value, 4), "unit": unit, "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+            "data": "synthetic", "config": config}
+    line.update(extra)
+    print(json.dumps(line), flush=True)
+
+
+def bench_batched(args):
+    """512 instances: one batch (tuned groups, HIP-graph replay) vs plain calls."""
+    import torch
+
+    from paper_1903_01665_amd import gen, gg
+
+    rng = np.random.default_rng(gen.STREAM["batch"])
+    inst = []
+    t = time.time()
+    for i in range(args.instances):
+        scale = int(rng.integers(10, 19))
+        ef = int(rng.integers(8, 33))
+        hg = gen.rmat(scale, ef << scale, stream=gen.STREAM["batch"] * 100000 + i,
+                      name=f"i{i}-rmat{scale}x{ef}")
+        algo = int(rng.integers(0, 2))
+        src = int(gen.pick_sources(hg, 1, stream=gen.STREAM["batch"] * 100000 + 50000 + i)[0])
+        inst.append((algo, hg, src))
+    total_m = sum(hg.m for _, hg, _ in inst)
+    log(f"[bench] {len(inst)} instances, {total_m} edges, generated in {time.time() - t:.1f}s")
+
+    t = time.time()
+    b = gg.Batch(inst)
+    info = b.info()
+    out = torch.empty(info["total_n"], dtype=torch.int32, device="cuda")
+    b.run(out)  # eager run + capture of every group
+    torch.cuda.synchronize()
+    log(f"[bench] batch built and captured in {time.time() - t:.1f}s: {info}")
+    res = out.cpu().numpy()
+    off = b.offsets()
+    m_trav = 0
+    for i, (algo, hg, s) in enumerate(inst):
+        m_trav += int(hg.degrees()[res[off[i]: off[i] + hg.n] != INF].sum())
+    for _ in range(args.warmup):
+        b.run(out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.run(out)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / args.steps
+    groups = [b.group(i) for i in range(info["groups"])]
+    log(f"[bench] batched: {tb * 1e3:.2f} ms per run -> {m_trav / tb / 1e9:.2f} GTEPS")
+
+    # plain: one graph per instance, one blocking call per instance, AUTO variant
+    graphs = [gg.Graph.from_host(hg) for _, hg, _ in inst]
+    outs = [torch.empty(hg.n, dtype=torch.int32, device="cuda") for _, hg, _ in inst]
+    torch.cuda.synchronize()
+
+    def plain():
+        for (algo, hg, s), g, o in zip(inst, graphs, outs):
+            (g.sssp if algo == 0 else g.bfs)(s, out=o)
+        torch.cuda.synchronize()
+
+    plain()
+    t0 = time.perf_counter()
+    for _ in range(max(1, args.steps // 2)):
+        plain()
+    tp = (time.perf_counter() - t0) / max(1, args.steps // 2)
+    same = all(np.array_equal(outs[i].cpu().numpy(), res[off[i]: off[i] + hg.n])
+               for i, (_, hg, _) in enumerate(inst))
+    log(f"[bench] plain: {tp * 1e3:.2f} ms per pass -> {m_trav / tp / 1e9:.2f} GTEPS; "
+        f"batched == plain: {same}")
+    for g in graphs:
+        g.free()
+    b.free()
+    common_line(args, "GTEPS batched (512 SSSP/BFS instances)", m_trav / tb / 1e9, "GTEPS",
+                tb * 1e3,
+                {"workload": "batched-rmat-10..18", "instances": len(inst), "edges": total_m,
+                 "traversed_edges": m_trav, "groups": groups},
+                plain={"GTEPS": round(m_trav / tp / 1e9, 4), "ms_per_pass": round(tp * 1e3, 3)},
+                speedup_vs_plain=round(tp / tb, 3), results_identical_to_plain=same)
+
+
+def bench_serve(args):
+    """Poisson trace served with continuous batching vs one query at a time."""
+    import torch
+
+    from paper_1903_01665_amd import gen, gg, serve
+
+    n_pool, upload_every = 32, 5.0
+    n_up = int(args.duration // upload_every)
+    scales = serve.pool_scales(n_pool + n_up, 12, 22, gen.STREAM["serve"])
+    t = time.time()
+    hosts = [serve.make_graph(i, sc) for i, sc in enumerate(scales)]
+    log(f"[bench] serve: {len(hosts)} graphs ({sum(h.m for h in hosts)} edges) in "
+        f"{time.time() - t:.1f}s")
+    sources = {i: gen.pick_sources(h, 16, stream=gen.STREAM["serve"] * 1000 + i)
+               for i, h in enumerate(hosts)}
+
+    def graphs_at(ti):
+        k = int(ti // upload_every)  # uploads done by time ti
+        return list(range(min(k, n_up), n_pool + min(k, n_up)))
+
+    trace = serve.make_trace(args.rate, args.duration, graphs_at, sources, gen.STREAM["serve"])
+    # traversed edges per (graph, source)
+    trav = {}
+    for i, h in enumerate(hosts):
+        g = gg.Graph.from_host(h)
+        trav[i] = serve.traversed_edges(g, h, sources[i])
+        g.free()
+    edges = sum(trav[int(gi)][int(s)] for gi, s in zip(trace.graph, trace.source))
+    log(f"[bench] trace: {len(trace.t)} queries over {args.duration}s, {edges} traversed edges")
+    lat_s, st, wall_s = serve.run_served(hosts, trace, slots=32, upload_every=upload_every,
+                                         n_pool=n_pool)
+    ok = int((st == 0).sum())
+    log(f"[bench] served: wall {wall_s:.2f}s p50 {serve.percentile(lat_s, 50) * 1e3:.2f} ms "
+        f"p99 {serve.percentile(lat_s, 99) * 1e3:.2f} ms ({ok}/{len(st)} ok)")
+    lat_p, wall_p = serve.run_plain(hosts, trace, n_pool=n_pool, upload_every=upload_every)
+    log(f"[bench] plain: wall {wall_p:.2f}s p50 {serve.percentile(lat_p, 50) * 1e3:.2f} ms "
+        f"p99 {serve.percentile(lat_p, 99) * 1e3:.2f} ms")
+    q = lambda x, p: round(serve.percentile(x, p) * 1e3, 3)
+    common_line(args, "GTEPS served (Poisson SSSP/BFS queries)", edges / wall_s / 1e9, "GTEPS",
+                wall_s * 1e3 / max(1, len(trace.t)),
+                {"workload": "serve-rmat-12..22", "graphs": n_pool, "uploads": n_up,
+                 "rate_qps": args.rate, "duration_s": args.duration, "queries": len(trace.t),
+                 "traversed_edges": edges, "slots": 32},
+                latency_ms={"served": {"p50": q(lat_s, 50), "p99": q(lat_s, 99)},
+                            "plain": {"p50": q(lat_p, 50), "p99": q(lat_p, 99)}},
+                plain={"GTEPS": round(edges / wall_p / 1e9, 4), "wall_s": round(wall_p, 3)},
+                served_ok=ok, served_wall_s=round(wall_s, 3))
 
 
 if __name__ == "__main__":

@@ -303,6 +303,56 @@ int gg_batch_group(gg_batch b, int32_t g, int32_t* algo, int32_t* instances, int
 /* Free a batch (waits for its work). */
 int gg_batch_free(gg_batch b);
 
+/* ---- Serving: SSSP/BFS queries admitted as they arrive (continuous
+ * batching).  A server holds resident graphs (added after gg_graph_upload;
+ * the server owns them from then on), a FIFO of submitted queries and a set
+ * of slots.  gg_server_poll admits queued queries while a slot is free and
+ * the per-query state of all admitted queries (a workspace: frontier flags
+ * and round stamps, ~6 bytes per vertex) fits the memory budget, enqueues
+ * each admitted query's rounds on the slot's own stream, and advances every
+ * query in flight without blocking, so their kernels overlap on the device.
+ * A query's result is bit-identical to the same call made alone.  The poll
+ * loop is single-threaded; submit/add/remove may come from other threads. */
+typedef struct gg_server_s* gg_server;
+
+typedef struct {
+    int64_t id;           /* from gg_server_submit */
+    int32_t status;       /* GG_OK or the traversal's error */
+    int32_t rounds;       /* rounds the traversal took */
+    double t_submit, t_admit, t_done; /* seconds on the server's steady clock */
+} gg_query_result;
+
+/* slots: queries in flight at most (1..1024); mem_budget_bytes: bound on the
+ * per-query state of queries in flight (0 = no bound). */
+int gg_server_create(int32_t slots, int64_t mem_budget_bytes, gg_server* out);
+
+/* Hand a graph to the server; *graph_id names it in submissions. */
+int gg_server_add_graph(gg_server s, gg_graph g, int32_t* graph_id);
+
+/* Retire a graph: later submissions to it fail; queries already queued or
+ * in flight finish.  Its memory is released by gg_server_free (releasing
+ * device memory while other queries run would synchronise the device). */
+int gg_server_remove_graph(gg_server s, int32_t graph_id);
+
+/* Queue a query.  out_dev: caller-owned device int32[n] of that graph,
+ * written by the traversal (readable once the query is reported done).
+ * GG_EINVAL for an unknown or retiring graph, a bad algorithm or source. */
+int gg_server_submit(gg_server s, int32_t graph_id, int32_t algo, int32_t source,
+                     int32_t* out_dev, int64_t* query_id);
+
+/* Admit and advance; copies up to `cap` newly finished queries to results
+ * and their count to *n_done.  Never blocks on the device. */
+int gg_server_poll(gg_server s, gg_query_result* results, int32_t cap, int32_t* n_done);
+
+/* Queued, in-flight and retained-state counts, memory of in-flight state. */
+int gg_server_state(gg_server s, int32_t* queued, int32_t* in_flight, int64_t* state_bytes);
+
+/* Seconds on the server's clock (the clock of gg_query_result). */
+double gg_server_now(gg_server s);
+
+/* Wait for all work, free the graphs the server owns and the server. */
+int gg_server_free(gg_server s);
+
 /* Human-readable status name. */
 const char* gg_status_str(int32_t status);
 

@@ -296,50 +296,80 @@ int reserve_stamps(gg_ws ws, hipStream_t s, long long span, hipError_t* err) {
     return base;
 }
 
-// Eager driver: enqueue rounds r0, r0+1, ... in doubling batches until the
-// round kernel reports the end through the workspace's pinned word (the
-// traversal tag `tag` is what that kernel stores).  Returns GG_OK, GG_EITER
-// or GG_ETIMEOUT; *r_end = rounds enqueued.
-int plan_drive(Plan& p, long long r0, int stamp_base, int tag, long long* r_end) {
-    gg_graph g = p.g;
-    gg_ws ws = p.ws;
-    hipStream_t s = p.s;
-    const long long max_rounds = (long long)g->n + 2;
-    const auto t0 = std::chrono::steady_clock::now();
-    int status = GG_OK;
-    long long r = r0;
-    int batch = 2, k = 0;
-    bool pending = false;
-    auto finished = [&] { return __atomic_load_n(ws->h_done, __ATOMIC_ACQUIRE) == tag; };
-    for (;;) {
-        const long long stop = std::min(r + batch, max_rounds);
-        for (; r < stop; ++r) HIPCHK(g, plan_round(p, (int)r, stamp_base + (int)r));
-        const int slot = k & 1;
-        HIPCHK(g, hipEventRecord(ws->ev[slot], s));
-        if (pending) {
-            // the previous batch has run once its event completes; the end
-            // may have been reported by a kernel of it or of the current one
-            HIPCHK(g, hipEventSynchronize(ws->ev[slot ^ 1]));
-            if (finished()) break;
-        }
-        pending = true;
-        ++k;
-        if (r >= max_rounds) {
-            HIPCHK(g, hipEventSynchronize(ws->ev[slot]));
-            if (!finished()) status = GG_EITER;
-            break;
-        }
-        const long long ms = std::chrono::duration_cast<std::chrono::milliseconds>(
-                                 std::chrono::steady_clock::now() - t0).count();
-        if (ms > p.o.time_limit_ms) {
-            HIPCHK(g, hipEventSynchronize(ws->ev[slot]));
-            if (!finished()) status = GG_ETIMEOUT;
-            break;
-        }
-        batch = std::min(batch * 2, kMaxBatch);
+// Eager driver as a resumable state machine.  Batches of rounds double in
+// size up to kMaxBatch; at most two batches are outstanding.  When the older
+// one has completed, the pinned word tells whether some round kernel found
+// the end (it stores the traversal's tag); if not, the next batch goes out.
+// Rounds enqueued past the end return at their first instruction.
+int drive_start(Drive& d, long long r0, int stamp_base, int tag) {
+    d.r = r0;
+    d.batch = 2;
+    d.k = 0;
+    d.stamp_base = stamp_base;
+    d.tag = tag;
+    d.max_rounds = (long long)d.p.g->n + 2;
+    d.t0 = std::chrono::steady_clock::now();
+    d.status = GG_OK;
+    d.finished = false;
+    // two batches in flight from the start
+    for (int i = 0; i < 2; ++i) {
+        int rc = drive_enqueue(d);
+        if (rc != GG_OK) return rc;
     }
-    *r_end = r;
-    return status;
+    return GG_OK;
+}
+
+int drive_enqueue(Drive& d) {
+    Plan& p = d.p;
+    const long long stop = std::min(d.r + d.batch, d.max_rounds);
+    for (; d.r < stop; ++d.r) HIPCHK(p.g, plan_round(p, (int)d.r, d.stamp_base + (int)d.r));
+    HIPCHK(p.g, hipEventRecord(p.ws->ev[d.k & 1], p.s));
+    ++d.k;
+    d.batch = std::min(d.batch * 2, kMaxBatch);
+    return GG_OK;
+}
+
+int drive_step(Drive& d, bool block) {
+    if (d.finished) return 1;
+    Plan& p = d.p;
+    gg_ws ws = p.ws;
+    hipEvent_t older = ws->ev[d.k & 1];  // batch k-2 (k-1 is the newer one)
+    if (block) {
+        HIPCHK(p.g, hipEventSynchronize(older));
+    } else {
+        const hipError_t q = hipEventQuery(older);
+        if (q == hipErrorNotReady) return 0;
+        HIPCHK(p.g, q);
+    }
+    auto reported = [&] { return __atomic_load_n(ws->h_done, __ATOMIC_ACQUIRE) == d.tag; };
+    if (reported()) {
+        d.finished = true;
+        return 1;
+    }
+    const long long ms = std::chrono::duration_cast<std::chrono::milliseconds>(
+                             std::chrono::steady_clock::now() - d.t0).count();
+    if (d.r >= d.max_rounds || ms > p.o.time_limit_ms) {
+        HIPCHK(p.g, hipEventSynchronize(ws->ev[(d.k + 1) & 1]));
+        if (!reported()) d.status = d.r >= d.max_rounds ? GG_EITER : GG_ETIMEOUT;
+        d.finished = true;
+        return 1;
+    }
+    int rc = drive_enqueue(d);
+    return rc == GG_OK ? 0 : rc;
+}
+
+// Blocking form: run the state machine to the end.
+int plan_drive(Plan& p, long long r0, int stamp_base, int tag, long long* r_end) {
+    Drive d;
+    d.p = p;
+    int rc = drive_start(d, r0, stamp_base, tag);
+    while (rc == GG_OK) {
+        rc = drive_step(d, true);
+        if (rc == 1) break;
+    }
+    *r_end = d.r;
+    if (rc < 0) return rc;
+    return d.status;
 }
 
 void record_last(Plan& p, int status, long long rounds) {

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <mutex>
 #include <vector>
 
@@ -135,7 +136,24 @@ hipError_t plan_init(Plan& p);
 hipError_t plan_round(Plan& p, int r, int stamp);
 // Reserve `span` round stamps on a workspace; returns the first.
 int reserve_stamps(gg_ws ws, hipStream_t s, long long span, hipError_t* err);
-// Eager driver from round r0 until the end is reported (see gg_api.hip).
+// Resumable eager driver of one traversal (see gg_api.hip).
+struct Drive {
+    Plan p;
+    long long r = 0, max_rounds = 0;
+    int batch = 2, k = 0;
+    int stamp_base = 0, tag = 0;
+    std::chrono::steady_clock::time_point t0;
+    int status = GG_OK;
+    bool finished = false;
+};
+// Enqueue the first two batches of rounds from round r0.
+int drive_start(Drive& d, long long r0, int stamp_base, int tag);
+// Enqueue the next batch.
+int drive_enqueue(Drive& d);
+// Advance: 1 = finished (d.status holds GG_OK, GG_EITER or GG_ETIMEOUT),
+// 0 = still running (non-blocking form only), < 0 = HIP failure.
+int drive_step(Drive& d, bool block);
+// Blocking form: rounds from r0 until the end is reported.
 int plan_drive(Plan& p, long long r0, int stamp_base, int tag, long long* r_end);
 // Record the variant, status and round count of a finished call.
 void record_last(Plan& p, int status, long long rounds);

@@ -35,7 +35,10 @@ EXPORTS = ["gg_graph_upload", "gg_graph_free", "gg_graph_info", "gg_graph_error"
            "gg_cc_ex", "gg_last_stats", "gg_last_profile", "gg_resolve", "gg_status_str",
            "gg_version", "gg_tune_set", "gg_tune_get", "gg_class_of", "gg_tune_lookup",
            "gg_graph_probe", "gg_graph_class", "gg_batch_create", "gg_batch_run",
-           "gg_batch_offsets", "gg_batch_info", "gg_batch_group", "gg_batch_free"]
+           "gg_batch_offsets", "gg_batch_info", "gg_batch_group", "gg_batch_free",
+           "gg_server_create", "gg_server_add_graph", "gg_server_remove_graph",
+           "gg_server_submit", "gg_server_poll", "gg_server_state", "gg_server_now",
+           "gg_server_free"]
 BATCH_NO_GRAPH, BATCH_ONE_GROUP = 1, 2
 
 TUNE_TABLE = os.path.join(_HERE, "tune_table.json")
@@ -77,6 +80,12 @@ class Instance(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("n", ctypes.c_int32), ("m", ctypes.c_int64),
                 ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("w", ctypes.c_void_p),
                 ("source", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class QueryResult(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("status", ctypes.c_int32), ("rounds", ctypes.c_int32),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
 
 
 class KindProfile(ctypes.Structure):
@@ -136,11 +145,20 @@ def lib():
     L.gg_batch_group.argtypes = [vp, i32, P(i32), P(i32), P(i64), P(i64), P(i32), P(i32),
                                  P(i32), P(i32), P(i32)]
     L.gg_batch_free.argtypes = [vp]
+    L.gg_server_create.argtypes = [i32, i64, P(vp)]
+    L.gg_server_add_graph.argtypes = [vp, vp, P(i32)]
+    L.gg_server_remove_graph.argtypes = [vp, i32]
+    L.gg_server_submit.argtypes = [vp, i32, i32, i32, vp, P(i64)]
+    L.gg_server_poll.argtypes = [vp, P(QueryResult), i32, P(i32)]
+    L.gg_server_state.argtypes = [vp, P(i32), P(i32), P(i64)]
+    L.gg_server_now.argtypes = [vp]
+    L.gg_server_now.restype = ctypes.c_double
+    L.gg_server_free.argtypes = [vp]
     L.gg_status_str.argtypes = [i32]
     L.gg_status_str.restype = ctypes.c_char_p
     L.gg_version.argtypes = []
     for f in EXPORTS:
-        if f != "gg_status_str":
+        if f not in ("gg_status_str", "gg_server_now"):
             getattr(L, f).restype = ctypes.c_int32
     if L.gg_version() != 1:
         raise RuntimeError("libgg.so version mismatch")
@@ -412,6 +430,63 @@ class Batch:
     def free(self):
         if getattr(self, "handle", None):
             _check(lib().gg_batch_free(self.handle), "gg_batch_free")
+            self.handle = None
+
+
+class Server:
+    """Continuous-batching query server (gg_server_* in gg.h).
+
+    ``add_graph`` hands an uploaded :class:`Graph` to the server (which owns
+    it from then on); ``submit`` queues a query whose result goes to a
+    caller-owned int32 cuda tensor; ``poll`` admits, advances and returns the
+    queries that finished since the last poll.
+    """
+
+    def __init__(self, slots=16, mem_budget_bytes=0):
+        h = ctypes.c_void_p()
+        _check(lib().gg_server_create(slots, mem_budget_bytes, ctypes.byref(h)),
+               "gg_server_create")
+        self.handle = h
+        self._res = (QueryResult * 4096)()
+        self._graphs = {}
+
+    def add_graph(self, graph: Graph) -> int:
+        gid = ctypes.c_int32()
+        _check(lib().gg_server_add_graph(self.handle, graph.handle, ctypes.byref(gid)),
+               "gg_server_add_graph")
+        graph.handle = None  # owned by the server now
+        self._graphs[gid.value] = graph.n
+        return gid.value
+
+    def remove_graph(self, gid: int):
+        _check(lib().gg_server_remove_graph(self.handle, gid), "gg_server_remove_graph")
+
+    def submit(self, gid, algo, source, out) -> int:
+        qid = ctypes.c_int64()
+        _check(lib().gg_server_submit(self.handle, gid, algo, int(source),
+                                      ctypes.c_void_p(out.data_ptr()), ctypes.byref(qid)),
+               "gg_server_submit")
+        return qid.value
+
+    def poll(self):
+        n = ctypes.c_int32()
+        _check(lib().gg_server_poll(self.handle, self._res, len(self._res), ctypes.byref(n)),
+               "gg_server_poll")
+        return [(r.id, r.status, r.rounds, r.t_submit, r.t_admit, r.t_done)
+                for r in self._res[: n.value]]
+
+    def state(self):
+        q, f, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        _check(lib().gg_server_state(self.handle, ctypes.byref(q), ctypes.byref(f),
+                                     ctypes.byref(b)), "gg_server_state")
+        return {"queued": q.value, "in_flight": f.value, "state_bytes": b.value}
+
+    def now(self) -> float:
+        return lib().gg_server_now(self.handle)
+
+    def free(self):
+        if getattr(self, "handle", None):
+            _check(lib().gg_server_free(self.handle), "gg_server_free")
             self.handle = None
 
 

@@ -1,0 +1,116 @@
+"""Serving: every query's result is the same alone and in the mix (bit-exact),
+admission respects the slot count and the memory budget."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1903_01665_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gg():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1903_01665_amd import gg as _gg
+    return _gg
+
+
+def test_results_same_alone_and_in_the_mix(gg):
+    import torch
+    hosts = [gen.rmat(s, 16 << s, stream=900 + s, name=f"rmat{s}") for s in (9, 11, 13)]
+    hosts.append(gen.grid(48, 48, 40, 8, 1, 1000, stream=950, name="grid48"))
+    rng = np.random.default_rng(3)
+    queries = []
+    for i in range(120):
+        gi = int(rng.integers(0, len(hosts)))
+        src = int(gen.pick_sources(hosts[gi], 1, stream=1000 + i)[0])
+        queries.append((gi, int(rng.integers(0, 2)), src))
+    # alone: the oracle and the single-query call
+    want = []
+    for gi, algo, src in queries:
+        h = hosts[gi]
+        want.append(oracle.sssp(h.n, h.row_ptr, h.col, h.w, src) if algo == 0
+                    else oracle.bfs(h.n, h.row_ptr, h.col, src))
+    srv = gg.Server(slots=12, mem_budget_bytes=0)
+    try:
+        gids = [srv.add_graph(gg.Graph.from_host(h)) for h in hosts]
+        outs = [torch.full((hosts[gi].n,), -1, dtype=torch.int32, device="cuda")
+                for gi, _, _ in queries]
+        ids = {}
+        # submit in waves while earlier queries are still running
+        k = 0
+        finished = {}
+        peak = 0
+        while len(finished) < len(queries):
+            for _ in range(7):
+                if k < len(queries):
+                    gi, algo, src = queries[k]
+                    ids[srv.submit(gids[gi], algo, src, outs[k])] = k
+                    k += 1
+            for qid, st, rounds, ts, ta, td in srv.poll():
+                assert st == 0
+                assert ts <= ta <= td
+                finished[ids[qid]] = rounds
+            peak = max(peak, srv.state()["in_flight"])
+        assert peak <= 12
+        torch.cuda.synchronize()
+        say(f"[gpu] serve mix: {len(queries)} queries, peak in flight {peak}")
+        for i, o in enumerate(outs):
+            np.testing.assert_array_equal(o.cpu().numpy(), want[i], err_msg=str(queries[i]))
+    finally:
+        srv.free()
+
+
+def test_memory_budget_limits_admission(gg):
+    import torch
+    h = gen.rmat(12, 16 << 12, stream=77, name="rmat12")
+    srcs = gen.pick_sources(h, 20, stream=78)
+    want = [oracle.bfs(h.n, h.row_ptr, h.col, int(s)) for s in srcs]
+    # a budget of about two workspaces of this graph: at most 2 in flight
+    srv = gg.Server(slots=16, mem_budget_bytes=2 * (6 * h.n + 500_000))
+    try:
+        gid = srv.add_graph(gg.Graph.from_host(h))
+        outs = [torch.empty(h.n, dtype=torch.int32, device="cuda") for _ in srcs]
+        ids = {srv.submit(gid, 1, int(s), o): i for i, (s, o) in enumerate(zip(srcs, outs))}
+        done, peak = 0, 0
+        while done < len(srcs):
+            res = srv.poll()
+            st = srv.state()
+            peak = max(peak, st["in_flight"])
+            done += len(res)
+        assert 1 <= peak <= 2
+        torch.cuda.synchronize()
+        for i, o in enumerate(outs):
+            np.testing.assert_array_equal(o.cpu().numpy(), want[i])
+    finally:
+        srv.free()
+
+
+def test_retired_graph_rejects_new_queries(gg):
+    import torch
+    h = gen.uniform(500, 3000, stream=5)
+    srv = gg.Server(slots=4)
+    try:
+        gid = srv.add_graph(gg.Graph.from_host(h))
+        out = torch.empty(h.n, dtype=torch.int32, device="cuda")
+        q = srv.submit(gid, 0, 0, out)
+        srv.remove_graph(gid)
+        with pytest.raises(gg.GGError):
+            srv.submit(gid, 0, 0, out)
+        got = []
+        while not got:
+            got = srv.poll()
+        assert got[0][0] == q and got[0][1] == 0
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(out.cpu().numpy(), oracle.sssp(h.n, h.row_ptr, h.col, h.w, 0))
+    finally:
+        srv.free()
