@@ -61,8 +61,14 @@ typedef enum {
 typedef enum { GG_VERTEX = 0, GG_EDGE = 1, GG_MODE_AUTO = 2 } gg_mode;
 
 /* Schedule: synchronous topology-driven sweeps with a changed flag
- * (Algorithms 1-3), or asynchronous data-driven worklist rounds (Sec. 3.3). */
-typedef enum { GG_SYNC = 0, GG_ASYNC = 1, GG_SCHED_AUTO = 2 } gg_sched;
+ * (Algorithms 1-3), or asynchronous data-driven worklist rounds (Sec. 3.3).
+ * GG_NEARFAR (SSSP, vertex-based, balanced mapping only) orders the worklist
+ * by distance in buckets of width delta -- the Delta-stepping idea the paper
+ * credits for the CPU worklist's win on road networks (Sec. 4.2-4.3): a round
+ * serves only frontier vertices below the current bound and keeps the rest;
+ * the bound grows by delta once a round pushes nothing below it.  The result
+ * is the same as every other schedule. */
+typedef enum { GG_SYNC = 0, GG_ASYNC = 1, GG_SCHED_AUTO = 2, GG_NEARFAR = 3 } gg_sched;
 
 /* How vertex-based work is mapped to lanes.  THREAD: one lane walks a whole
  * row (the paper's generated GPU code); WAVE: one wavefront per vertex;
@@ -91,7 +97,8 @@ typedef struct {
     int32_t heavy_threshold; /* 0 = default; rows longer than this are chunked (BALANCED) */
     int32_t time_limit_ms; /* 0 = default (60000); no round is launched after it (GG_ETIMEOUT) */
     int32_t flags;         /* GG_OPT_* bits */
-    int32_t reserved[4];
+    int32_t delta;         /* GG_NEARFAR bucket width; 0 = default (from the average weight) */
+    int32_t reserved[3];
 } gg_opts;
 
 /* gg_opts.flags */
@@ -217,7 +224,7 @@ int gg_resolve(gg_graph g, int32_t algo, const gg_opts* in, gg_opts* out);
 typedef struct {
     int32_t algo, size_class, skew_class, depth_class; /* depth -1 = any */
     int32_t mode, sched, mapping;
-    int32_t reserved;
+    int32_t delta_mult; /* GG_NEARFAR: bucket width in mean edge weights (0 = 4) */
 } gg_tune_entry;
 
 /* Replace the process-wide tuning table (count 0 clears it).  The entries
@@ -236,7 +243,7 @@ int gg_class_of(int64_t m, int32_t n, int32_t max_out_degree, int32_t levels,
 /* Variant the table (else the built-in rules) picks for an algorithm and a
  * class, as gg_resolve would.  Outputs may not be NULL. */
 int gg_tune_lookup(int32_t algo, int32_t size_class, int32_t skew_class, int32_t depth_class,
-                   int32_t* mode, int32_t* sched, int32_t* mapping);
+                   int32_t* mode, int32_t* sched, int32_t* mapping, int32_t* delta_mult);
 
 /* Measure the graph's depth class (one BFS on `stream`, waited for) and keep
  * it on the handle; later AUTO resolutions use it. */

@@ -144,14 +144,18 @@ void resolve(gg_graph g, int algo, const gg_opts* in, gg_opts* out) {
     gg_opts o{};
     if (in) o = *in;
     const bool auto_mode = o.mode != GG_VERTEX && o.mode != GG_EDGE;
-    const bool auto_sched = o.sched != GG_SYNC && o.sched != GG_ASYNC;
+    const bool auto_sched = o.sched != GG_SYNC && o.sched != GG_ASYNC && o.sched != GG_NEARFAR;
     const bool auto_map = o.mapping < GG_MAP_THREAD || o.mapping > GG_MAP_BALANCED;
-    int32_t sc = 0, kc = 0, dc = -1, tm = GG_VERTEX, ts = GG_ASYNC, tp = GG_MAP_BALANCED;
+    int32_t sc = 0, kc = 0, dc = -1, tm = GG_VERTEX, ts = GG_ASYNC, tp = GG_MAP_BALANCED, td = 0;
     gg_class_of(g->m, g->n, g->max_deg, g->levels, &sc, &kc, &dc);
-    gg_tune_lookup(algo, sc, kc, dc, &tm, &ts, &tp);
+    gg_tune_lookup(algo, sc, kc, dc, &tm, &ts, &tp, &td);
     if (auto_mode) o.mode = tm;
     if (auto_sched) o.sched = ts;
     if (auto_map) o.mapping = tp;
+    // bucket width of the near-far schedule: explicit, else the table's
+    // multiple of the mean weight, else 4 mean weights
+    if (o.sched == GG_NEARFAR && o.delta <= 0)
+        o.delta = std::max(1, (int)((td > 0 ? td : 4) * g->avg_w));
     // without the both-directions CSR only the edge sweep can run CC
     if (algo == GG_ALGO_CC && !g->has_sym) {
         if (auto_mode) o.mode = GG_EDGE;
@@ -187,12 +191,16 @@ int plan_make(gg_graph g, gg_ws ws, int algo, int source, const int* sources_dev
     if (algo == GG_ALGO_CC && !g->has_sym && (o.mode != GG_EDGE || o.sched != GG_SYNC))
         return GG_ENOTSUP;
     if (o.block_threads != kBlock) return GG_ENOTSUP;
+    const bool nearfar = o.sched == GG_NEARFAR;
+    if (nearfar && (algo != GG_ALGO_SSSP || o.mode != GG_VERTEX || o.mapping != GG_MAP_BALANCED))
+        return GG_ENOTSUP;
+    if (o.delta < 0) return GG_EINVAL;
     const Dev& dv = device();
     const int cap_blocks = o.max_blocks > 0 ? std::min(o.max_blocks, dv.max_blocks) : dv.max_blocks;
     auto grid = [&](long long units) {
         return (int)std::max(1LL, std::min<long long>(units, cap_blocks));
     };
-    p.async = o.sched == GG_ASYNC;
+    p.async = o.sched == GG_ASYNC || nearfar;
     p.edge = o.mode == GG_EDGE;
     p.cc = algo == GG_ALGO_CC;
     Round& R = p.R;
@@ -205,6 +213,9 @@ int plan_make(gg_graph g, gg_ws ws, int algo, int source, const int* sources_dev
     R.mapping = o.mapping;
     R.jump = p.cc && !(o.flags & GG_OPT_CC_NO_JUMP);
     R.host_done = ws->h_done;
+    // default bucket width: a few mean weights (one bucket then spans paths
+    // of several light edges)
+    R.delta = nearfar ? std::max(1, o.delta) : 0;
 
     const int wpb = kBlock / 64;
     const long long n = g->n;
@@ -301,13 +312,24 @@ int reserve_stamps(gg_ws ws, hipStream_t s, long long span, hipError_t* err) {
 // one has completed, the pinned word tells whether some round kernel found
 // the end (it stores the traversal's tag); if not, the next batch goes out.
 // Rounds enqueued past the end return at their first instruction.
+// Bound on the rounds of a traversal.  Every round of a sweep or worklist
+// schedule that changes something fixes at least one more vertex, so n + 2
+// rounds suffice; a near-far round may only raise the bound, which happens
+// at most (largest possible distance) / delta times.
+long long max_rounds(const Plan& p) {
+    long long r = (long long)p.g->n + 2;
+    if (p.R.delta > 0)
+        r += std::min<long long>(((long long)p.g->n * p.g->max_w) / p.R.delta + 1, 1LL << 29);
+    return std::min(r, 1LL << 30);
+}
+
 int drive_start(Drive& d, long long r0, int stamp_base, int tag) {
     d.r = r0;
     d.batch = 2;
     d.k = 0;
     d.stamp_base = stamp_base;
     d.tag = tag;
-    d.max_rounds = (long long)d.p.g->n + 2;
+    d.max_rounds = max_rounds(d.p);
     d.t0 = std::chrono::steady_clock::now();
     d.status = GG_OK;
     d.finished = false;
@@ -408,8 +430,8 @@ int run_multi(gg_graph g, gg_ws ws, int algo, int source, const int* sources_dev
     long long r_end = 0;
     const int status = plan_drive(p, 0, base, base, &r_end);
     if (status != GG_OK && status != GG_EITER && status != GG_ETIMEOUT) return status;
-    // stamps of later traversals start after the rounds used here
-    ws->epoch = base + (int)std::min<long long>(r_end + 1, (long long)g->n + 3);
+    // stamps of later traversals start after every round used here
+    ws->epoch = (int)std::min<long long>((long long)base + r_end + 1, 1LL << 30);
     HIPCHK(g, hipEventRecord(ws->finished, s));
     record_last(p, status, r_end);
     return status;
@@ -460,7 +482,8 @@ int gg_graph_upload(int32_t n, int64_t m, const int32_t* row_ptr, const int32_t*
         std::memcpy(hrow.data(), row_ptr, sizeof(int) * ((size_t)n + 1));
     }
     if (hrow[0] != 0 || hrow[n] != m) return GG_EINVAL;
-    int max_deg = 0, argmax_deg = 0;
+    int max_deg = 0, argmax_deg = 0, max_w = 0;
+    double avg_w = 0;
     for (int v = 0; v < n; ++v) {
         if (hrow[v + 1] < hrow[v]) return GG_EINVAL;
         if (hrow[v + 1] - hrow[v] > max_deg) {
@@ -471,9 +494,15 @@ int gg_graph_upload(int32_t n, int64_t m, const int32_t* row_ptr, const int32_t*
     if (!on_dev) {
         for (long long e = 0; e < m; ++e)
             if (col[e] < 0 || col[e] >= n) return GG_EINVAL;
-        if (w)
-            for (long long e = 0; e < m; ++e)
+        if (w) {
+            double sum = 0;
+            for (long long e = 0; e < m; ++e) {
                 if (w[e] < 0) return GG_EINVAL;
+                sum += w[e];
+                max_w = std::max(max_w, (int)w[e]);
+            }
+            avg_w = m ? sum / (double)m : 0.0;
+        }
     }
     gg_graph g = new (std::nothrow) gg_graph_s();
     if (!g) return GG_ENOMEM;
@@ -481,6 +510,8 @@ int gg_graph_upload(int32_t n, int64_t m, const int32_t* row_ptr, const int32_t*
     g->m = m;
     g->max_deg = max_deg;
     g->argmax_deg = argmax_deg;
+    g->avg_w = avg_w;
+    g->max_w = max_w;
     g->weighted = w != nullptr;
     const hipMemcpyKind kind = on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     auto bail = [&](int code) {
@@ -516,8 +547,13 @@ int gg_graph_upload(int32_t n, int64_t m, const int32_t* row_ptr, const int32_t*
         if (w) {
             if (m && hipMemcpy(hc.data(), g->w, sizeof(int) * m, hipMemcpyDeviceToHost) != hipSuccess)
                 return bail(GG_EHIP);
-            for (long long i = 0; i < m; ++i)
+            double sum = 0;
+            for (long long i = 0; i < m; ++i) {
                 if (hc[i] < 0) return bail(GG_EINVAL);
+                sum += hc[i];
+                g->max_w = std::max(g->max_w, (int)hc[i]);
+            }
+            g->avg_w = m ? sum / (double)m : 0.0;
         }
     }
     std::vector<int2> hch = build_chunks(hrow, n, g->heavy, g->chunk);

@@ -253,7 +253,7 @@ int gg_batch_run(gg_batch b, int32_t* out_dev, void* stream) {
         p.R.epoch = base;
         long long r_end = 0;
         rc = plan_drive(p, G.r_cap, base, base, &r_end);
-        p.ws->epoch = base + (int)std::min<long long>(r_end + 1, (long long)G.n + 3);
+        p.ws->epoch = (int)std::min<long long>((long long)base + r_end + 1, 1LL << 30);
         record_last(p, rc, r_end);
         if (rc != GG_OK) status = rc;
         G.last_rounds = (int)r_end;

@@ -27,7 +27,9 @@ struct Ctl {
     int done;        // set by the first round kernel that finds nothing left to do
     int iters;       // rounds that ran, set together with done
     int changed[4];  // [r % 3]: round r updated or pushed something
-    int pad[10];
+    int bound[4];    // near-far schedule: [r % 3] = distance bound of round r
+    int near_[4];    // near-far schedule: [r % 3] = round r pushed below its bound
+    int pad[2];
 };
 
 // Per-block counters, summed on the host after a traversal; one array of
@@ -83,6 +85,7 @@ struct Round {
     int* host_done; // pinned host word: set to `epoch` by the kernel that finds the end
     int mapping; // Map
     int jump;    // CC: apply the label[label[v]] shortcut
+    int delta;   // SSSP near-far schedule: bucket width (0 = plain worklist rounds)
 };
 
 // Launch entry points (gg_kernels.hip).  Each returns the hipError_t of the

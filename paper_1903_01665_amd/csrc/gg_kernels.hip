@@ -60,6 +60,7 @@ __device__ __forceinline__ int wave_sum(int x) {
 // Counters of one lane for the current kernel.
 struct Acc {
     int e = 0, v = 0, u = 0, p = 0;
+    int nr = 0;  // near-far: pushed a distance below the round's bound
 };
 
 // Round entry, uniform over the whole grid.  Returns false when the
@@ -84,6 +85,30 @@ __device__ __forceinline__ bool round_begin(const Round& R) {
         ctl->changed[(R.r + 1) % 3] = 0;
     }
     return true;
+}
+
+// Near-far schedule (SSSP, delta > 0): round r serves only the frontier
+// vertices whose distance is below the bound B_r and keeps the others on the
+// frontier.  B_0 = delta; B_r = B_{r-1} while round r-1 pushed some distance
+// below B_{r-1}, else B_{r-1} + delta.  Every block derives B_r from the slots
+// of round r-1, so the choice is the same grid-wide; block 0 records it.
+__device__ __forceinline__ int nearfar_bound(const Round& R) {
+    Ctl* ctl = R.ws.ctl;
+    int b = R.delta;
+    if (R.r > 0) {
+        const int pb = *(volatile int*)&ctl->bound[(R.r - 1) % 3];
+        const bool near = *(volatile int*)&ctl->near_[(R.r - 1) % 3] != 0;
+        b = near ? pb : (pb > kInf - R.delta ? kInf : pb + R.delta);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->bound[R.r % 3] = b;
+        ctl->near_[(R.r + 1) % 3] = 0;
+    }
+    return b;
+}
+
+__device__ __forceinline__ void nearfar_finish(const Round& R, const Acc& acc) {
+    if (__syncthreads_or(acc.nr) && threadIdx.x == 0) R.ws.ctl->near_[R.r % 3] = 1;
 }
 
 // Block-level reduction of the lane counters; one plain update of this
@@ -186,7 +211,7 @@ __device__ __forceinline__ bool relax_edge(const Round& R, const int* col, int e
 template <int A, int U, bool PUSH>
 __device__ __forceinline__ void relax_batch(const Round& R, const int* col, const int (&e)[U],
                                             const int (&sv)[U], const bool (&ok)[U], int nxt,
-                                            Acc& acc) {
+                                            Acc& acc, int bound = kInf) {
     int* val = R.val;
     int t[U], wt[U], cur[U];
 #pragma unroll
@@ -219,6 +244,9 @@ __device__ __forceinline__ void relax_batch(const Round& R, const int* col, cons
                 R.ws.vflag[nxt][t[j]] = 1;
                 R.ws.tflag[nxt][t[j] >> 6] = 1;
                 acc.p++;
+                // near-far: a new distance below the round's bound keeps the
+                // bound where it is for the next round
+                if (A == SSSP && (unsigned)sv[j] + (unsigned)wt[j] < (unsigned)bound) acc.nr = 1;
             } else {
                 acc.u++;
             }
@@ -230,7 +258,7 @@ __device__ __forceinline__ void relax_batch(const Round& R, const int* col, cons
 // whole wavefront kBatch x 64 edges per step.
 template <int A, bool PUSH>
 __device__ __forceinline__ void wave_relax_range(const Round& R, const int* col, int e0, int e1,
-                                                 int sv, int nxt, Acc& acc) {
+                                                 int sv, int nxt, Acc& acc, int bound = kInf) {
     const int lane = threadIdx.x & 63;
     for (int eb = e0; eb < e1; eb += 64 * kBatch) {
         int e[kBatch], s[kBatch];
@@ -241,7 +269,7 @@ __device__ __forceinline__ void wave_relax_range(const Round& R, const int* col,
             ok[j] = e[j] < e1;
             s[j] = sv;
         }
-        relax_batch<A, kBatch, PUSH>(R, col, e, s, ok, nxt, acc);
+        relax_batch<A, kBatch, PUSH>(R, col, e, s, ok, nxt, acc, bound);
     }
 }
 
@@ -251,7 +279,7 @@ __device__ __forceinline__ void wave_relax_range(const Round& R, const int* col,
 // the exclusive prefix of the degrees.
 template <int A, bool PUSH>
 __device__ __forceinline__ void wave_relax_rows(const Round& R, const int* col, int beg, int deg,
-                                                int sv, int nxt, Acc& acc) {
+                                                int sv, int nxt, Acc& acc, int bound = kInf) {
     const int lane = threadIdx.x & 63;
     const int incl = wave_incl_scan(deg);
     const int total = __shfl(incl, 63, 64);
@@ -272,7 +300,7 @@ __device__ __forceinline__ void wave_relax_rows(const Round& R, const int* col, 
             s[j] = __shfl(sv, o, 64);
             ok[j] = k < total;
         }
-        relax_batch<A, kBatch, PUSH>(R, col, e, s, ok, nxt, acc);
+        relax_batch<A, kBatch, PUSH>(R, col, e, s, ok, nxt, acc, bound);
     }
 }
 
@@ -536,6 +564,8 @@ __global__ __launch_bounds__(256) void k_vasync(Round R) {
     const long long tw = (long long)gridDim.x * wpb;
     const long long ntiles = (n + 63) / 64;
     const long long nitems = (ntiles + 63) / 64 * kParts;
+    const bool nf = A == SSSP && MAP == MAP_BALANCED && R.delta > 0;
+    const int bound = nf ? nearfar_bound(R) : kInf;
     Acc acc;
     for (long long it = gw; it < nitems; it += tw) {
         const long long st = it / kParts;
@@ -549,21 +579,28 @@ __global__ __launch_bounds__(256) void k_vasync(Round R) {
             const int b = __ffsll(tm) - 1;
             tm &= tm - 1;
             const int u = (int)((st * 64 + b) * 64 + lane);
-            const bool on = u < n && vf[u] != 0;
+            bool on = u < n && vf[u] != 0;
             if (on) vf[u] = 0;
             int rb = 0, re = 0, sv = 0;
             if (on) {
-                rb = row[u];
-                re = row[u + 1];
                 tail_value<A, true>(R, u, sv, acc);
-                acc.v++;
+                if (nf && sv >= bound) {
+                    // a far vertex waits on the frontier for a later bound
+                    push(R, nxt, u);
+                    acc.u++;
+                    on = false;
+                } else {
+                    rb = row[u];
+                    re = row[u + 1];
+                    acc.v++;
+                }
             }
             if (MAP == MAP_BALANCED) {
                 // heavy rows are served by the chunk kernel of this round
                 const bool hv = on && re - rb > g.heavy;
                 if (hv) R.ws.hstamp[u] = R.stamp;
                 wave_relax_rows<A, true>(R, col, on && !hv ? rb : 0, on && !hv ? re - rb : 0, sv,
-                                         nxt, acc);
+                                         nxt, acc, bound);
             } else if (MAP == MAP_THREAD) {
                 if (on)
                     for (int e = rb; e < re; ++e) {
@@ -593,6 +630,7 @@ __global__ __launch_bounds__(256) void k_vasync(Round R) {
             }
         }
     }
+    if (nf) nearfar_finish(R, acc);
     block_finish(R, acc, R.r % 3, KIND_ROUND);
 }
 
@@ -698,6 +736,8 @@ __global__ __launch_bounds__(256) void k_heavy(Round R) {
     const long long gw = (long long)blockIdx.x * wpb + (threadIdx.x >> 6);
     const long long tw = (long long)gridDim.x * wpb;
     const int lane = threadIdx.x & 63;
+    const bool nf = A == SSSP && R.delta > 0;
+    const int bound = nf ? *(volatile int*)&ctl->bound[R.r % 3] : kInf;
     Acc acc;
     // 64 chunk stamps are checked at once, then the wavefront serves the
     // chunks that match in turn.  The 64 chunks of one check are spread over
@@ -719,9 +759,10 @@ __global__ __launch_bounds__(256) void k_heavy(Round R) {
             const int e0 = __shfl(c.y, o, 64);
             const int e1 = min(e0 + g.chunk, row[u + 1]);
             const int sv = A == BFS ? R.r : R.val[u];
-            wave_relax_range<A, true>(R, col, e0, e1, sv, nxt, acc);
+            wave_relax_range<A, true>(R, col, e0, e1, sv, nxt, acc, bound);
         }
     }
+    if (nf) nearfar_finish(R, acc);
     block_finish(R, acc, R.r % 3, KIND_HEAVY);
 }
 

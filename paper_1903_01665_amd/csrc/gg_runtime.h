@@ -96,6 +96,8 @@ struct gg_graph_s {
     int n_hchunks = 0, n_shchunks = 0;
     long long ms = 0;
     int heavy = gg::kDefaultHeavy, chunk = gg::kChunk;
+    double avg_w = 0;  // mean edge weight (0 when unweighted)
+    int max_w = 0;     // largest edge weight
     gg_ws_s* ws0 = nullptr;
 };
 
@@ -146,6 +148,8 @@ struct Drive {
     int status = GG_OK;
     bool finished = false;
 };
+// Bound on the rounds of a traversal planned by p.
+long long max_rounds(const Plan& p);
 // Enqueue the first two batches of rounds from round r0.
 int drive_start(Drive& d, long long r0, int stamp_base, int tag);
 // Enqueue the next batch.

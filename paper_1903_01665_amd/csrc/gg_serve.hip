@@ -228,6 +228,9 @@ int gg_server_poll(gg_server s, gg_query_result* results, int32_t cap, int32_t* 
             // keep going: the status of this query reports the failure
         }
         record_last(p, status, q->d.r);
+        // stamps of the workspace's next query start after every round used
+        q->ws->epoch = std::max(q->ws->epoch,
+                                (int)std::min<long long>(q->d.stamp_base + q->d.r + 1, 1LL << 30));
         SGraph& G = s->graphs[q->graph_id];
         G.pool.push_back(q->ws);
         s->used -= G.ws_bytes;

@@ -16,16 +16,21 @@ std::vector<gg_tune_entry> g_table;
 bool valid(const gg_tune_entry& e) {
     return e.algo >= 0 && e.algo <= 2 && e.size_class >= 0 && e.size_class < 64 &&
            e.skew_class >= 0 && e.skew_class <= 2 && e.depth_class >= -1 && e.depth_class <= 2 &&
-           (e.mode == GG_VERTEX || e.mode == GG_EDGE) && (e.sched == GG_SYNC || e.sched == GG_ASYNC) &&
-           e.mapping >= GG_MAP_AUTO && e.mapping <= GG_MAP_BALANCED;
+           (e.mode == GG_VERTEX || e.mode == GG_EDGE) &&
+           (e.sched == GG_SYNC || e.sched == GG_ASYNC ||
+            (e.sched == GG_NEARFAR && e.algo == GG_ALGO_SSSP && e.mode == GG_VERTEX)) &&
+           e.mapping >= GG_MAP_AUTO && e.mapping <= GG_MAP_BALANCED && e.delta_mult >= 0 &&
+           e.delta_mult <= 1 << 20;
 }
 
 // Built-in choice, from the measured behaviour of the variants on the
 // synthetic workloads (uniform, R-MAT, grid): asynchronous vertex-based
 // rounds for SSSP everywhere; BFS synchronous on shallow graphs and
 // asynchronous on deep ones; CC by edge sweeps with the shortcut.
-void builtin(int algo, int depth, int32_t* mode, int32_t* sched, int32_t* mapping) {
+void builtin(int algo, int depth, int32_t* mode, int32_t* sched, int32_t* mapping,
+             int32_t* delta_mult) {
     *mapping = GG_MAP_BALANCED;
+    *delta_mult = 0;
     if (algo == GG_ALGO_SSSP) {
         *mode = GG_VERTEX;
         *sched = GG_ASYNC;
@@ -73,8 +78,8 @@ int gg_tune_get(gg_tune_entry* out, int32_t cap) {
 }
 
 int gg_tune_lookup(int32_t algo, int32_t size_class, int32_t skew_class, int32_t depth_class,
-                   int32_t* mode, int32_t* sched, int32_t* mapping) {
-    if (algo < 0 || algo > 2 || !mode || !sched || !mapping) return GG_EINVAL;
+                   int32_t* mode, int32_t* sched, int32_t* mapping, int32_t* delta_mult) {
+    if (algo < 0 || algo > 2 || !mode || !sched || !mapping || !delta_mult) return GG_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
     int best = -1, best_score = 1 << 30;
     for (int i = 0; i < (int)g_table.size(); ++i) {
@@ -89,11 +94,12 @@ int gg_tune_lookup(int32_t algo, int32_t size_class, int32_t skew_class, int32_t
         }
     }
     if (best < 0) {
-        builtin(algo, depth_class, mode, sched, mapping);
+        builtin(algo, depth_class, mode, sched, mapping, delta_mult);
     } else {
         *mode = g_table[best].mode;
         *sched = g_table[best].sched;
         *mapping = g_table[best].mapping == GG_MAP_AUTO ? GG_MAP_BALANCED : g_table[best].mapping;
+        *delta_mult = g_table[best].delta_mult;
     }
     return GG_OK;
 }

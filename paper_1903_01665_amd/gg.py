@@ -18,7 +18,7 @@ INF = 2**31 - 1
 
 # enums of gg.h
 VERTEX, EDGE, MODE_AUTO = 0, 1, 2
-SYNC, ASYNC, SCHED_AUTO = 0, 1, 2
+SYNC, ASYNC, SCHED_AUTO, NEARFAR = 0, 1, 2, 3
 MAP_AUTO, MAP_THREAD, MAP_WAVE, MAP_BALANCED = 0, 1, 2, 3
 ALGO_SSSP, ALGO_BFS, ALGO_CC = 0, 1, 2
 SYMMETRIZE, INPUT_ON_DEVICE, SYMMETRIC = 1, 2, 4
@@ -54,7 +54,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("sched", ctypes.c_int32), ("mapping", ctypes.c_int32),
                 ("block_threads", ctypes.c_int32), ("max_blocks", ctypes.c_int32),
                 ("heavy_threshold", ctypes.c_int32), ("time_limit_ms", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("flags", ctypes.c_int32), ("delta", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class Stats(ctypes.Structure):
@@ -73,7 +74,7 @@ class TuneEntry(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("size_class", ctypes.c_int32),
                 ("skew_class", ctypes.c_int32), ("depth_class", ctypes.c_int32),
                 ("mode", ctypes.c_int32), ("sched", ctypes.c_int32), ("mapping", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("delta_mult", ctypes.c_int32)]
 
 
 class Instance(ctypes.Structure):
@@ -135,7 +136,7 @@ def lib():
     L.gg_tune_set.argtypes = [P(TuneEntry), i32]
     L.gg_tune_get.argtypes = [P(TuneEntry), i32]
     L.gg_class_of.argtypes = [i64, i32, i32, i32, P(i32), P(i32), P(i32)]
-    L.gg_tune_lookup.argtypes = [i32, i32, i32, i32, P(i32), P(i32), P(i32)]
+    L.gg_tune_lookup.argtypes = [i32, i32, i32, i32, P(i32), P(i32), P(i32), P(i32)]
     L.gg_graph_probe.argtypes = [vp, vp]
     L.gg_graph_class.argtypes = [vp, P(i32), P(i32), P(i32)]
     L.gg_batch_create.argtypes = [P(Instance), i32, u32, vp, P(vp)]
@@ -176,6 +177,7 @@ def tune_set(entries):
     for i, e in enumerate(entries):
         for k in ("algo", "size_class", "skew_class", "depth_class", "mode", "sched", "mapping"):
             setattr(arr[i], k, int(e[k]))
+        arr[i].delta_mult = int(e.get("delta_mult", 0))
     _check(lib().gg_tune_set(arr, len(entries)), "gg_tune_set")
 
 
@@ -183,8 +185,7 @@ def tune_get():
     n = lib().gg_tune_get(None, 0)
     arr = (TuneEntry * max(1, n))()
     lib().gg_tune_get(arr, n)
-    return [{k: getattr(arr[i], k) for k, _ in TuneEntry._fields_ if k != "reserved"}
-            for i in range(n)]
+    return [{k: getattr(arr[i], k) for k, _ in TuneEntry._fields_} for i in range(n)]
 
 
 def load_tune_table(path):
@@ -200,11 +201,12 @@ def class_of(m, n, max_out_degree, levels=-1):
     return a.value, b.value, c.value
 
 
-def tune_lookup(algo, size_class, skew_class, depth_class):
-    a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+def tune_lookup(algo, size_class, skew_class, depth_class, with_delta=False):
+    a, b, c, d = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     _check(lib().gg_tune_lookup(algo, size_class, skew_class, depth_class, ctypes.byref(a),
-                                ctypes.byref(b), ctypes.byref(c)), "gg_tune_lookup")
-    return a.value, b.value, c.value
+                                ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)),
+           "gg_tune_lookup")
+    return (a.value, b.value, c.value, d.value) if with_delta else (a.value, b.value, c.value)
 
 
 def _check(rc, what):
@@ -225,10 +227,10 @@ def _arr(a):
 
 
 def make_opts(mode=MODE_AUTO, sched=SCHED_AUTO, mapping=MAP_AUTO, max_blocks=0, flags=0,
-              time_limit_ms=0) -> Opts:
+              time_limit_ms=0, delta=0) -> Opts:
     o = Opts()
     o.mode, o.sched, o.mapping = mode, sched, mapping
-    o.max_blocks, o.flags, o.time_limit_ms = max_blocks, flags, time_limit_ms
+    o.max_blocks, o.flags, o.time_limit_ms, o.delta = max_blocks, flags, time_limit_ms, delta
     return o
 
 

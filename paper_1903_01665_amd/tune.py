@@ -22,10 +22,12 @@ import time
 from . import gen, gg
 
 ALGOS = ("sssp", "bfs", "cc")
-VARIANTS = [(gg.VERTEX, gg.SYNC, gg.MAP_THREAD), (gg.VERTEX, gg.SYNC, gg.MAP_WAVE),
-            (gg.VERTEX, gg.SYNC, gg.MAP_BALANCED), (gg.VERTEX, gg.ASYNC, gg.MAP_THREAD),
-            (gg.VERTEX, gg.ASYNC, gg.MAP_WAVE), (gg.VERTEX, gg.ASYNC, gg.MAP_BALANCED),
-            (gg.EDGE, gg.SYNC, gg.MAP_AUTO), (gg.EDGE, gg.ASYNC, gg.MAP_AUTO)]
+# (mode, schedule, mapping, near-far bucket width in mean weights)
+VARIANTS = [(gg.VERTEX, gg.SYNC, gg.MAP_THREAD, 0), (gg.VERTEX, gg.SYNC, gg.MAP_WAVE, 0),
+            (gg.VERTEX, gg.SYNC, gg.MAP_BALANCED, 0), (gg.VERTEX, gg.ASYNC, gg.MAP_THREAD, 0),
+            (gg.VERTEX, gg.ASYNC, gg.MAP_WAVE, 0), (gg.VERTEX, gg.ASYNC, gg.MAP_BALANCED, 0),
+            (gg.EDGE, gg.SYNC, gg.MAP_AUTO, 0), (gg.EDGE, gg.ASYNC, gg.MAP_AUTO, 0)]
+NEARFAR = [(gg.VERTEX, gg.NEARFAR, gg.MAP_BALANCED, dm) for dm in (1, 2, 4, 8, 16, 64)]
 
 # calibration graphs: the size classes of the workloads, from a seed stream of
 # their own so that no benchmark graph is itself in the set
@@ -45,9 +47,11 @@ def make(kind, p, seed):
                     seed=seed, name=f"grid{p}")
 
 
-def time_variant(g, algo, src, v, reps, out):
+def time_variant(g, algo, src, v, reps, out, avg_w):
     import torch
-    o = gg.make_opts(*v, time_limit_ms=4000)
+    mode, sched, mapping, dm = v
+    o = gg.make_opts(mode, sched, mapping, time_limit_ms=4000,
+                     delta=max(1, int(dm * avg_w)) if sched == gg.NEARFAR else 0)
     ts = []
     for _ in range(reps):
         torch.cuda.synchronize()
@@ -79,10 +83,11 @@ def main(argv=None):
         cls = g.probe()
         src = int(gen.pick_sources(hg, 1, stream=CALIB_STREAM)[0])
         out = torch.empty(hg.n, dtype=torch.int32, device="cuda")
+        avg_w = float(hg.w.mean()) if hg.w is not None and hg.m else 1.0
         for algo in ALGOS:
             times = {}
-            for v in VARIANTS:
-                times[v] = time_variant(g, algo, src, v, args.reps, out)
+            for v in VARIANTS + (NEARFAR if algo == "sssp" else []):
+                times[v] = time_variant(g, algo, src, v, args.reps, out, avg_w)
             best = min(times.values())
             print(f"[tune] {hg.name:8s} class={cls} {algo:4s} best "
                   f"{min(times, key=times.get)} {best * 1e3:.3f} ms", file=sys.stderr, flush=True)
@@ -101,13 +106,14 @@ def main(argv=None):
         score = {v: sum(x) / len(x) for v, x in per_v.items()}
         v = min(score, key=score.get)
         entries.append({"algo": ALGOS.index(algo), "size_class": cls[0], "skew_class": cls[1],
-                        "depth_class": cls[2], "mode": v[0], "sched": v[1], "mapping": v[2]})
+                        "depth_class": cls[2], "mode": v[0], "sched": v[1], "mapping": v[2],
+                        "delta_mult": v[3]})
         detail.append({"algo": algo, "class": list(cls),
-                       "relative_to_best": {f"{m}/{s}/{mp}": round(math.exp(x), 3)
-                                            for (m, s, mp), x in score.items()}})
-    raw = [{"algo": a, "class": list(c), "ms": {f"{m}/{s}/{mp}": (round(t * 1e3, 4)
-                                                               if math.isfinite(t) else None)
-                                                 for (m, s, mp), t in ts.items()}}
+                       "relative_to_best": {f"{m}/{s}/{mp}/{dm}": round(math.exp(x), 3)
+                                            for (m, s, mp, dm), x in score.items()}})
+    raw = [{"algo": a, "class": list(c), "ms": {f"{m}/{s}/{mp}/{dm}": (round(t * 1e3, 4)
+                                                                    if math.isfinite(t) else None)
+                                                 for (m, s, mp, dm), t in ts.items()}}
            for a, c, ts in results]
     with open(args.out, "w") as f:
         json.dump({"entries": entries, "scores": detail, "measurements": raw,

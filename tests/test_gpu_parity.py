@@ -92,7 +92,7 @@ def test_no_edges_and_single_vertex(gg):
 
 
 def test_heavy_rows_are_chunked(gg):
-    # hubs above the heavy threshold (512) in both directions, plus a tail
+    # hubs far above the heavy-row threshold (64 edges), plus a tail
     rng = np.random.default_rng(5)
     src, dst = [], []
     for hub, deg in [(0, 3000), (1, 700), (65, 1500)]:
@@ -219,3 +219,33 @@ def test_two_streams_two_workspaces(gg):
         for w in ws:
             w.free()
         g.free()
+
+
+def test_nearfar_sssp(gg):
+    """The near-far schedule (buckets of width delta) gives the same distances."""
+    rng = np.random.default_rng(1903)
+    graphs = [read_golden(f)[:2] for f in golden_files()]
+    for i in range(8):
+        n = int(rng.integers(1, 300))
+        graphs.append((random_graph(rng, n, int(rng.integers(0, 6 * n + 1)), 0, 9,
+                                    name=f"nf{i}"), int(rng.integers(0, n))))
+    hub = gen.workload("rmat14")
+    graphs += [(gen.workload("er16k"), 0), (gen.workload("grid96"), 0),
+               (hub, int(gen.pick_sources(hub, 1, stream=gen.STREAM["sources"])[0])),
+               (path_graph(700, np.arange(1, 700) % 5 + 1), 0)]
+    for hg, s in graphs:
+        want = oracle.sssp(hg.n, hg.row_ptr, hg.col, hg.w, s)
+        g = gg.Graph.from_host(hg)
+        try:
+            for delta in (1, 5, 0, 10**6):
+                say(f"[gpu] nearfar {hg.name} n={hg.n} delta={delta}")
+                o = gg.make_opts(gg.VERTEX, gg.NEARFAR, gg.MAP_BALANCED, delta=delta)
+                got = g.sssp(s, opts=o).cpu().numpy()
+                assert g.stats()["rc"] == 0
+                np.testing.assert_array_equal(got, want, err_msg=f"{hg.name} delta={delta}")
+            with pytest.raises(gg.GGError):
+                g.bfs(s, opts=gg.make_opts(gg.VERTEX, gg.NEARFAR, gg.MAP_BALANCED))
+            with pytest.raises(gg.GGError):
+                g.sssp(s, opts=gg.make_opts(gg.EDGE, gg.NEARFAR))
+        finally:
+            g.free()
