@@ -44,7 +44,7 @@ HBM_PEAK_GBS = 8000.0
 INF = 2**31 - 1
 ALGOS = ("sssp", "bfs", "cc")
 VARIANTS = {"vertex-sync": (0, 0, 3), "vertex-async": (0, 1, 3), "edge-sync": (1, 0, 0),
-            "edge-async": (1, 1, 0)}
+            "edge-async": (1, 1, 0), "nearfar": (0, 3, 3), "diropt": (0, 4, 3)}
 
 
 def log(*a):
@@ -75,6 +75,8 @@ def algorithmic_bytes(algo, mode, sched, kind, n, prof_kind, launches):
     if kind == "round":
         if sched == 0 and mode == 0:
             return 8 * n * launches + per_edge * E + 4 * U
+        # asynchronous and near-far rounds (near-far: U counts deferred vertices,
+        # each a flag read and a flag store)
         if sched == 0 and mode == 1:
             return (20 if algo == "sssp" else 16) * E + 4 * U
         ntiles = (n + 63) // 64
@@ -94,7 +96,7 @@ def kernel_symbol(algo, kind, mode, sched, mapping):
         return "gg::k_init(gg::Round, int, int)"
     if mode == 1:
         return f"void gg::k_{'esync' if sched == 0 else 'easync'}<{a}>(gg::Round)"
-    return f"void gg::k_{'vsync' if sched == 0 else 'vasync'}<{a}, {mapping}>(gg::Round)"
+    return f"void gg::k_{'vsync' if sched == 0 else 'vasync'}<{a}, {mapping}>(gg::Round)"  # async, near-far
 
 
 def measured_traffic(symbol, workload):
@@ -231,7 +233,7 @@ def main():
         x[2] += b
     (da, dk), (dl, dms, db) = max(agg.items(), key=lambda kv: kv[1][1])
     c = chosen[da]
-    mname = ["vertex", "edge"][c.mode] + "-" + ["sync", "async"][c.sched]
+    mname = ["vertex", "edge"][c.mode] + "-" + ["sync", "async", "auto", "nearfar", "diropt"][c.sched]
     achieved = db / (dms * 1e-3) / 1e9
     sym = kernel_symbol(da, dk, c.mode, c.sched, c.mapping)
     traffic = measured_traffic(sym, args.workload)
@@ -253,6 +255,8 @@ def main():
         s = sources[0]
         for a in ALGOS:
             for vname, (mode, sched, mp) in VARIANTS.items():
+                if (sched == 3 and a != "sssp") or (sched == 4 and a != "bfs"):
+                    continue  # near-far is an SSSP schedule, direction-optimizing a BFS one
                 o = gg.make_opts(mode, sched, mp)
                 times = []
                 for _ in range(args.reps):
@@ -310,7 +314,7 @@ def main():
         "config": {"workload": args.workload, "n": hg.n, "m": hg.m, "m_sym": m_sym,
                    "step": "sssp+bfs+cc, AUTO variants",
                    "variant": {a: {"mode": ["vertex", "edge"][chosen[a].mode],
-                                   "sched": ["sync", "async"][chosen[a].sched],
+                                   "sched": ["sync", "async", "auto", "nearfar", "diropt"][chosen[a].sched],
                                    "mapping": chosen[a].mapping} for a in ALGOS},
                    "sources": sources, "upload_s": round(upload_s, 2),
                    "verified_vs_oracle": verified},

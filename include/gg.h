@@ -67,8 +67,19 @@ typedef enum { GG_VERTEX = 0, GG_EDGE = 1, GG_MODE_AUTO = 2 } gg_mode;
  * credits for the CPU worklist's win on road networks (Sec. 4.2-4.3): a round
  * serves only frontier vertices below the current bound and keeps the rest;
  * the bound grows by delta once a round pushes nothing below it.  The result
- * is the same as every other schedule. */
-typedef enum { GG_SYNC = 0, GG_ASYNC = 1, GG_SCHED_AUTO = 2, GG_NEARFAR = 3 } gg_sched;
+ * is the same as every other schedule.
+ * GG_DIROPT (BFS, vertex-based, needs the in-neighbours that GG_SYMMETRIZE
+ * or GG_SYMMETRIC provide) decides per level on the device: a small frontier
+ * pushes along out-edges as GG_ASYNC does; a frontier of more than n/20
+ * vertices is pulled -- every unvisited vertex scans its in-neighbours (the
+ * DSL's innbrs iterator, Sec. 2) and stops at the first one on the level. */
+typedef enum {
+    GG_SYNC = 0,
+    GG_ASYNC = 1,
+    GG_SCHED_AUTO = 2,
+    GG_NEARFAR = 3,
+    GG_DIROPT = 4
+} gg_sched;
 
 /* How vertex-based work is mapped to lanes.  THREAD: one lane walks a whole
  * row (the paper's generated GPU code); WAVE: one wavefront per vertex;

@@ -55,6 +55,7 @@ void free_ws_arrays(gg_ws_s* ws) {
     if (ws->dev.hstamp) hipFree(ws->dev.hstamp);
     if (ws->dev.ctl) hipFree(ws->dev.ctl);
     if (ws->dev.stat) hipFree(ws->dev.stat);
+    if (ws->dev.pcount) hipFree(ws->dev.pcount);
     if (ws->h_done) hipHostFree(ws->h_done);
     for (auto& e : ws->ev)
         if (e) hipEventDestroy(e);
@@ -83,6 +84,7 @@ int make_ws(gg_graph g, gg_ws_s** out) {
     if (e == hipSuccess) e = hipMemset(ws->dev.hstamp, 0xff, sizeof(int) * (size_t)g->n);
     if (e == hipSuccess) e = dalloc(&ws->dev.ctl, 1);
     if (e == hipSuccess) e = dalloc(&ws->dev.stat, (size_t)kKinds * kMaxStatBlocks);
+    if (e == hipSuccess) e = dalloc(&ws->dev.pcount, (size_t)3 * 2 * kMaxStatBlocks);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&ws->h_done), 4 * sizeof(int));
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ws->ev[0], hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ws->ev[1], hipEventDisableTiming);
@@ -144,7 +146,8 @@ void resolve(gg_graph g, int algo, const gg_opts* in, gg_opts* out) {
     gg_opts o{};
     if (in) o = *in;
     const bool auto_mode = o.mode != GG_VERTEX && o.mode != GG_EDGE;
-    const bool auto_sched = o.sched != GG_SYNC && o.sched != GG_ASYNC && o.sched != GG_NEARFAR;
+    const bool auto_sched = o.sched != GG_SYNC && o.sched != GG_ASYNC && o.sched != GG_NEARFAR &&
+                            o.sched != GG_DIROPT;
     const bool auto_map = o.mapping < GG_MAP_THREAD || o.mapping > GG_MAP_BALANCED;
     int32_t sc = 0, kc = 0, dc = -1, tm = GG_VERTEX, ts = GG_ASYNC, tp = GG_MAP_BALANCED, td = 0;
     gg_class_of(g->m, g->n, g->max_deg, g->levels, &sc, &kc, &dc);
@@ -195,12 +198,15 @@ int plan_make(gg_graph g, gg_ws ws, int algo, int source, const int* sources_dev
     if (nearfar && (algo != GG_ALGO_SSSP || o.mode != GG_VERTEX || o.mapping != GG_MAP_BALANCED))
         return GG_ENOTSUP;
     if (o.delta < 0) return GG_EINVAL;
+    const bool diropt = o.sched == GG_DIROPT;
+    if (diropt && (algo != GG_ALGO_BFS || o.mode != GG_VERTEX || !g->has_sym)) return GG_ENOTSUP;
     const Dev& dv = device();
     const int cap_blocks = o.max_blocks > 0 ? std::min(o.max_blocks, dv.max_blocks) : dv.max_blocks;
     auto grid = [&](long long units) {
         return (int)std::max(1LL, std::min<long long>(units, cap_blocks));
     };
-    p.async = o.sched == GG_ASYNC || nearfar;
+    p.async = o.sched == GG_ASYNC || nearfar || diropt;
+    p.diropt = diropt;
     p.edge = o.mode == GG_EDGE;
     p.cc = algo == GG_ALGO_CC;
     Round& R = p.R;
@@ -230,10 +236,12 @@ int plan_make(gg_graph g, gg_ws ws, int algo, int source, const int* sources_dev
         else p.g_round = grid((n + wpb - 1) / wpb);
     } else if (!p.async && p.edge) {
         p.g_round = grid((g->m / 4 + kBlock - 1) / kBlock);
+    } else if (diropt) {
+        p.g_round = grid(std::max(ngroups * kParts, ntiles) / wpb + 1);
     } else {
         p.g_round = grid((ngroups * kParts + wpb - 1) / wpb);
     }
-    p.need_heavy = p.async && (p.edge || o.mapping == GG_MAP_BALANCED) && nh > 0;
+    p.need_heavy = p.async && (p.edge || diropt || o.mapping == GG_MAP_BALANCED) && nh > 0;
     p.g_heavy = grid((nh + 64LL * wpb - 1) / (64LL * wpb));
     p.need_jump = p.cc && p.edge && !p.async && R.jump;
     p.g_jump = grid((n + kBlock - 1) / kBlock);
@@ -280,6 +288,7 @@ hipError_t plan_round(Plan& p, int r, int stamp) {
     R.r = r;
     R.stamp = stamp;
     hipError_t e = plan_launch(p, KIND_ROUND, [&] {
+        if (p.diropt) return launch_bfs_diropt(R, p.g_round, kBlock, p.s);
         if (!p.async && !p.edge) return launch_vsync(R, p.algo, p.g_round, kBlock, p.s);
         if (!p.async) return launch_esync(R, p.algo, p.g_round, kBlock, p.s);
         if (!p.edge) return launch_vasync(R, p.algo, p.g_round, kBlock, p.s);

@@ -29,6 +29,9 @@ struct Ctl {
     int changed[4];  // [r % 3]: round r updated or pushed something
     int bound[4];    // near-far schedule: [r % 3] = distance bound of round r
     int near_[4];    // near-far schedule: [r % 3] = round r pushed below its bound
+    int grid[4];     // [r % 3] = grid of round r's round kernel (push counts below)
+    int hgrid[4];    // [r % 3] = grid of round r's heavy kernel
+    int pull[4];     // direction-optimizing BFS: [r % 3] = round r pulled
     int pad[2];
 };
 
@@ -69,6 +72,7 @@ struct DevWs {
     int* hstamp;  // [n]: stamp of the last round that had the row on its frontier
     Ctl* ctl;
     Stat* stat;
+    int* pcount;  // [3][2][kMaxStatBlocks]: pushes per block of round r % 3 (round, heavy)
 };
 
 // Everything a round kernel needs.  Passed by value.
@@ -97,6 +101,7 @@ hipError_t launch_esync(const Round& R, int algo, int grid, int block, hipStream
 hipError_t launch_vasync(const Round& R, int algo, int grid, int block, hipStream_t s);
 hipError_t launch_easync(const Round& R, int algo, int grid, int block, hipStream_t s);
 hipError_t launch_heavy(const Round& R, int algo, int grid, int block, hipStream_t s);
+hipError_t launch_bfs_diropt(const Round& R, int grid, int block, hipStream_t s);
 hipError_t launch_jump(const Round& R, int grid, int block, hipStream_t s);
 
 // Graph build helpers (gg_kernels.hip).

@@ -39,6 +39,10 @@ namespace gg {
 // Edges each lane keeps in flight in the relaxation loops.
 constexpr int kBatch = 4;
 
+// Direction-optimizing BFS pulls a level when its frontier holds more than
+// n / kPullRatio vertices.
+constexpr int kPullRatio = 20;
+
 // ------------------------------------------------------------ helpers ----
 
 __device__ __forceinline__ int wave_incl_scan(int x) {
@@ -140,6 +144,13 @@ __device__ void block_finish(const Round& R, const Acc& a, int slot, int kind) {
             st->pushes += P;
         }
         if (U > 0 || P > 0) R.ws.ctl->changed[slot] = 1;
+        // pushes of this block in this round (every block writes its slot)
+        if (kind != KIND_AUX)
+            R.ws.pcount[(slot * 2 + kind) * kMaxStatBlocks + blockIdx.x] = (int)P;
+        if (blockIdx.x == 0) {
+            if (kind == KIND_ROUND) R.ws.ctl->grid[slot] = gridDim.x;
+            if (kind == KIND_HEAVY) R.ws.ctl->hgrid[slot] = gridDim.x;
+        }
     }
 }
 
@@ -719,6 +730,143 @@ __global__ __launch_bounds__(256) void k_easync(Round R) {
     block_finish(R, acc, R.r % 3, KIND_ROUND);
 }
 
+// Direction-optimizing BFS round.  Level r is pushed from the frontier (as in
+// k_vasync: out-edges of the flagged vertices, heavy rows to the chunk kernel)
+// while the frontier is small, and pulled while it is large: every unvisited
+// vertex scans its in-neighbours (the innbrs iterator of the DSL) and takes
+// level r+1 at the first one on level r, so no atomics and few edges.  The
+// frontier size is the sum of the previous round's per-block push counts;
+// every block computes the same sum, so the direction is grid-uniform.
+__global__ __launch_bounds__(256) void k_bfs_diropt(Round R) {
+    if (!round_begin(R)) return;
+    const DevGraph& g = R.g;
+    Ctl* ctl = R.ws.ctl;
+    const int n = g.n;
+    const int lev = R.r;
+    long long front = 1;  // round 0: the source
+    if (R.r > 0) {
+        const int slot = (R.r - 1) % 3;
+        const int gr = *(volatile int*)&ctl->grid[slot];
+        const int gh = *(volatile int*)&ctl->hgrid[slot];
+        __shared__ long long s_sum[4];
+        long long part = 0;
+        for (int b = threadIdx.x; b < gr; b += blockDim.x)
+            part += R.ws.pcount[(slot * 2 + KIND_ROUND) * kMaxStatBlocks + b];
+        for (int b = threadIdx.x; b < gh; b += blockDim.x)
+            part += R.ws.pcount[(slot * 2 + KIND_HEAVY) * kMaxStatBlocks + b];
+        for (int d = 32; d > 0; d >>= 1) part += __shfl_xor(part, d, 64);
+        if ((threadIdx.x & 63) == 0) s_sum[threadIdx.x >> 6] = part;
+        __syncthreads();
+        front = 0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) front += s_sum[i];
+    }
+    const bool pull = front * kPullRatio > n;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->pull[R.r % 3] = pull;
+        ctl->hgrid[R.r % 3] = 0;  // a push round's heavy kernel rewrites it
+    }
+    const int cur = R.r & 1, nxt = cur ^ 1;
+    const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    const long long gw = (long long)blockIdx.x * wpb + (threadIdx.x >> 6);
+    const long long tw = (long long)gridDim.x * wpb;
+    const long long ntiles = (n + 63) / 64;
+    Acc acc;
+    if (!pull) {
+        // push: the balanced frontier round of k_vasync, inlined for BFS
+        unsigned char* vf = R.ws.vflag[cur];
+        unsigned char* tf = R.ws.tflag[cur];
+        const long long nitems = (ntiles + 63) / 64 * kParts;
+        for (long long it = gw; it < nitems; it += tw) {
+            const long long st = it / kParts;
+            const int part = (int)(it % kParts);
+            const long long t = st * 64 + lane;
+            const bool mine = lane / (64 / kParts) == part;
+            const bool tfl = mine && t < ntiles && tf[t] != 0;
+            unsigned long long tm = __ballot(tfl);
+            if (tfl) tf[t] = 0;
+            while (tm) {
+                const int b = __ffsll(tm) - 1;
+                tm &= tm - 1;
+                const int u = (int)((st * 64 + b) * 64 + lane);
+                const bool on = u < n && vf[u] != 0;
+                if (on) vf[u] = 0;
+                int rb = 0, re = 0;
+                if (on) {
+                    rb = g.row[u];
+                    re = g.row[u + 1];
+                    acc.v++;
+                }
+                const bool hv = on && re - rb > g.heavy;
+                if (hv) R.ws.hstamp[u] = R.stamp;
+                wave_relax_rows<BFS, true>(R, g.col, on && !hv ? rb : 0,
+                                           on && !hv ? re - rb : 0, lev, nxt, acc);
+            }
+        }
+    } else {
+        // pull: one tile of 64 vertices per wavefront step; the frontier flags
+        // of this round are cleared on the way (they are not read)
+        unsigned char* vf = R.ws.vflag[cur];
+        unsigned char* tf = R.ws.tflag[cur];
+        int* val = R.val;
+        for (long long t = gw; t < ntiles; t += tw) {
+            const int v = (int)(t * 64 + lane);
+            const bool in = v < n;
+            if (in) vf[v] = 0;
+            if (lane == 0) tf[t] = 0;
+            const bool todo = in && val[v] == kInf;
+            int ib = 0, ie = 0;
+            if (todo) {
+                // in-neighbours: the whole row of a symmetric graph, else the
+                // part of the both-directions row after v's out-edges
+                if (g.symmetric) {
+                    ib = g.row[v];
+                    ie = g.row[v + 1];
+                } else {
+                    ib = g.srow[v] + (g.row[v + 1] - g.row[v]);
+                    ie = g.srow[v + 1];
+                }
+                acc.v++;
+            }
+            const int* icol = g.symmetric ? g.col : g.scol;
+            bool found = false;
+            // short lists: each lane walks its own, kBatch entries at a time
+            const bool shortl = todo && ie - ib <= 64;
+            for (int e = ib; shortl && !found && e < ie; e += kBatch) {
+                int x[kBatch];
+#pragma unroll
+                for (int j = 0; j < kBatch; ++j) x[j] = e + j < ie ? val[icol[e + j]] : kInf;
+#pragma unroll
+                for (int j = 0; j < kBatch; ++j) {
+                    if (e + j < ie) acc.e++;
+                    found |= x[j] == lev;
+                }
+            }
+            // long lists: the wavefront walks them one vertex at a time
+            unsigned long long lm = __ballot(todo && !shortl);
+            while (lm) {
+                const int o = __ffsll(lm) - 1;
+                lm &= lm - 1;
+                const int ob = __shfl(ib, o, 64), oe = __shfl(ie, o, 64);
+                bool hit = false;
+                for (int e = ob; e < oe && !hit; e += 64) {
+                    const bool h = e + lane < oe && val[icol[e + lane]] == lev;
+                    if (e + lane < oe) acc.e++;
+                    hit = __ballot(h) != 0;
+                }
+                if (lane == o) found = hit;
+            }
+            if (found) {
+                val[v] = lev + 1;
+                R.ws.vflag[nxt][v] = 1;
+                R.ws.tflag[nxt][v >> 6] = 1;
+                acc.p++;
+            }
+        }
+    }
+    block_finish(R, acc, R.r % 3, KIND_ROUND);
+}
+
 // Heavy rows of the frontier: the light kernel of the same round stamped
 // them; every wavefront walks the static chunk list and serves the chunks
 // whose row carries this round's stamp.
@@ -738,12 +886,14 @@ __global__ __launch_bounds__(256) void k_heavy(Round R) {
     const int lane = threadIdx.x & 63;
     const bool nf = A == SSSP && R.delta > 0;
     const int bound = nf ? *(volatile int*)&ctl->bound[R.r % 3] : kInf;
+    // a pulling BFS round stamps no heavy row: nothing to serve
+    const bool pulled = A == BFS && *(volatile int*)&ctl->pull[R.r % 3] != 0;
     Acc acc;
     // 64 chunk stamps are checked at once, then the wavefront serves the
     // chunks that match in turn.  The 64 chunks of one check are spread over
     // the list with the stride of the whole grid, so that the chunks of one
     // long row (which sit next to each other) land on different wavefronts.
-    for (long long k0 = 0; gw + k0 * tw < nch; k0 += 64) {
+    for (long long k0 = 0; !pulled && gw + k0 * tw < nch; k0 += 64) {
         const long long it = gw + (k0 + lane) * tw;
         int2 c = make_int2(0, 0);
         bool on = false;
@@ -910,6 +1060,10 @@ hipError_t launch_heavy(const Round& R, int algo, int grid, int block, hipStream
         case BFS: GG_LAUNCH(k_heavy<BFS>, grid, block, s, R);
         default: GG_LAUNCH(k_heavy<CC>, grid, block, s, R);
     }
+}
+
+hipError_t launch_bfs_diropt(const Round& R, int grid, int block, hipStream_t s) {
+    GG_LAUNCH(k_bfs_diropt, grid, block, s, R);
 }
 
 hipError_t launch_jump(const Round& R, int grid, int block, hipStream_t s) {

@@ -124,7 +124,7 @@ struct Plan {
     gg_opts o{};
     hipStream_t s = nullptr;
     Round R{};
-    bool async = false, edge = false, cc = false;
+    bool async = false, edge = false, cc = false, diropt = false;
     bool need_heavy = false, need_jump = false, prof = false;
     int g_init = 1, g_seed = 1, g_round = 1, g_heavy = 1, g_jump = 1;
 };

@@ -45,7 +45,7 @@ long long ws_bytes_of(gg_graph g) {
     const long long vbytes = ((ntiles + 63) / 64) * 64 * 64;
     const long long tbytes = ((ntiles + 63) / 64) * 64;
     return 2 * (vbytes + tbytes) + 4LL * g->n + (long long)sizeof(Ctl) +
-           (long long)sizeof(Stat) * kKinds * kMaxStatBlocks;
+           (long long)sizeof(Stat) * kKinds * kMaxStatBlocks + 4LL * 3 * 2 * kMaxStatBlocks;
 }
 
 }  // namespace

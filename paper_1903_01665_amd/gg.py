@@ -18,7 +18,7 @@ INF = 2**31 - 1
 
 # enums of gg.h
 VERTEX, EDGE, MODE_AUTO = 0, 1, 2
-SYNC, ASYNC, SCHED_AUTO, NEARFAR = 0, 1, 2, 3
+SYNC, ASYNC, SCHED_AUTO, NEARFAR, DIROPT = 0, 1, 2, 3, 4
 MAP_AUTO, MAP_THREAD, MAP_WAVE, MAP_BALANCED = 0, 1, 2, 3
 ALGO_SSSP, ALGO_BFS, ALGO_CC = 0, 1, 2
 SYMMETRIZE, INPUT_ON_DEVICE, SYMMETRIC = 1, 2, 4

@@ -249,3 +249,37 @@ def test_nearfar_sssp(gg):
                 g.sssp(s, opts=gg.make_opts(gg.EDGE, gg.NEARFAR))
         finally:
             g.free()
+
+
+def test_diropt_bfs(gg):
+    """Direction-optimizing BFS (push small frontiers, pull large ones) gives
+    the same levels; both directions run on these graphs."""
+    rng = np.random.default_rng(77)
+    graphs = [read_golden(f)[:2] for f in golden_files()]
+    for i in range(8):
+        n = int(rng.integers(1, 400))
+        graphs.append((random_graph(rng, n, int(rng.integers(0, 8 * n + 1)), 1, 9,
+                                    name=f"do{i}"), int(rng.integers(0, n))))
+    hub = gen.workload("rmat14")
+    graphs += [(gen.workload("er16k"), 0), (gen.workload("grid96"), 0),
+               (hub, int(gen.pick_sources(hub, 1, stream=gen.STREAM["sources"])[0])),
+               (gen.workload("rmat12"), 0), (path_graph(300, np.ones(299)), 0)]
+    for hg, s in graphs:
+        want = oracle.bfs(hg.n, hg.row_ptr, hg.col, s)
+        g = gg.Graph.from_host(hg, symmetrize=True)
+        try:
+            say(f"[gpu] diropt {hg.name} n={hg.n}")
+            for rep in range(2):
+                got = g.bfs(s, gg.VERTEX, gg.DIROPT).cpu().numpy()
+                assert g.stats()["rc"] == 0
+                np.testing.assert_array_equal(got, want, err_msg=hg.name)
+        finally:
+            g.free()
+    # without in-neighbours the schedule is refused
+    hg = gen.workload("er300x900")
+    g = gg.Graph(hg.n, hg.row_ptr, hg.col, hg.w)
+    try:
+        with pytest.raises(gg.GGError):
+            g.bfs(0, gg.VERTEX, gg.DIROPT)
+    finally:
+        g.free()
