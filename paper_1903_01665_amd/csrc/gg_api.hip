@@ -105,7 +105,65 @@ int make_ws(gg_graph g, gg_ws_s** out) {
     return GG_OK;
 }
 
+// Graphs with fewer edges keep the single edge list for the edge sweep.
+constexpr long long kPartMinEdges = 1LL << 20;
+
+// The edge list again, cut into kXcd parts by head vertex with equal edge
+// counts (part boundaries at the in-degree quantiles), CSR order kept inside
+// a part, each part padded to a multiple of 4 edges with the self-loop 0->0
+// of weight 0 (it never changes a value).
+int build_parts(gg_graph g, const std::vector<int>& hrow, const int* col, const int* w,
+                hipStream_t s) {
+    const int n = g->n;
+    const long long m = g->m;
+    std::vector<long long> cum((size_t)n + 1, 0);
+    for (long long e = 0; e < m; ++e) cum[(size_t)col[e] + 1]++;
+    for (int v = 0; v < n; ++v) cum[v + 1] += cum[v];
+    std::vector<unsigned char> part((size_t)n);
+    int p = 0;
+    for (int v = 0; v < n; ++v) {
+        while (p < kXcd - 1 && cum[v] >= (long long)(p + 1) * m / kXcd) ++p;
+        part[v] = (unsigned char)p;
+    }
+    long long cnt[kXcd] = {};
+    for (long long e = 0; e < m; ++e) cnt[part[col[e]]]++;
+    long long off[kXcd + 1];
+    off[0] = 0;
+    for (int k = 0; k < kXcd; ++k) off[k + 1] = off[k] + ((cnt[k] + 3) & ~3LL);
+    const long long mp = off[kXcd];
+    if (mp >= (1LL << 31)) return GG_OK;  // keep the single list
+    std::vector<int> ps((size_t)mp, 0), pc((size_t)mp, 0), pwv(w ? (size_t)mp : 0, 0);
+    long long cur[kXcd];
+    for (int k = 0; k < kXcd; ++k) cur[k] = off[k];
+    for (int u = 0; u < n; ++u)
+        for (int e = hrow[u]; e < hrow[u + 1]; ++e) {
+            const long long at = cur[part[col[e]]]++;
+            ps[at] = u;
+            pc[at] = col[e];
+            if (w) pwv[at] = w[e];
+        }
+    hipError_t e = dalloc(&g->psrc, (size_t)mp);
+    if (e == hipSuccess) e = dalloc(&g->pcol, (size_t)mp);
+    if (e == hipSuccess && w) e = dalloc(&g->pw, (size_t)mp);
+    if (e == hipSuccess) e = hipMemcpyAsync(g->psrc, ps.data(), sizeof(int) * mp, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(g->pcol, pc.data(), sizeof(int) * mp, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && w)
+        e = hipMemcpyAsync(g->pw, pwv.data(), sizeof(int) * mp, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        dfree(g->psrc);
+        dfree(g->pcol);
+        dfree(g->pw);
+        return e == hipErrorOutOfMemory ? GG_ENOMEM : GG_EHIP;
+    }
+    for (int k = 0; k <= kXcd; ++k) g->poff[k] = (int)off[k];
+    return GG_OK;
+}
+
 void free_graph_arrays(gg_graph g) {
+    dfree(g->psrc);
+    dfree(g->pcol);
+    dfree(g->pw);
     if (g->srow && g->srow != g->row) hipFree(g->srow);
     if (g->scol && g->scol != g->col) hipFree(g->scol);
     if (g->ssrc && g->ssrc != g->src) hipFree(g->ssrc);
@@ -137,6 +195,10 @@ DevGraph dev_graph(gg_graph g) {
     d.shchunks = g->shchunks;
     d.n_shchunks = g->n_shchunks;
     d.symmetric = g->symmetric;
+    d.psrc = g->psrc;
+    d.pcol = g->pcol;
+    d.pw = g->pw;
+    for (int k = 0; k <= kXcd; ++k) d.poff[k] = g->poff[k];
     return d;
 }
 
@@ -548,22 +610,29 @@ int gg_graph_upload(int32_t n, int64_t m, const int32_t* row_ptr, const int32_t*
     if (e != hipSuccess) return bail(e == hipErrorOutOfMemory ? GG_ENOMEM : GG_EHIP);
     if (on_dev) {
         // validate device input on the host after copying it back
-        std::vector<int> hc((size_t)m);
+        std::vector<int> hc((size_t)m), hw(w ? (size_t)m : 0);
         if (m && hipMemcpy(hc.data(), g->col, sizeof(int) * m, hipMemcpyDeviceToHost) != hipSuccess)
             return bail(GG_EHIP);
         for (long long i = 0; i < m; ++i)
             if (hc[i] < 0 || hc[i] >= n) return bail(GG_EINVAL);
         if (w) {
-            if (m && hipMemcpy(hc.data(), g->w, sizeof(int) * m, hipMemcpyDeviceToHost) != hipSuccess)
+            if (m && hipMemcpy(hw.data(), g->w, sizeof(int) * m, hipMemcpyDeviceToHost) != hipSuccess)
                 return bail(GG_EHIP);
             double sum = 0;
             for (long long i = 0; i < m; ++i) {
-                if (hc[i] < 0) return bail(GG_EINVAL);
-                sum += hc[i];
-                g->max_w = std::max(g->max_w, (int)hc[i]);
+                if (hw[i] < 0) return bail(GG_EINVAL);
+                sum += hw[i];
+                g->max_w = std::max(g->max_w, (int)hw[i]);
             }
             g->avg_w = m ? sum / (double)m : 0.0;
         }
+        if (m >= kPartMinEdges) {
+            const int rc = build_parts(g, hrow, hc.data(), w ? hw.data() : nullptr, s);
+            if (rc != GG_OK) return bail(rc);
+        }
+    } else if (m >= kPartMinEdges) {
+        const int rc = build_parts(g, hrow, col, w, s);
+        if (rc != GG_OK) return bail(rc);
     }
     std::vector<int2> hch = build_chunks(hrow, n, g->heavy, g->chunk);
     g->n_hchunks = (int)hch.size();

@@ -15,6 +15,7 @@ constexpr int kDefaultHeavy = 64;    // rows longer than this are chunked (balan
 constexpr int kChunk = 256;          // edges per heavy-row chunk
 constexpr int kKinds = 3;            // statistics kinds: round, heavy chunks, auxiliary
 constexpr int kParts = 32;           // frontier work items per 64-tile group (2 tiles each)
+constexpr int kXcd = 8;              // accelerator dies; workgroups go to them round-robin
 enum Kind { KIND_ROUND = 0, KIND_HEAVY = 1, KIND_AUX = 2 };
 
 enum Algo { SSSP = 0, BFS = 1, CC = 2 };
@@ -61,6 +62,13 @@ struct DevGraph {
     const int2* shchunks;
     int n_shchunks;
     bool symmetric;  // input already holds both directions of every edge
+    // the edge list again, cut into kXcd parts by head vertex (equal edge
+    // counts), each padded to a multiple of 4 with self-loops on vertex 0;
+    // null when not built
+    const int* psrc;
+    const int* pcol;
+    const int* pw;
+    int poff[kXcd + 1];
 };
 
 // Device view of a workspace: frontier flags (one byte per vertex, one per

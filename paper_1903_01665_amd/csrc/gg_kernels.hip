@@ -498,24 +498,21 @@ __device__ __forceinline__ void edge_sync_one(const Round& R, int u, int t, int 
     }
 }
 
+// Four consecutive edges [e, e+4) of an edge list (16-byte aligned), with
+// every value loaded before the first atomic.
 template <int A>
-__global__ __launch_bounds__(256) void k_esync(Round R) {
-    if (!round_begin(R)) return;
+__device__ __forceinline__ void edge_sync_four(const Round& R, const int* src, const int* col,
+                                               const int* w, long long e, Acc& acc) {
     const DevGraph& g = R.g;
-    const int m = g.m;
-    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long tt = (long long)gridDim.x * blockDim.x;
-    const int m4 = m & ~3;
-    Acc acc;
     int* val = R.val;
-    for (long long e = tid * 4; e < m4; e += tt * 4) {
-        const int4 s4 = *reinterpret_cast<const int4*>(g.src + e);
-        const int4 c4 = *reinterpret_cast<const int4*>(g.col + e);
+    {
+        const int4 s4 = *reinterpret_cast<const int4*>(src + e);
+        const int4 c4 = *reinterpret_cast<const int4*>(col + e);
         const int u[4] = {s4.x, s4.y, s4.z, s4.w};
         const int t[4] = {c4.x, c4.y, c4.z, c4.w};
         int wt[4] = {0, 0, 0, 0};
         if (A == SSSP) {
-            const int4 w4 = *reinterpret_cast<const int4*>(g.w + e);
+            const int4 w4 = *reinterpret_cast<const int4*>(w + e);
             wt[0] = w4.x;
             wt[1] = w4.y;
             wt[2] = w4.z;
@@ -552,7 +549,40 @@ __global__ __launch_bounds__(256) void k_esync(Round R) {
             }
         }
     }
-    for (long long e = m4 + tid; e < m; e += tt) edge_sync_one<A>(R, g.src[e], g.col[e], (int)e, acc);
+}
+
+// Synchronous edge sweep.  With the head-partitioned edge list, block b
+// sweeps part b % kXcd: workgroups are dispatched to the accelerator dies
+// round-robin, so each die gathers and updates the values of one slice of
+// the vertices only, and that slice stays in the die's own L2.  (Any grid
+// size is correct; a grid that is not a multiple of kXcd walks all parts.)
+template <int A>
+__global__ __launch_bounds__(256) void k_esync(Round R) {
+    if (!round_begin(R)) return;
+    const DevGraph& g = R.g;
+    Acc acc;
+    if (g.psrc) {
+        const bool split = gridDim.x >= kXcd && gridDim.x % kXcd == 0;
+        const int p0 = split ? (int)(blockIdx.x % kXcd) : 0;
+        const int p1 = split ? p0 + 1 : kXcd;
+        const long long bpp = split ? gridDim.x / kXcd : gridDim.x;
+        const long long bi = split ? blockIdx.x / kXcd : blockIdx.x;
+        for (int p = p0; p < p1; ++p) {
+            const long long e1 = g.poff[p + 1];
+            for (long long e = g.poff[p] + (bi * blockDim.x + threadIdx.x) * 4; e < e1;
+                 e += bpp * blockDim.x * 4)
+                edge_sync_four<A>(R, g.psrc, g.pcol, g.pw, e, acc);
+        }
+    } else {
+        const int m = g.m;
+        const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+        const long long tt = (long long)gridDim.x * blockDim.x;
+        const int m4 = m & ~3;
+        for (long long e = tid * 4; e < m4; e += tt * 4)
+            edge_sync_four<A>(R, g.src, g.col, g.w, e, acc);
+        for (long long e = m4 + tid; e < m; e += tt)
+            edge_sync_one<A>(R, g.src[e], g.col[e], (int)e, acc);
+    }
     block_finish(R, acc, R.r % 3, KIND_ROUND);
 }
 

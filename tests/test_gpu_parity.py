@@ -283,3 +283,23 @@ def test_diropt_bfs(gg):
             g.bfs(0, gg.VERTEX, gg.DIROPT)
     finally:
         g.free()
+
+
+def test_partitioned_edge_sweep(gg):
+    """Graphs with >= 2^20 edges sweep a head-partitioned edge list, one part
+    per die; any grid size gives the same result."""
+    for name in ("rmat16", "grid724"):
+        hg = gen.workload(name)
+        assert hg.m >= 1 << 20
+        s = int(gen.pick_sources(hg, 1, stream=gen.STREAM["sources"])[0])
+        want = expected(hg, s)
+        g = gg.Graph.from_host(hg, symmetrize=True)
+        try:
+            for cap in (0, 8, 7, 24, 1):
+                say(f"[gpu] partitioned edge sweep {name} cap={cap}")
+                o = gg.make_opts(EDGE, SYNC, max_blocks=cap)
+                np.testing.assert_array_equal(g.sssp(s, opts=o).cpu().numpy(), want["sssp"])
+                np.testing.assert_array_equal(g.bfs(s, opts=o).cpu().numpy(), want["bfs"])
+                np.testing.assert_array_equal(g.cc(opts=o).cpu().numpy(), want["cc"])
+        finally:
+            g.free()
