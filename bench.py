@@ -172,8 +172,10 @@ def main():
     g = gg.Graph.from_host(hg, symmetrize=True)
     torch.cuda.synchronize()
     upload_s = time.time() - t
+    # depth class for the AUTO choice (one BFS, outside the timed region)
+    gclass = g.probe()
     m_sym = hg.m if hg.symmetric else 2 * hg.m
-    log(f"[bench] uploaded in {upload_s:.2f}s; sources {sources}")
+    log(f"[bench] uploaded in {upload_s:.2f}s; class {gclass}; sources {sources}")
 
     outs = {a: torch.empty(hg.n, dtype=torch.int32, device="cuda") for a in ALGOS}
     auto = gg.make_opts()
@@ -317,6 +319,7 @@ def main():
                                    "sched": ["sync", "async", "auto", "nearfar", "diropt"][chosen[a].sched],
                                    "mapping": chosen[a].mapping} for a in ALGOS},
                    "sources": sources, "upload_s": round(upload_s, 2),
+                   "graph_class": list(gclass),
                    "verified_vs_oracle": verified},
         "roofline": roofline,
         "cpu_baseline": cpu,
