@@ -436,7 +436,7 @@ def bench_serve(args):
     # traversed edges per (graph, source)
     trav = {}
     for i, h in enumerate(hosts):
-        g = gg.Graph.from_host(h)
+        g = gg.Graph.from_host(h, symmetrize=True)
         trav[i] = serve.traversed_edges(g, h, sources[i])
         g.free()
     edges = sum(trav[int(gi)][int(s)] for gi, s in zip(trace.graph, trace.source))

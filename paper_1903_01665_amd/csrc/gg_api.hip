@@ -221,6 +221,12 @@ void resolve(gg_graph g, int algo, const gg_opts* in, gg_opts* out) {
     // multiple of the mean weight, else 4 mean weights
     if (o.sched == GG_NEARFAR && o.delta <= 0)
         o.delta = std::max(1, (int)((td > 0 ? td : 4) * g->avg_w));
+    // a choice taken from the table must be one this graph can run
+    if (auto_sched && o.sched == GG_DIROPT &&
+        (algo != GG_ALGO_BFS || o.mode != GG_VERTEX || !g->has_sym))
+        o.sched = GG_ASYNC;
+    if (auto_sched && o.sched == GG_NEARFAR && (algo != GG_ALGO_SSSP || o.mode != GG_VERTEX))
+        o.sched = GG_ASYNC;
     // without the both-directions CSR only the edge sweep can run CC
     if (algo == GG_ALGO_CC && !g->has_sym) {
         if (auto_mode) o.mode = GG_EDGE;

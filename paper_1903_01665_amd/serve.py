@@ -89,7 +89,7 @@ def run_served(hosts, trace, slots=32, mem_budget=8 << 30, upload_every=5.0, n_p
     srv = gg.Server(slots, mem_budget)
     gid = {}
     for i in range(n_pool):
-        gid[i] = srv.add_graph(gg.Graph.from_host(hosts[i]))
+        gid[i] = srv.add_graph(gg.Graph.from_host(hosts[i], symmetrize=True))
     lock = threading.Lock()
     stop = threading.Event()
 
@@ -106,7 +106,7 @@ def run_served(hosts, trace, slots=32, mem_budget=8 << 30, upload_every=5.0, n_p
             if stop.is_set():
                 break
             s = torch.cuda.Stream()
-            g = gg.Graph.from_host(hosts[k], stream=s)
+            g = gg.Graph.from_host(hosts[k], symmetrize=True, stream=s)
             with lock:
                 gid[k] = srv.add_graph(g)
                 retire.append((due, k - n_pool))
@@ -178,7 +178,7 @@ def run_plain(hosts, trace, n_pool=None, upload_every=5.0):
         gi = int(trace.graph[k])
         if gi not in graphs:
             tu = time.perf_counter()
-            graphs[gi] = gg.Graph.from_host(hosts[gi])
+            graphs[gi] = gg.Graph.from_host(hosts[gi], symmetrize=True)
             out[gi] = torch.empty(hosts[gi].n, dtype=torch.int32, device="cuda")
             torch.cuda.synchronize()
             upload_s += time.perf_counter() - tu

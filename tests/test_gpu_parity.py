@@ -303,3 +303,22 @@ def test_partitioned_edge_sweep(gg):
                 np.testing.assert_array_equal(g.cc(opts=o).cpu().numpy(), want["cc"])
         finally:
             g.free()
+
+
+def test_auto_never_picks_an_unavailable_variant(gg):
+    """A tuning table may name the direction-optimizing BFS; on a graph without
+    in-neighbours AUTO falls back instead of failing."""
+    saved = gg.tune_get()
+    try:
+        gg.tune_set([dict(algo=1, size_class=8, skew_class=2, depth_class=-1, mode=0, sched=4,
+                          mapping=3)])
+        hg = gen.workload("rmat12")
+        g = gg.Graph(hg.n, hg.row_ptr, hg.col, hg.w)  # no in-neighbours
+        try:
+            np.testing.assert_array_equal(g.bfs(0).cpu().numpy(),
+                                          oracle.bfs(hg.n, hg.row_ptr, hg.col, 0))
+            assert g.resolve(gg.ALGO_BFS).sched == gg.ASYNC
+        finally:
+            g.free()
+    finally:
+        gg.tune_set(saved)
