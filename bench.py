@@ -132,6 +132,8 @@ def main():
     ap.add_argument("--instances", type=int, default=512, help="batched: instance count")
     ap.add_argument("--duration", type=float, default=12.0, help="serve: trace seconds")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: queries per second")
+    ap.add_argument("--slots", type=int, default=8, help="serve: queries in flight at most")
+    ap.add_argument("--no-plain", action="store_true", help="serve: skip the plain run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported",
@@ -441,20 +443,23 @@ def bench_serve(args):
         g.free()
     edges = sum(trav[int(gi)][int(s)] for gi, s in zip(trace.graph, trace.source))
     log(f"[bench] trace: {len(trace.t)} queries over {args.duration}s, {edges} traversed edges")
-    lat_s, st, wall_s = serve.run_served(hosts, trace, slots=32, upload_every=upload_every,
-                                         n_pool=n_pool)
+    lat_s, st, wall_s = serve.run_served(hosts, trace, slots=args.slots,
+                                         upload_every=upload_every, n_pool=n_pool)
     ok = int((st == 0).sum())
     log(f"[bench] served: wall {wall_s:.2f}s p50 {serve.percentile(lat_s, 50) * 1e3:.2f} ms "
         f"p99 {serve.percentile(lat_s, 99) * 1e3:.2f} ms ({ok}/{len(st)} ok)")
-    lat_p, wall_p = serve.run_plain(hosts, trace, n_pool=n_pool, upload_every=upload_every)
-    log(f"[bench] plain: wall {wall_p:.2f}s p50 {serve.percentile(lat_p, 50) * 1e3:.2f} ms "
-        f"p99 {serve.percentile(lat_p, 99) * 1e3:.2f} ms")
+    if args.no_plain:
+        lat_p, wall_p = np.array([np.nan]), float("nan")
+    else:
+        lat_p, wall_p = serve.run_plain(hosts, trace, n_pool=n_pool, upload_every=upload_every)
+        log(f"[bench] plain: wall {wall_p:.2f}s p50 {serve.percentile(lat_p, 50) * 1e3:.2f} ms "
+            f"p99 {serve.percentile(lat_p, 99) * 1e3:.2f} ms")
     q = lambda x, p: round(serve.percentile(x, p) * 1e3, 3)
     common_line(args, "GTEPS served (Poisson SSSP/BFS queries)", edges / wall_s / 1e9, "GTEPS",
                 wall_s * 1e3 / max(1, len(trace.t)),
                 {"workload": "serve-rmat-12..22", "graphs": n_pool, "uploads": n_up,
                  "rate_qps": args.rate, "duration_s": args.duration, "queries": len(trace.t),
-                 "traversed_edges": edges, "slots": 32},
+                 "traversed_edges": edges, "slots": args.slots},
                 latency_ms={"served": {"p50": q(lat_s, 50), "p99": q(lat_s, 99)},
                             "plain": {"p50": q(lat_p, 50), "p99": q(lat_p, 99)}},
                 plain={"GTEPS": round(edges / wall_p / 1e9, 4), "wall_s": round(wall_p, 3)},
