@@ -63,7 +63,10 @@ def log(*a):
 #                 row pair, value); per edge 12 B SSSP / 8 B BFS, CC;
 #                 2 B per push (vertex and tile flag bytes)
 #   edge async    as vertex async, plus the 4 B edge-list source per edge
-# heavy kernels: per edge 12 / 8 B, per push 2 B
+#   CC diropt     swept edges as edge sync (16 B), the other edges, vertices
+#                 and tiles as vertex async; 4 B per update; per push 2 B of
+#                 flags and 8 B for the pushed vertex's row length
+# heavy kernels: per edge 12 / 8 B, per push 2 B (10 B under CC diropt)
 # aux kernels:   init 4 B per vertex (+2 B of flags when async); CC shortcut
 #                8 B per vertex per launch
 def algorithmic_bytes(algo, mode, sched, kind, n, prof_kind, launches):
@@ -72,6 +75,13 @@ def algorithmic_bytes(algo, mode, sched, kind, n, prof_kind, launches):
     U = prof_kind["updates"]
     P = prof_kind["pushes"]
     per_edge = 12 if algo == "sssp" else 8
+    if algo == "cc" and sched == 4:
+        D = prof_kind.get("swept_edges", 0)
+        if kind == "round":
+            return (16 * D + 8 * (E - D) + 16 * V + ((n + 63) // 64) * launches
+                    + 4 * U + 10 * P)
+        if kind == "heavy":
+            return 8 * E + 10 * P
     if kind == "round":
         if sched == 0 and mode == 0:
             return 8 * n * launches + per_edge * E + 4 * U
@@ -94,6 +104,8 @@ def kernel_symbol(algo, kind, mode, sched, mapping):
         return f"void gg::k_heavy<{a}>(gg::Round)"
     if kind == "aux":
         return "gg::k_init(gg::Round, int, int)"
+    if sched == 4:
+        return f"gg::k_{algo}_diropt(gg::Round)"
     if mode == 1:
         return f"void gg::k_{'esync' if sched == 0 else 'easync'}<{a}>(gg::Round)"
     return f"void gg::k_{'vsync' if sched == 0 else 'vasync'}<{a}, {mapping}>(gg::Round)"  # async, near-far
@@ -259,8 +271,10 @@ def main():
         s = sources[0]
         for a in ALGOS:
             for vname, (mode, sched, mp) in VARIANTS.items():
-                if (sched == 3 and a != "sssp") or (sched == 4 and a != "bfs"):
-                    continue  # near-far is an SSSP schedule, direction-optimizing a BFS one
+                if (sched == 3 and a != "sssp") or (sched == 4 and a == "sssp"):
+                    continue  # near-far is an SSSP schedule, the per-round choice BFS/CC
+                if sched == 4 and a == "cc":
+                    mode = 1  # CC's per-round choice starts from edge sweeps
                 o = gg.make_opts(mode, sched, mp)
                 times = []
                 for _ in range(args.reps):

@@ -68,11 +68,19 @@ typedef enum { GG_VERTEX = 0, GG_EDGE = 1, GG_MODE_AUTO = 2 } gg_mode;
  * serves only frontier vertices below the current bound and keeps the rest;
  * the bound grows by delta once a round pushes nothing below it.  The result
  * is the same as every other schedule.
- * GG_DIROPT (BFS, vertex-based, needs the in-neighbours that GG_SYMMETRIZE
- * or GG_SYMMETRIC provide) decides per level on the device: a small frontier
- * pushes along out-edges as GG_ASYNC does; a frontier of more than n/20
- * vertices is pulled -- every unvisited vertex scans its in-neighbours (the
- * DSL's innbrs iterator, Sec. 2) and stops at the first one on the level. */
+ * GG_DIROPT picks the dense or the sparse form of each round on the device,
+ * from the size of the frontier the previous round left; it needs the
+ * both-directions CSR that GG_SYMMETRIZE or GG_SYMMETRIC provide.
+ *   BFS (vertex-based): a small frontier pushes along out-edges as GG_ASYNC
+ *   does; a frontier of more than n/20 vertices is pulled -- every unvisited
+ *   vertex scans its in-neighbours (the DSL's innbrs iterator, Sec. 2) and
+ *   stops at the first one on the level.
+ *   CC (edge-based): rounds sweep every stored edge (GG_SYNC's edge form)
+ *   while the rows of the vertices lowered by the previous round hold more
+ *   than 1/8 of the both-directions edges, then serve those vertices as a
+ *   worklist (GG_ASYNC's vertex form) -- the paper's synchronous and
+ *   asynchronous schedules (Sec. 3.3) chosen per round instead of per run.
+ * With GG_MODE_AUTO an explicit GG_DIROPT takes the mode it runs in. */
 typedef enum {
     GG_SYNC = 0,
     GG_ASYNC = 1,
@@ -134,12 +142,15 @@ typedef struct {
 
 /* Per-kernel-kind timing and work of the last traversal run with
  * GG_OPT_PROFILE.  Kinds: 0 = round kernels (sweeps / worklist rounds),
- * 1 = heavy-row chunk kernels, 2 = auxiliary kernels (init, CC shortcut). */
+ * 1 = heavy-row chunk kernels, 2 = auxiliary kernels (init, CC shortcut).
+ * swept_edges: the part of edges_processed read by the edge sweeps of CC
+ * under GG_DIROPT (the rest went through the worklist). */
 #define GG_KINDS 3
 typedef struct {
     int32_t launches;
     float total_ms;   /* sum of per-launch event times */
     int64_t edges_processed, vertices_processed, updates, pushes;
+    int64_t swept_edges;
 } gg_kind_profile;
 
 typedef struct {

@@ -202,6 +202,14 @@ DevGraph dev_graph(gg_graph g) {
     return d;
 }
 
+// The per-round dense/sparse schedule: BFS vertex-based (pull over
+// in-neighbours), CC edge-based (sweeps, then the worklist); both read the
+// both-directions CSR.
+bool diropt_ok(gg_graph g, int algo, int mode) {
+    if (!g->has_sym) return false;
+    return (algo == GG_ALGO_BFS && mode == GG_VERTEX) || (algo == GG_ALGO_CC && mode == GG_EDGE);
+}
+
 // AUTO fields resolve through the tuning table (else built-in rules) for
 // the graph's class; explicit fields are kept.
 void resolve(gg_graph g, int algo, const gg_opts* in, gg_opts* out) {
@@ -216,15 +224,19 @@ void resolve(gg_graph g, int algo, const gg_opts* in, gg_opts* out) {
     gg_tune_lookup(algo, sc, kc, dc, &tm, &ts, &tp, &td);
     if (auto_mode) o.mode = tm;
     if (auto_sched) o.sched = ts;
+    // an explicit per-round schedule fixes the mode it runs in
+    if (!auto_sched && o.sched == GG_DIROPT && auto_mode)
+        o.mode = algo == GG_ALGO_CC ? GG_EDGE : GG_VERTEX;
     if (auto_map) o.mapping = tp;
     // bucket width of the near-far schedule: explicit, else the table's
     // multiple of the mean weight, else 4 mean weights
     if (o.sched == GG_NEARFAR && o.delta <= 0)
         o.delta = std::max(1, (int)((td > 0 ? td : 4) * g->avg_w));
     // a choice taken from the table must be one this graph can run
-    if (auto_sched && o.sched == GG_DIROPT &&
-        (algo != GG_ALGO_BFS || o.mode != GG_VERTEX || !g->has_sym))
-        o.sched = GG_ASYNC;
+    if (auto_sched && o.sched == GG_DIROPT && !diropt_ok(g, algo, o.mode)) {
+        o.sched = algo == GG_ALGO_CC ? GG_SYNC : GG_ASYNC;
+        if (algo == GG_ALGO_CC && auto_mode) o.mode = GG_EDGE;
+    }
     if (auto_sched && o.sched == GG_NEARFAR && (algo != GG_ALGO_SSSP || o.mode != GG_VERTEX))
         o.sched = GG_ASYNC;
     // without the both-directions CSR only the edge sweep can run CC
@@ -267,7 +279,7 @@ int plan_make(gg_graph g, gg_ws ws, int algo, int source, const int* sources_dev
         return GG_ENOTSUP;
     if (o.delta < 0) return GG_EINVAL;
     const bool diropt = o.sched == GG_DIROPT;
-    if (diropt && (algo != GG_ALGO_BFS || o.mode != GG_VERTEX || !g->has_sym)) return GG_ENOTSUP;
+    if (diropt && !diropt_ok(g, algo, o.mode)) return GG_ENOTSUP;
     const Dev& dv = device();
     const int cap_blocks = o.max_blocks > 0 ? std::min(o.max_blocks, dv.max_blocks) : dv.max_blocks;
     auto grid = [&](long long units) {
@@ -290,6 +302,7 @@ int plan_make(gg_graph g, gg_ws ws, int algo, int source, const int* sources_dev
     // default bucket width: a few mean weights (one bucket then spans paths
     // of several light edges)
     R.delta = nearfar ? std::max(1, o.delta) : 0;
+    R.fedges = p.cc && diropt;
 
     const int wpb = kBlock / 64;
     const long long n = g->n;
@@ -304,6 +317,8 @@ int plan_make(gg_graph g, gg_ws ws, int algo, int source, const int* sources_dev
         else p.g_round = grid((n + wpb - 1) / wpb);
     } else if (!p.async && p.edge) {
         p.g_round = grid((g->m / 4 + kBlock - 1) / kBlock);
+    } else if (diropt && p.cc) {
+        p.g_round = grid(std::max(ngroups * kParts / wpb + 1, (g->m / 4 + kBlock - 1) / kBlock));
     } else if (diropt) {
         p.g_round = grid(std::max(ngroups * kParts, ntiles) / wpb + 1);
     } else {
@@ -311,7 +326,7 @@ int plan_make(gg_graph g, gg_ws ws, int algo, int source, const int* sources_dev
     }
     p.need_heavy = p.async && (p.edge || diropt || o.mapping == GG_MAP_BALANCED) && nh > 0;
     p.g_heavy = grid((nh + 64LL * wpb - 1) / (64LL * wpb));
-    p.need_jump = p.cc && p.edge && !p.async && R.jump;
+    p.need_jump = p.cc && p.edge && (!p.async || diropt) && R.jump;
     p.g_jump = grid((n + kBlock - 1) / kBlock);
     return GG_OK;
 }
@@ -356,6 +371,7 @@ hipError_t plan_round(Plan& p, int r, int stamp) {
     R.r = r;
     R.stamp = stamp;
     hipError_t e = plan_launch(p, KIND_ROUND, [&] {
+        if (p.diropt && p.cc) return launch_cc_diropt(R, p.g_round, kBlock, p.s);
         if (p.diropt) return launch_bfs_diropt(R, p.g_round, kBlock, p.s);
         if (!p.async && !p.edge) return launch_vsync(R, p.algo, p.g_round, kBlock, p.s);
         if (!p.async) return launch_esync(R, p.algo, p.g_round, kBlock, p.s);
@@ -851,6 +867,7 @@ int gg_last_profile(gg_graph g, gg_ws ws, gg_profile* out) {
             out->kind[kind].vertices_processed += x.verts;
             out->kind[kind].updates += x.updates;
             out->kind[kind].pushes += x.pushes;
+            out->kind[kind].swept_edges += x.swept;
         }
     return GG_OK;
 }

@@ -32,7 +32,7 @@ struct Ctl {
     int near_[4];    // near-far schedule: [r % 3] = round r pushed below its bound
     int grid[4];     // [r % 3] = grid of round r's round kernel (push counts below)
     int hgrid[4];    // [r % 3] = grid of round r's heavy kernel
-    int pull[4];     // direction-optimizing BFS: [r % 3] = round r pulled
+    int pull[4];     // [r % 3] = round r took the dense form (BFS pull, CC edge sweep)
     int pad[2];
 };
 
@@ -40,6 +40,7 @@ struct Ctl {
 // kMaxStatBlocks slots per kernel kind.
 struct Stat {
     long long edges, verts, updates, pushes;
+    long long swept;  // edges read by the sweeps of a per-round CC schedule
 };
 
 // Device view of an uploaded graph.  Arrays are owned by the host-side
@@ -80,7 +81,8 @@ struct DevWs {
     int* hstamp;  // [n]: stamp of the last round that had the row on its frontier
     Ctl* ctl;
     Stat* stat;
-    int* pcount;  // [3][2][kMaxStatBlocks]: pushes per block of round r % 3 (round, heavy)
+    int* pcount;  // [3][2][kMaxStatBlocks]: frontier size pushed per block of round r % 3
+                  // (round, heavy): vertices, or with Round::fedges their row lengths
 };
 
 // Everything a round kernel needs.  Passed by value.
@@ -98,6 +100,8 @@ struct Round {
     int mapping; // Map
     int jump;    // CC: apply the label[label[v]] shortcut
     int delta;   // SSSP near-far schedule: bucket width (0 = plain worklist rounds)
+    int fedges;  // CC per-round dense/sparse choice: push counts are the row lengths
+                 // (both-directions CSR) of the pushed vertices, and edge sweeps push
 };
 
 // Launch entry points (gg_kernels.hip).  Each returns the hipError_t of the
@@ -111,6 +115,7 @@ hipError_t launch_easync(const Round& R, int algo, int grid, int block, hipStrea
 hipError_t launch_heavy(const Round& R, int algo, int grid, int block, hipStream_t s);
 hipError_t launch_bfs_diropt(const Round& R, int grid, int block, hipStream_t s);
 hipError_t launch_jump(const Round& R, int grid, int block, hipStream_t s);
+hipError_t launch_cc_diropt(const Round& R, int grid, int block, hipStream_t s);
 
 // Graph build helpers (gg_kernels.hip).
 hipError_t launch_fill_src(const int* row, int n, int* src, int grid, int block, hipStream_t s);

@@ -43,6 +43,10 @@ constexpr int kBatch = 4;
 // n / kPullRatio vertices.
 constexpr int kPullRatio = 20;
 
+// CC with the per-round choice sweeps every edge while the rows of the
+// frontier hold more than (both-directions edges) / kSweepRatio edges.
+constexpr int kSweepRatio = 8;
+
 // ------------------------------------------------------------ helpers ----
 
 __device__ __forceinline__ int wave_incl_scan(int x) {
@@ -65,7 +69,33 @@ __device__ __forceinline__ int wave_sum(int x) {
 struct Acc {
     int e = 0, v = 0, u = 0, p = 0;
     int nr = 0;  // near-far: pushed a distance below the round's bound
+    int f = 0;   // row lengths of the pushed vertices (Round::fedges), saturating
+    int d = 0;   // edges read by a sweep of the per-round CC schedule
+    __device__ void add_f(int d) { f = f > (1 << 30) - d ? 1 << 30 : f + d; }
 };
+
+// Frontier size of round r-1 as its kernels recorded it: the sum of the
+// per-block push counts of its round and heavy kernels.  Every block reads
+// the same slots, so the result is the same grid-wide.
+__device__ long long prev_front(const Round& R) {
+    const Ctl* ctl = R.ws.ctl;
+    const int slot = (R.r - 1) % 3;
+    const int gr = *(volatile const int*)&ctl->grid[slot];
+    const int gh = *(volatile const int*)&ctl->hgrid[slot];
+    __shared__ long long s_sum[4];
+    long long part = 0;
+    for (int b = threadIdx.x; b < gr; b += blockDim.x)
+        part += R.ws.pcount[(slot * 2 + KIND_ROUND) * kMaxStatBlocks + b];
+    for (int b = threadIdx.x; b < gh; b += blockDim.x)
+        part += R.ws.pcount[(slot * 2 + KIND_HEAVY) * kMaxStatBlocks + b];
+    for (int d = 32; d > 0; d >>= 1) part += __shfl_xor(part, d, 64);
+    if ((threadIdx.x & 63) == 0) s_sum[threadIdx.x >> 6] = part;
+    __syncthreads();
+    long long front = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) front += s_sum[i];
+    __syncthreads();
+    return front;
+}
 
 // Round entry, uniform over the whole grid.  Returns false when the
 // traversal has finished: either an earlier round set `done`, or round r-1
@@ -116,25 +146,35 @@ __device__ __forceinline__ void nearfar_finish(const Round& R, const Acc& acc) {
 }
 
 // Block-level reduction of the lane counters; one plain update of this
-// block's statistics slot and, when anything changed, of the round's flag.
-__device__ void block_finish(const Round& R, const Acc& a, int slot, int kind) {
-    __shared__ long long s_acc[4][4];
+// block's statistics slot (row `kind`) and, when anything changed, of the
+// round's flag.  The block's frontier count goes to push-count row `pk`: the
+// kind's own row by default, none for the auxiliary kind.
+__device__ void block_finish(const Round& R, const Acc& a, int slot, int kind, int pk = -1) {
+    __shared__ long long s_acc[4][6];
     int e = wave_sum(a.e), v = wave_sum(a.v), u = wave_sum(a.u), p = wave_sum(a.p);
+    int dd = wave_sum(a.d);
+    long long f = a.f;
+    for (int d = 32; d > 0; d >>= 1) f += __shfl_xor(f, d, 64);
     const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
     if ((threadIdx.x & 63) == 0) {
         s_acc[wid][0] = e;
         s_acc[wid][1] = v;
         s_acc[wid][2] = u;
         s_acc[wid][3] = p;
+        s_acc[wid][4] = f;
+        s_acc[wid][5] = dd;
     }
     __syncthreads();
+    if (pk < 0 && kind != KIND_AUX) pk = kind;
     if (threadIdx.x == 0) {
-        long long E = 0, V = 0, U = 0, P = 0;
+        long long E = 0, V = 0, U = 0, P = 0, F = 0, D = 0;
         for (int i = 0; i < nw; ++i) {
             E += s_acc[i][0];
             V += s_acc[i][1];
             U += s_acc[i][2];
             P += s_acc[i][3];
+            F += s_acc[i][4];
+            D += s_acc[i][5];
         }
         if (E | V | U | P) {
             Stat* st = R.ws.stat + kind * kMaxStatBlocks + blockIdx.x;
@@ -142,14 +182,19 @@ __device__ void block_finish(const Round& R, const Acc& a, int slot, int kind) {
             st->verts += V;
             st->updates += U;
             st->pushes += P;
+            st->swept += D;
         }
         if (U > 0 || P > 0) R.ws.ctl->changed[slot] = 1;
-        // pushes of this block in this round (every block writes its slot)
-        if (kind != KIND_AUX)
-            R.ws.pcount[(slot * 2 + kind) * kMaxStatBlocks + blockIdx.x] = (int)P;
+        // frontier pushed by this block in this round (every block writes its
+        // slot): vertices, or their row lengths
+        if (pk >= 0) {
+            const long long c = R.fedges ? F : P;
+            R.ws.pcount[(slot * 2 + pk) * kMaxStatBlocks + blockIdx.x] =
+                (int)(c < 2147483647LL ? c : 2147483647LL);
+        }
         if (blockIdx.x == 0) {
-            if (kind == KIND_ROUND) R.ws.ctl->grid[slot] = gridDim.x;
-            if (kind == KIND_HEAVY) R.ws.ctl->hgrid[slot] = gridDim.x;
+            if (pk == KIND_ROUND) R.ws.ctl->grid[slot] = gridDim.x;
+            if (pk == KIND_HEAVY) R.ws.ctl->hgrid[slot] = gridDim.x;
         }
     }
 }
@@ -255,6 +300,7 @@ __device__ __forceinline__ void relax_batch(const Round& R, const int* col, cons
                 R.ws.vflag[nxt][t[j]] = 1;
                 R.ws.tflag[nxt][t[j] >> 6] = 1;
                 acc.p++;
+                if (A == CC && R.fedges) acc.add_f(R.g.srow[t[j] + 1] - R.g.srow[t[j]]);
                 // near-far: a new distance below the round's bound keeps the
                 // bound where it is for the next round
                 if (A == SSSP && (unsigned)sv[j] + (unsigned)wt[j] < (unsigned)bound) acc.nr = 1;
@@ -372,7 +418,7 @@ __global__ __launch_bounds__(256) void k_init(Round R, int algo, int async) {
             }
         }
     }
-    for (long long i = tid; i < kKinds * kMaxStatBlocks; i += tt) R.ws.stat[i] = Stat{0, 0, 0, 0};
+    for (long long i = tid; i < kKinds * kMaxStatBlocks; i += tt) R.ws.stat[i] = Stat{0, 0, 0, 0, 0};
     if (tid == 0) *R.ws.ctl = Ctl{};
 }
 
@@ -468,7 +514,17 @@ __global__ __launch_bounds__(256) void k_vsync(Round R) {
 // One edge of the synchronous edge sweep (Algorithm 2; the edge form of
 // Algorithm 3 for BFS; CC relaxes both directions of a stored edge unless
 // the input is symmetric, where the reverse edge is stored too).
-template <int A>
+// A CC sweep of the per-round schedule also puts every vertex it lowers on
+// the next round's frontier, with the vertex's row length counted.
+__device__ __forceinline__ void sweep_push(const Round& R, int x, Acc& acc) {
+    const int nxt = (R.r & 1) ^ 1;
+    R.ws.vflag[nxt][x] = 1;
+    R.ws.tflag[nxt][x >> 6] = 1;
+    acc.p++;
+    acc.add_f(R.g.srow[x + 1] - R.g.srow[x]);
+}
+
+template <int A, bool PUSH = false>
 __device__ __forceinline__ void edge_sync_one(const Round& R, int u, int t, int e, Acc& acc) {
     int* val = R.val;
     acc.e++;
@@ -490,17 +546,23 @@ __device__ __forceinline__ void edge_sync_one(const Round& R, int u, int t, int 
         const int lu = val[u], lt = val[t];
         if (lu < lt) {
             const int old = atomicMin(&val[t], lu);
-            if (lu < old) acc.u++;
+            if (lu < old) {
+                acc.u++;
+                if (PUSH) sweep_push(R, t, acc);
+            }
         } else if (lt < lu && !R.g.symmetric) {
             const int old = atomicMin(&val[u], lt);
-            if (lt < old) acc.u++;
+            if (lt < old) {
+                acc.u++;
+                if (PUSH) sweep_push(R, u, acc);
+            }
         }
     }
 }
 
 // Four consecutive edges [e, e+4) of an edge list (16-byte aligned), with
 // every value loaded before the first atomic.
-template <int A>
+template <int A, bool PUSH = false>
 __device__ __forceinline__ void edge_sync_four(const Round& R, const int* src, const int* col,
                                                const int* w, long long e, Acc& acc) {
     const DevGraph& g = R.g;
@@ -542,9 +604,15 @@ __device__ __forceinline__ void edge_sync_four(const Round& R, const int* src, c
                 }
             } else {
                 if (vu[j] < vt[j]) {
-                    if (vu[j] < atomicMin(&val[t[j]], vu[j])) acc.u++;
+                    if (vu[j] < atomicMin(&val[t[j]], vu[j])) {
+                        acc.u++;
+                        if (PUSH) sweep_push(R, t[j], acc);
+                    }
                 } else if (vt[j] < vu[j] && !g.symmetric) {
-                    if (vt[j] < atomicMin(&val[u[j]], vt[j])) acc.u++;
+                    if (vt[j] < atomicMin(&val[u[j]], vt[j])) {
+                        acc.u++;
+                        if (PUSH) sweep_push(R, u[j], acc);
+                    }
                 }
             }
         }
@@ -556,11 +624,9 @@ __device__ __forceinline__ void edge_sync_four(const Round& R, const int* src, c
 // round-robin, so each die gathers and updates the values of one slice of
 // the vertices only, and that slice stays in the die's own L2.  (Any grid
 // size is correct; a grid that is not a multiple of kXcd walks all parts.)
-template <int A>
-__global__ __launch_bounds__(256) void k_esync(Round R) {
-    if (!round_begin(R)) return;
+template <int A, bool PUSH>
+__device__ __forceinline__ void esync_body(const Round& R, Acc& acc) {
     const DevGraph& g = R.g;
-    Acc acc;
     if (g.psrc) {
         const bool split = gridDim.x >= kXcd && gridDim.x % kXcd == 0;
         const int p0 = split ? (int)(blockIdx.x % kXcd) : 0;
@@ -571,7 +637,7 @@ __global__ __launch_bounds__(256) void k_esync(Round R) {
             const long long e1 = g.poff[p + 1];
             for (long long e = g.poff[p] + (bi * blockDim.x + threadIdx.x) * 4; e < e1;
                  e += bpp * blockDim.x * 4)
-                edge_sync_four<A>(R, g.psrc, g.pcol, g.pw, e, acc);
+                edge_sync_four<A, PUSH>(R, g.psrc, g.pcol, g.pw, e, acc);
         }
     } else {
         const int m = g.m;
@@ -579,10 +645,17 @@ __global__ __launch_bounds__(256) void k_esync(Round R) {
         const long long tt = (long long)gridDim.x * blockDim.x;
         const int m4 = m & ~3;
         for (long long e = tid * 4; e < m4; e += tt * 4)
-            edge_sync_four<A>(R, g.src, g.col, g.w, e, acc);
+            edge_sync_four<A, PUSH>(R, g.src, g.col, g.w, e, acc);
         for (long long e = m4 + tid; e < m; e += tt)
-            edge_sync_one<A>(R, g.src[e], g.col[e], (int)e, acc);
+            edge_sync_one<A, PUSH>(R, g.src[e], g.col[e], (int)e, acc);
     }
+}
+
+template <int A>
+__global__ __launch_bounds__(256) void k_esync(Round R) {
+    if (!round_begin(R)) return;
+    Acc acc;
+    esync_body<A, false>(R, acc);
     block_finish(R, acc, R.r % 3, KIND_ROUND);
 }
 
@@ -590,8 +663,7 @@ __global__ __launch_bounds__(256) void k_esync(Round R) {
 // vertices; each wavefront scans 64 tile flags at a time and serves the
 // flagged tiles it finds.
 template <int A, int MAP>
-__global__ __launch_bounds__(256) void k_vasync(Round R) {
-    if (!round_begin(R)) return;
+__device__ __forceinline__ void vasync_body(const Round& R, Acc& acc, bool nf, int bound) {
     const DevGraph& g = R.g;
     const int* row = A == CC ? g.srow : g.row;
     const int* col = A == CC ? g.scol : g.col;
@@ -605,9 +677,6 @@ __global__ __launch_bounds__(256) void k_vasync(Round R) {
     const long long tw = (long long)gridDim.x * wpb;
     const long long ntiles = (n + 63) / 64;
     const long long nitems = (ntiles + 63) / 64 * kParts;
-    const bool nf = A == SSSP && MAP == MAP_BALANCED && R.delta > 0;
-    const int bound = nf ? nearfar_bound(R) : kInf;
-    Acc acc;
     for (long long it = gw; it < nitems; it += tw) {
         const long long st = it / kParts;
         const int part = (int)(it % kParts);
@@ -671,6 +740,15 @@ __global__ __launch_bounds__(256) void k_vasync(Round R) {
             }
         }
     }
+}
+
+template <int A, int MAP>
+__global__ __launch_bounds__(256) void k_vasync(Round R) {
+    if (!round_begin(R)) return;
+    const bool nf = A == SSSP && MAP == MAP_BALANCED && R.delta > 0;
+    const int bound = nf ? nearfar_bound(R) : kInf;
+    Acc acc;
+    vasync_body<A, MAP>(R, acc, nf, bound);
     if (nf) nearfar_finish(R, acc);
     block_finish(R, acc, R.r % 3, KIND_ROUND);
 }
@@ -773,23 +851,7 @@ __global__ __launch_bounds__(256) void k_bfs_diropt(Round R) {
     Ctl* ctl = R.ws.ctl;
     const int n = g.n;
     const int lev = R.r;
-    long long front = 1;  // round 0: the source
-    if (R.r > 0) {
-        const int slot = (R.r - 1) % 3;
-        const int gr = *(volatile int*)&ctl->grid[slot];
-        const int gh = *(volatile int*)&ctl->hgrid[slot];
-        __shared__ long long s_sum[4];
-        long long part = 0;
-        for (int b = threadIdx.x; b < gr; b += blockDim.x)
-            part += R.ws.pcount[(slot * 2 + KIND_ROUND) * kMaxStatBlocks + b];
-        for (int b = threadIdx.x; b < gh; b += blockDim.x)
-            part += R.ws.pcount[(slot * 2 + KIND_HEAVY) * kMaxStatBlocks + b];
-        for (int d = 32; d > 0; d >>= 1) part += __shfl_xor(part, d, 64);
-        if ((threadIdx.x & 63) == 0) s_sum[threadIdx.x >> 6] = part;
-        __syncthreads();
-        front = 0;
-        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) front += s_sum[i];
-    }
+    const long long front = R.r > 0 ? prev_front(R) : 1;  // round 0: the source
     const bool pull = front * kPullRatio > n;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctl->pull[R.r % 3] = pull;
@@ -916,8 +978,10 @@ __global__ __launch_bounds__(256) void k_heavy(Round R) {
     const int lane = threadIdx.x & 63;
     const bool nf = A == SSSP && R.delta > 0;
     const int bound = nf ? *(volatile int*)&ctl->bound[R.r % 3] : kInf;
-    // a pulling BFS round stamps no heavy row: nothing to serve
-    const bool pulled = A == BFS && *(volatile int*)&ctl->pull[R.r % 3] != 0;
+    // a pulling BFS round or a sweeping CC round stamps no heavy row:
+    // nothing to serve
+    const bool pulled =
+        (A == BFS || (A == CC && R.fedges)) && *(volatile int*)&ctl->pull[R.r % 3] != 0;
     Acc acc;
     // 64 chunk stamps are checked at once, then the wavefront serves the
     // chunks that match in turn.  The 64 chunks of one check are spread over
@@ -947,8 +1011,13 @@ __global__ __launch_bounds__(256) void k_heavy(Round R) {
 }
 
 // CC shortcut pass used after an edge sweep: label[v] = label[label[v]].
+// Under the per-round schedule it runs after sweeping rounds only, puts the
+// vertices it lowers on the next frontier, and records that frontier in the
+// heavy kernel's push-count row (the heavy kernel idles in those rounds).
 __global__ __launch_bounds__(256) void k_jump(Round R) {
-    if (*(volatile int*)&R.ws.ctl->done) return;
+    const Ctl* ctl = R.ws.ctl;
+    if (*(volatile const int*)&ctl->done) return;
+    if (R.fedges && *(volatile const int*)&ctl->pull[R.r % 3] == 0) return;
     const int n = R.g.n;
     const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long tt = (long long)gridDim.x * blockDim.x;
@@ -958,10 +1027,50 @@ __global__ __launch_bounds__(256) void k_jump(Round R) {
         const int y = R.val[x];
         if (y < x) {
             const int old = atomicMin(&R.val[v], y);
-            if (y < old) acc.u++;
+            if (y < old) {
+                acc.u++;
+                if (R.fedges) sweep_push(R, (int)v, acc);
+            }
         }
     }
-    block_finish(R, acc, R.r % 3, KIND_AUX);
+    block_finish(R, acc, R.r % 3, KIND_AUX, R.fedges ? KIND_HEAVY : -1);
+}
+
+// CC with a per-round choice between the two schedules of the paper (a
+// topology-driven sweep, Algorithm 2's edge form, and the data-driven
+// worklist of Sec. 3.3).  Round r sweeps every stored edge while the rows of
+// the frontier left by round r-1 hold more than 1/kSweepRatio of the
+// both-directions edges (always in round 0), else it serves that frontier
+// from the both-directions CSR.  A sweep puts every vertex it lowers on the
+// next frontier (so a later worklist round sees every vertex whose value
+// changed after its edges were last read) and clears the frontier it skips.
+__global__ __launch_bounds__(256) void k_cc_diropt(Round R) {
+    if (!round_begin(R)) return;
+    Ctl* ctl = R.ws.ctl;
+    const long long front = R.r > 0 ? prev_front(R) : (long long)R.g.ms;
+    const bool sweep = front * kSweepRatio > (long long)R.g.ms || R.r == 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->pull[R.r % 3] = sweep;
+        ctl->hgrid[R.r % 3] = 0;  // rewritten by this round's heavy or shortcut kernel
+    }
+    Acc acc;
+    if (sweep) {
+        // the frontier generation of this round is not read: clear it (the
+        // flag arrays are padded to whole groups of 64 tiles, 16-byte aligned)
+        const int cur = R.r & 1;
+        const long long groups = ((long long)R.g.n + 4095) / 4096;
+        const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+        const long long tt = (long long)gridDim.x * blockDim.x;
+        uint4* vf = reinterpret_cast<uint4*>(R.ws.vflag[cur]);
+        uint4* tf = reinterpret_cast<uint4*>(R.ws.tflag[cur]);
+        for (long long i = tid; i < groups * 256; i += tt) vf[i] = make_uint4(0, 0, 0, 0);
+        for (long long i = tid; i < groups * 4; i += tt) tf[i] = make_uint4(0, 0, 0, 0);
+        esync_body<CC, true>(R, acc);
+        acc.d = acc.e;
+    } else {
+        vasync_body<CC, MAP_BALANCED>(R, acc, false, kInf);
+    }
+    block_finish(R, acc, R.r % 3, KIND_ROUND);
 }
 
 // ------------------------------------------------------- graph build ----
@@ -1094,6 +1203,10 @@ hipError_t launch_heavy(const Round& R, int algo, int grid, int block, hipStream
 
 hipError_t launch_bfs_diropt(const Round& R, int grid, int block, hipStream_t s) {
     GG_LAUNCH(k_bfs_diropt, grid, block, s, R);
+}
+
+hipError_t launch_cc_diropt(const Round& R, int grid, int block, hipStream_t s) {
+    GG_LAUNCH(k_cc_diropt, grid, block, s, R);
 }
 
 hipError_t launch_jump(const Round& R, int grid, int block, hipStream_t s) {

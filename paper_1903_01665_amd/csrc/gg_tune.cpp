@@ -19,7 +19,8 @@ bool valid(const gg_tune_entry& e) {
            (e.mode == GG_VERTEX || e.mode == GG_EDGE) &&
            (e.sched == GG_SYNC || e.sched == GG_ASYNC ||
             (e.sched == GG_NEARFAR && e.algo == GG_ALGO_SSSP && e.mode == GG_VERTEX) ||
-            (e.sched == GG_DIROPT && e.algo == GG_ALGO_BFS && e.mode == GG_VERTEX)) &&
+            (e.sched == GG_DIROPT && e.algo == GG_ALGO_BFS && e.mode == GG_VERTEX) ||
+            (e.sched == GG_DIROPT && e.algo == GG_ALGO_CC && e.mode == GG_EDGE)) &&
            e.mapping >= GG_MAP_AUTO && e.mapping <= GG_MAP_BALANCED && e.delta_mult >= 0 &&
            e.delta_mult <= 1 << 20;
 }

@@ -92,7 +92,8 @@ class QueryResult(ctypes.Structure):
 class KindProfile(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int32), ("total_ms", ctypes.c_float),
                 ("edges_processed", ctypes.c_int64), ("vertices_processed", ctypes.c_int64),
-                ("updates", ctypes.c_int64), ("pushes", ctypes.c_int64)]
+                ("updates", ctypes.c_int64), ("pushes", ctypes.c_int64),
+                ("swept_edges", ctypes.c_int64)]
 
 
 class Profile(ctypes.Structure):

@@ -285,6 +285,55 @@ def test_diropt_bfs(gg):
         g.free()
 
 
+def test_diropt_cc(gg):
+    """CC with the per-round choice (edge sweeps while the frontier is large,
+    then the worklist) gives the minimum-id labels, with and without the
+    shortcut, at any grid size; on a skewed graph both forms run."""
+    rng = np.random.default_rng(78)
+    graphs = [read_golden(f)[0] for f in golden_files()]
+    for i in range(8):
+        n = int(rng.integers(1, 400))
+        graphs.append(random_graph(rng, n, int(rng.integers(0, 3 * n + 1)), 1, 9, name=f"dc{i}"))
+    graphs += [gen.workload("er16k"), gen.workload("grid96"), gen.workload("rmat14"),
+               gen.workload("rmat12"), path_graph(300, np.ones(299)), gen.workload("rmat16")]
+    for hg in graphs:
+        want = oracle.cc(hg.n, hg.row_ptr, hg.col)
+        g = gg.Graph.from_host(hg, symmetrize=True)
+        try:
+            caps = (0, 8, 7, 1) if hg.m >= 1 << 20 else (0, 3)
+            for cap in caps:
+                for flags in (0, gg.OPT_CC_NO_JUMP):
+                    say(f"[gpu] cc diropt {hg.name} n={hg.n} m={hg.m} cap={cap} flags={flags}")
+                    o = gg.make_opts(EDGE, gg.DIROPT, max_blocks=cap, flags=flags)
+                    for rep in range(2):
+                        got = g.cc(opts=o).cpu().numpy()[: hg.n]
+                        assert g.stats()["rc"] == 0
+                        np.testing.assert_array_equal(got, want, err_msg=hg.name)
+            if hg.name in ("rmat14", "rmat16"):
+                o = gg.make_opts(EDGE, gg.DIROPT, flags=gg.OPT_PROFILE)
+                np.testing.assert_array_equal(g.cc(opts=o).cpu().numpy(), want)
+                pr = g.profile()
+                # a sweep reads every stored edge; a worklist round serves vertices
+                assert pr["round"]["swept_edges"] >= hg.m, pr
+                assert pr["round"]["vertices_processed"] > 0, pr
+                assert pr["round"]["edges_processed"] > pr["round"]["swept_edges"], pr
+            # a vertex-based mode is refused; AUTO takes the edge mode
+            with pytest.raises(gg.GGError):
+                g.cc(VERTEX, gg.DIROPT)
+            np.testing.assert_array_equal(g.cc(gg.MODE_AUTO, gg.DIROPT).cpu().numpy()[: hg.n],
+                                          want)
+        finally:
+            g.free()
+    # without the both-directions CSR the schedule is refused
+    hg = gen.workload("er300x900")
+    g = gg.Graph(hg.n, hg.row_ptr, hg.col, hg.w)
+    try:
+        with pytest.raises(gg.GGError):
+            g.cc(EDGE, gg.DIROPT)
+    finally:
+        g.free()
+
+
 def test_partitioned_edge_sweep(gg):
     """Graphs with >= 2^20 edges sweep a head-partitioned edge list, one part
     per die; any grid size gives the same result."""
