@@ -140,7 +140,10 @@ def main():
     ap.add_argument("--reps", type=int, default=3, help="repeats per variant in the table")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration)")
-    ap.add_argument("--config", default="single", choices=["single", "batched", "serve"])
+    ap.add_argument("--config", default="single",
+                    choices=["single", "batched", "serve", "concurrent"])
+    ap.add_argument("--workloads", default="er16k,rmat16,rmat22",
+                    help="concurrent: workloads to run")
     ap.add_argument("--instances", type=int, default=512, help="batched: instance count")
     ap.add_argument("--duration", type=float, default=12.0, help="serve: trace seconds")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: queries per second")
@@ -155,6 +158,8 @@ def main():
         return bench_batched(args)
     if args.config == "serve":
         return bench_serve(args)
+    if args.config == "concurrent":
+        return bench_concurrent(args)
 
     import torch
 
@@ -428,6 +433,73 @@ def bench_batched(args):
                 speedup_vs_plain=round(tp / tb, 3), results_identical_to_plain=same)
 
 
+def bench_concurrent(args):
+    """SSSP and BFS from the same source on one resident graph: one after the
+    other on one stream, or at the same time on two streams with a workspace
+    each and no barrier between them (the paper's barrier-free independent
+    kernels, Sec. 3.2)."""
+    import threading
+
+    import torch
+
+    from paper_1903_01665_amd import gen, gg
+
+    per = {}
+    tot_e = tot_t = 0.0
+    for w in args.workloads.split(","):
+        hg = gen.workload(w)
+        g = gg.Graph.from_host(hg, symmetrize=True)
+        s = int(gen.pick_sources(hg, 1, stream=gen.STREAM["sources"])[0])
+        deg = hg.degrees()
+        ws = [gg.Workspace(g), gg.Workspace(g)]
+        st = [torch.cuda.Stream(), torch.cuda.Stream()]
+        outs = [torch.empty(hg.n, dtype=torch.int32, device="cuda") for _ in range(4)]
+        calls = [lambda: g.sssp(s, out=outs[0], ws=ws[0], stream=st[0]),
+                 lambda: g.bfs(s, out=outs[1], ws=ws[1], stream=st[1])]
+
+        def seq():
+            g.sssp(s, out=outs[2], ws=ws[0], stream=st[0])
+            g.bfs(s, out=outs[3], ws=ws[0], stream=st[0])
+            torch.cuda.synchronize()
+
+        def both():
+            th = threading.Thread(target=calls[1])
+            th.start()
+            calls[0]()
+            th.join()
+            torch.cuda.synchronize()
+
+        reps = max(args.steps, 200 if hg.m < 1 << 20 else 10)
+        res = {}
+        for name, fn in (("sequential", seq), ("concurrent", both)):
+            for _ in range(max(1, args.warmup)):
+                fn()
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                fn()
+                ts.append(time.perf_counter() - t0)
+            res[name] = float(np.median(ts))
+        same = bool(torch.equal(outs[0], outs[2]) and torch.equal(outs[1], outs[3]))
+        d = outs[0].cpu().numpy()
+        edges = 2 * traversed_edges(deg, d)  # SSSP and BFS reach the same vertices
+        per[w] = {"sequential_ms": round(res["sequential"] * 1e3, 4),
+                  "concurrent_ms": round(res["concurrent"] * 1e3, 4),
+                  "speedup": round(res["sequential"] / res["concurrent"], 3),
+                  "GTEPS_concurrent": round(edges / res["concurrent"] / 1e9, 3),
+                  "results_identical": same, "reps": reps}
+        log(f"[bench] concurrent {w}: seq {res['sequential'] * 1e3:.3f} ms, "
+            f"two streams {res['concurrent'] * 1e3:.3f} ms, same={same}")
+        tot_e += edges
+        tot_t += res["concurrent"]
+        for x in ws:
+            x.free()
+        g.free()
+    common_line(args, "GTEPS SSSP+BFS on two streams", tot_e / tot_t / 1e9, "GTEPS",
+                tot_t * 1e3, {"workload": "concurrent-" + args.workloads.replace(",", "+")},
+                per_workload=per)
+
+
 def bench_serve(args):
     """Poisson trace served with continuous batching vs one query at a time."""
     import torch
@@ -457,18 +529,26 @@ def bench_serve(args):
         g.free()
     edges = sum(trav[int(gi)][int(s)] for gi, s in zip(trace.graph, trace.source))
     log(f"[bench] trace: {len(trace.t)} queries over {args.duration}s, {edges} traversed edges")
+    svc_s = np.full(len(trace.t), np.nan)
     lat_s, st, wall_s = serve.run_served(hosts, trace, slots=args.slots,
-                                         upload_every=upload_every, n_pool=n_pool)
+                                         upload_every=upload_every, n_pool=n_pool, service=svc_s)
     ok = int((st == 0).sum())
     log(f"[bench] served: wall {wall_s:.2f}s p50 {serve.percentile(lat_s, 50) * 1e3:.2f} ms "
-        f"p99 {serve.percentile(lat_s, 99) * 1e3:.2f} ms ({ok}/{len(st)} ok)")
+        f"p99 {serve.percentile(lat_s, 99) * 1e3:.2f} ms ({ok}/{len(st)} ok), "
+        f"service mean {np.nanmean(svc_s) * 1e3:.3f} ms")
+    svc_p = np.full(len(trace.t), np.nan)
     if args.no_plain:
         lat_p, wall_p = np.array([np.nan]), float("nan")
     else:
-        lat_p, wall_p = serve.run_plain(hosts, trace, n_pool=n_pool, upload_every=upload_every)
+        lat_p, wall_p = serve.run_plain(hosts, trace, n_pool=n_pool, upload_every=upload_every,
+                                        service=svc_p)
         log(f"[bench] plain: wall {wall_p:.2f}s p50 {serve.percentile(lat_p, 50) * 1e3:.2f} ms "
-            f"p99 {serve.percentile(lat_p, 99) * 1e3:.2f} ms")
+            f"p99 {serve.percentile(lat_p, 99) * 1e3:.2f} ms, "
+            f"service mean {np.nanmean(svc_p) * 1e3:.3f} ms")
     q = lambda x, p: round(serve.percentile(x, p) * 1e3, 3)
+    sv = lambda x: {"mean": round(float(np.nanmean(x)) * 1e3, 4),
+                    "p50": round(float(np.nanpercentile(x, 50)) * 1e3, 4)} \
+        if np.isfinite(x).any() else None
     common_line(args, "GTEPS served (Poisson SSSP/BFS queries)", edges / wall_s / 1e9, "GTEPS",
                 wall_s * 1e3 / max(1, len(trace.t)),
                 {"workload": "serve-rmat-12..22", "graphs": n_pool, "uploads": n_up,
@@ -477,6 +557,7 @@ def bench_serve(args):
                 latency_ms={"served": {"p50": q(lat_s, 50), "p99": q(lat_s, 99)},
                             "plain": {"p50": q(lat_p, 50), "p99": q(lat_p, 99)}},
                 plain={"GTEPS": round(edges / wall_p / 1e9, 4), "wall_s": round(wall_p, 3)},
+                service_ms={"served": sv(svc_s), "plain": sv(svc_p)},
                 served_ok=ok, served_wall_s=round(wall_s, 3))
 
 

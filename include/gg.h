@@ -335,13 +335,14 @@ int gg_batch_free(gg_batch b);
 /* ---- Serving: SSSP/BFS queries admitted as they arrive (continuous
  * batching).  A server holds resident graphs (added after gg_graph_upload;
  * the server owns them from then on), a FIFO of submitted queries and a set
- * of slots.  gg_server_poll admits queued queries while a slot is free and
- * the per-query state of all admitted queries (a workspace: frontier flags
- * and round stamps, ~6 bytes per vertex) fits the memory budget, enqueues
- * each admitted query's rounds on the slot's own stream, and advances every
- * query in flight without blocking, so their kernels overlap on the device.
- * A query's result is bit-identical to the same call made alone.  The poll
- * loop is single-threaded; submit/add/remove may come from other threads. */
+ * of slots.  A driver thread of the server admits queued queries while a
+ * slot is free and the per-query state of all admitted queries (a
+ * workspace: frontier flags and round stamps, ~6 bytes per vertex) fits the
+ * memory budget, enqueues each admitted query's rounds on the slot's own
+ * stream, and launches a query's next batch of rounds as soon as its
+ * previous one completes, so the kernels of different queries overlap on
+ * the device.  A query's result is bit-identical to the same call made
+ * alone.  Every call may come from any thread. */
 typedef struct gg_server_s* gg_server;
 
 typedef struct {
@@ -369,8 +370,8 @@ int gg_server_remove_graph(gg_server s, int32_t graph_id);
 int gg_server_submit(gg_server s, int32_t graph_id, int32_t algo, int32_t source,
                      int32_t* out_dev, int64_t* query_id);
 
-/* Admit and advance; copies up to `cap` newly finished queries to results
- * and their count to *n_done.  Never blocks on the device. */
+/* Copies up to `cap` newly finished queries to results and their count to
+ * *n_done.  Never blocks on the device. */
 int gg_server_poll(gg_server s, gg_query_result* results, int32_t cap, int32_t* n_done);
 
 /* Queued, in-flight and retained-state counts, memory of in-flight state. */
@@ -379,7 +380,9 @@ int gg_server_state(gg_server s, int32_t* queued, int32_t* in_flight, int64_t* s
 /* Seconds on the server's clock (the clock of gg_query_result). */
 double gg_server_now(gg_server s);
 
-/* Wait for all work, free the graphs the server owns and the server. */
+/* Stop the driver thread (queries still queued are dropped), wait for the
+ * device work already enqueued, free the graphs the server owns and the
+ * server. */
 int gg_server_free(gg_server s);
 
 /* Human-readable status name. */

@@ -10,7 +10,10 @@ that the paper's fixpoint methods reach:
         nothing changes);
 * BFS   hop distance (Algorithm 3's level-synchronous fixpoint);
 * CC    smallest vertex id in the component of the graph with every edge taken
-        both ways (Sec. 4.1 names the algorithm, Sec. 2 the union-find Set).
+        both ways (Sec. 4.1 names the algorithm, Sec. 2 the union-find Set);
+* MSF   the minimum spanning forest of the graph with every stored edge taken
+        as undirected, edge keys (weight, edge index) so that it is unique
+        (Sec. 4.1 names MST); Kruskal with the union-find Set.
 
 Each returns a new int32 numpy array.  Brute-force variants and O(n+m)
 certificates are exposed for pinning and for checking full-size outputs.
@@ -45,6 +48,9 @@ def _load():
             "oracle_cc_warshall": [i32, vp, vp, vp],
             "oracle_check_sssp": [i32, vp, vp, vp, i32, vp],
             "oracle_check_cc": [i32, vp, vp, vp],
+            "oracle_msf": [i32, vp, vp, vp, vp, vp],
+            "oracle_msf_brute": [i32, vp, vp, vp, vp],
+            "oracle_check_msf": [i32, vp, vp, vp, vp],
         }
         for name, args in sigs.items():
             f = getattr(lib, name)
@@ -123,3 +129,33 @@ def check_cc(n, row_ptr, col, label) -> int:
     row_ptr, col, _ = _csr(row_ptr, col)
     label = np.ascontiguousarray(label, dtype=np.int32)
     return _load().oracle_check_cc(n, _p(row_ptr), _p(col), _p(label))
+
+
+def msf(n, row_ptr, col, w):
+    """(in_msf uint8[m], total weight) of the minimum spanning forest."""
+    row_ptr, col, w = _csr(row_ptr, col, w)
+    m = int(row_ptr[-1])
+    out = np.zeros(max(m, 1), np.uint8)
+    total = ctypes.c_int64()
+    rc = _load().oracle_msf(n, _p(row_ptr), _p(col), _p(w), _p(out), ctypes.byref(total))
+    if rc != 0:
+        raise ValueError(f"oracle_msf returned {rc}")
+    return out[:m], int(total.value)
+
+
+def msf_brute(n, row_ptr, col, w):
+    row_ptr, col, w = _csr(row_ptr, col, w)
+    m = int(row_ptr[-1])
+    out = np.zeros(max(m, 1), np.uint8)
+    rc = _load().oracle_msf_brute(n, _p(row_ptr), _p(col), _p(w), _p(out))
+    if rc != 0:
+        raise ValueError(f"oracle_msf_brute returned {rc}")
+    return out[:m]
+
+
+def check_msf(n, row_ptr, col, w, in_msf) -> int:
+    """0 when ``in_msf`` marks exactly the minimum spanning forest."""
+    row_ptr, col, w = _csr(row_ptr, col, w)
+    sel = np.zeros(max(len(in_msf), 1), np.uint8)
+    sel[: len(in_msf)] = np.asarray(in_msf, dtype=np.uint8)
+    return _load().oracle_check_msf(n, _p(row_ptr), _p(col), _p(w), _p(sel))

@@ -203,6 +203,123 @@ int oracle_cc(int32_t n, const int32_t* row_ptr, const int32_t* col, int32_t* la
     return 0;
 }
 
+/* ------------------------------------------------------------- MST ----- */
+/* Minimum spanning forest: the fourth algorithm of the evaluation (Sec. 4.1,
+ * Table 3); the DSL's Set type is a union-find structure (Sec. 2).  Every
+ * stored edge e = (u, col[e]) with weight w[e] is taken as an undirected
+ * edge with key (w[e], e), compared as the 64-bit number w[e] * 2^32 + e.
+ * Keys are distinct, so the spanning forest of least key is unique; a
+ * self-loop never belongs to it.  Kruskal's algorithm: edges in increasing
+ * key order; an edge joins the forest when its ends lie in different sets. */
+
+static uint64_t msf_key(const int32_t* w, int64_t e) { return ((uint64_t)w[e] << 32) | (uint64_t)e; }
+
+static int cmp_u64(const void* a, const void* b) {
+    const uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+    return x < y ? -1 : x > y;
+}
+
+static int32_t* edge_sources(int32_t n, const int32_t* row_ptr) {
+    int32_t* src = (int32_t*)malloc(sizeof(int32_t) * (size_t)(row_ptr[n] + 1));
+    if (!src) return NULL;
+    for (int32_t u = 0; u < n; ++u)
+        for (int32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) src[e] = u;
+    return src;
+}
+
+int oracle_msf(int32_t n, const int32_t* row_ptr, const int32_t* col, const int32_t* w,
+               uint8_t* in_msf, int64_t* total_weight) {
+    if (!valid_csr(n, row_ptr, col, w) || !w || !in_msf) return -1;
+    const int64_t m = row_ptr[n];
+    uint64_t* keys = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(m + 1));
+    int32_t* src = edge_sources(n, row_ptr);
+    int32_t* parent = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t* size = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    if (!keys || !src || !parent || !size) {
+        free(keys);
+        free(src);
+        free(parent);
+        free(size);
+        return -3;
+    }
+    for (int64_t e = 0; e < m; ++e) {
+        keys[e] = msf_key(w, e);
+        in_msf[e] = 0;
+    }
+    qsort(keys, (size_t)m, sizeof(uint64_t), cmp_u64);
+    for (int32_t v = 0; v < n; ++v) {
+        parent[v] = v;
+        size[v] = 1;
+    }
+    int64_t total = 0;
+    for (int64_t i = 0; i < m; ++i) {
+        const int64_t e = (int64_t)(keys[i] & 0xffffffffu);
+        int32_t a = uf_find(parent, src[e]), b = uf_find(parent, col[e]);
+        if (a == b) continue;
+        if (size[a] < size[b]) {
+            int32_t t = a;
+            a = b;
+            b = t;
+        }
+        parent[b] = a;
+        size[a] += size[b];
+        in_msf[e] = 1;
+        total += w[e];
+    }
+    if (total_weight) *total_weight = total;
+    free(keys);
+    free(src);
+    free(parent);
+    free(size);
+    return 0;
+}
+
+/* Brute force (n <= 10, m <= 20, weights < 2^24): among all edge subsets
+ * with n - (number of components) edges and no cycle, the one of least
+ * summed key (exact, 128-bit). */
+int oracle_msf_brute(int32_t n, const int32_t* row_ptr, const int32_t* col, const int32_t* w,
+                     uint8_t* in_msf) {
+    if (!valid_csr(n, row_ptr, col, w) || !w || !in_msf || n > 10 || row_ptr[n] > 20) return -1;
+    const int32_t m = row_ptr[n];
+    int32_t src[20], parent[10];
+    for (int32_t u = 0; u < n; ++u)
+        for (int32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) src[e] = u;
+    for (int32_t e = 0; e < m; ++e)
+        if (w[e] >= (1 << 24)) return -1;
+    /* components of the whole graph */
+    for (int32_t v = 0; v < n; ++v) parent[v] = v;
+    int32_t comps = n;
+    for (int32_t e = 0; e < m; ++e) {
+        int32_t a = uf_find(parent, src[e]), b = uf_find(parent, col[e]);
+        if (a != b) {
+            parent[a] = b;
+            --comps;
+        }
+    }
+    const int32_t want = n - comps;
+    unsigned __int128 best = 0;
+    int64_t best_set = -1;
+    for (int64_t set = 0; set < ((int64_t)1 << m); ++set) {
+        if (__builtin_popcountll((unsigned long long)set) != want) continue;
+        for (int32_t v = 0; v < n; ++v) parent[v] = v;
+        int ok = 1;
+        unsigned __int128 sum = 0;
+        for (int32_t e = 0; e < m && ok; ++e) {
+            if (!((set >> e) & 1)) continue;
+            int32_t a = uf_find(parent, src[e]), b = uf_find(parent, col[e]);
+            if (a == b) ok = 0;
+            else parent[a] = b;
+            sum += msf_key(w, e);
+        }
+        if (ok && (best_set < 0 || sum < best)) {
+            best = sum;
+            best_set = set;
+        }
+    }
+    for (int32_t e = 0; e < m; ++e) in_msf[e] = best_set >= 0 ? (uint8_t)((best_set >> e) & 1) : 0;
+    return 0;
+}
+
 /* ----------------------------------------------------- brute force ----- */
 
 #define BRUTE_MAX_N 512
@@ -404,4 +521,155 @@ int oracle_check_cc(int32_t n, const int32_t* row_ptr, const int32_t* col, const
     free(queue);
     free(fill);
     return distinct == components ? 0 : 4;
+}
+
+/* MSF certificate.  The selected edges must form a forest (no self-loop, no
+ * cycle: 1), span every component of the graph (as many edges as vertices
+ * minus components, components counted by a breadth-first search over the
+ * undirected adjacency: 2), and every edge left out must close a cycle whose
+ * other edges all have smaller keys (the cycle property: 3).  Together these
+ * hold for exactly one edge set, the minimum spanning forest.  Path maxima
+ * come from binary lifting over each tree rooted by a breadth-first search. */
+int oracle_check_msf(int32_t n, const int32_t* row_ptr, const int32_t* col, const int32_t* w,
+                     const uint8_t* in_msf) {
+    if (!valid_csr(n, row_ptr, col, w) || !w || !in_msf) return -1;
+    const int64_t m = row_ptr[n];
+    int rc = 0;
+    int levels = 1;
+    while (((int64_t)1 << levels) < n) ++levels;
+    int32_t* src = edge_sources(n, row_ptr);
+    int32_t* uf = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    int64_t* start = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * ((size_t)n + 1));
+    int32_t* adj = (int32_t*)malloc(sizeof(int32_t) * (size_t)(2 * m + 1));
+    int64_t* adj_e = (int64_t*)malloc(sizeof(int64_t) * (size_t)(2 * m + 1));
+    int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t* depth = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t* up = (int32_t*)malloc(sizeof(int32_t) * (size_t)n * (size_t)levels);
+    uint64_t* mx = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)n * (size_t)levels);
+    if (!src || !uf || !start || !fill || !adj || !adj_e || !queue || !depth || !up || !mx) {
+        rc = -3;
+        goto done;
+    }
+    /* 1: a forest */
+    for (int32_t v = 0; v < n; ++v) uf[v] = v;
+    int64_t chosen = 0;
+    for (int64_t e = 0; e < m && !rc; ++e) {
+        if (!in_msf[e]) continue;
+        ++chosen;
+        const int32_t a = uf_find(uf, src[e]), b = uf_find(uf, col[e]);
+        if (a == b) rc = 1;
+        else uf[a] = b;
+    }
+    if (rc) goto done;
+    /* 2: spanning -- components of the whole graph by BFS */
+    for (int64_t e = 0; e < m; ++e) {
+        start[src[e] + 1]++;
+        start[col[e] + 1]++;
+    }
+    for (int32_t v = 0; v < n; ++v) start[v + 1] += start[v];
+    memcpy(fill, start, sizeof(int64_t) * (size_t)n);
+    for (int64_t e = 0; e < m; ++e) {
+        adj[fill[src[e]]] = col[e];
+        adj_e[fill[src[e]]++] = e;
+        adj[fill[col[e]]] = src[e];
+        adj_e[fill[col[e]]++] = e;
+    }
+    int64_t comps = 0;
+    for (int32_t v = 0; v < n; ++v) depth[v] = -1;
+    for (int32_t s0 = 0; s0 < n; ++s0) {
+        if (depth[s0] >= 0) continue;
+        ++comps;
+        int64_t head = 0, tail = 0;
+        depth[s0] = 0;
+        queue[tail++] = s0;
+        while (head < tail) {
+            const int32_t u = queue[head++];
+            for (int64_t k = start[u]; k < start[u + 1]; ++k)
+                if (depth[adj[k]] < 0) {
+                    depth[adj[k]] = 0;
+                    queue[tail++] = adj[k];
+                }
+        }
+    }
+    if (chosen != (int64_t)n - comps) {
+        rc = 2;
+        goto done;
+    }
+    /* 3: root every tree of the forest, then check each edge left out */
+    for (int32_t v = 0; v < n; ++v) depth[v] = -1;
+    for (int32_t r = 0; r < n; ++r) {
+        if (depth[r] >= 0) continue;
+        int64_t head = 0, tail = 0;
+        depth[r] = 0;
+        up[r] = r;
+        mx[r] = 0;
+        queue[tail++] = r;
+        while (head < tail) {
+            const int32_t u = queue[head++];
+            for (int64_t k = start[u]; k < start[u + 1]; ++k) {
+                const int64_t e = adj_e[k];
+                const int32_t v = adj[k];
+                if (!in_msf[e] || depth[v] >= 0) continue;
+                depth[v] = depth[u] + 1;
+                up[v] = u;
+                mx[v] = msf_key(w, e);
+                queue[tail++] = v;
+            }
+        }
+    }
+    for (int l = 1; l < levels; ++l)
+        for (int32_t v = 0; v < n; ++v) {
+            const int32_t h = up[(size_t)(l - 1) * n + v];
+            up[(size_t)l * n + v] = up[(size_t)(l - 1) * n + h];
+            const uint64_t a = mx[(size_t)(l - 1) * n + v], b = mx[(size_t)(l - 1) * n + h];
+            mx[(size_t)l * n + v] = a > b ? a : b;
+        }
+    for (int64_t e = 0; e < m && !rc; ++e) {
+        if (in_msf[e]) continue;
+        int32_t a = src[e], b = col[e];
+        if (a == b) continue;
+        uint64_t path = 0;
+        if (depth[a] < depth[b]) {
+            int32_t t = a;
+            a = b;
+            b = t;
+        }
+        for (int l = levels - 1; l >= 0; --l)
+            if (depth[a] - (1 << l) >= depth[b]) {
+                const uint64_t x = mx[(size_t)l * n + a];
+                if (x > path) path = x;
+                a = up[(size_t)l * n + a];
+            }
+        for (int l = levels - 1; l >= 0 && a != b; --l) {
+            const int32_t pa = up[(size_t)l * n + a], pb = up[(size_t)l * n + b];
+            if (pa != pb) {
+                if (mx[(size_t)l * n + a] > path) path = mx[(size_t)l * n + a];
+                if (mx[(size_t)l * n + b] > path) path = mx[(size_t)l * n + b];
+                a = pa;
+                b = pb;
+            }
+        }
+        if (a != b) {
+            if (mx[a] > path) path = mx[a];
+            if (mx[b] > path) path = mx[b];
+            a = up[a];
+            b = up[b];
+        }
+        /* a != b here would mean the ends lie in different trees, which the
+         * spanning check has ruled out */
+        if (a != b || path > msf_key(w, e)) rc = 3;
+    }
+done:
+    free(src);
+    free(uf);
+    free(start);
+    free(fill);
+    free(adj);
+    free(adj_e);
+    free(queue);
+    free(depth);
+    free(up);
+    free(mx);
+    return rc;
 }

@@ -6,7 +6,8 @@
  * header, helper or table with the GPU library; the two meet only through
  * the plain CSR arrays the input generator produces.
  *
- * Every function is a plain, sequential, obviously-correct CPU routine:
+ * Every function is a plain, sequential, obviously-correct CPU routine
+ * (and MSF, the minimum spanning forest, as below):
  *   - the paper's fixpoint methods (vertex/edge relaxation sweeps with an
  *     atomic MIN and a changed flag, Algorithms 1-2; level-synchronous BFS,
  *     Algorithm 3; CC by label propagation, named in Sec. 4.1) reach exactly
@@ -51,12 +52,23 @@ int oracle_bfs(int32_t n, const int32_t* row_ptr, const int32_t* col, int32_t so
  * undirected; label = smallest member id of the set. */
 int oracle_cc(int32_t n, const int32_t* row_ptr, const int32_t* col, int32_t* label);
 
+/* Minimum spanning forest (Kruskal; Sec. 4.1 names MST, Sec. 2 the
+ * union-find Set).  Every stored edge e is an undirected edge with key
+ * (w[e], e) -- distinct keys, so the forest is unique; self-loops are never
+ * in it.  in_msf: caller-owned uint8[m], 1 for the edges of the forest;
+ * *total_weight (nullable): their summed weight. */
+int oracle_msf(int32_t n, const int32_t* row_ptr, const int32_t* col, const int32_t* w,
+               uint8_t* in_msf, int64_t* total_weight);
+
 /* Brute force for tiny graphs (n <= 512). */
 int oracle_sssp_floyd_warshall(int32_t n, const int32_t* row_ptr, const int32_t* col,
                                const int32_t* w, int32_t source, int32_t* dist);
 int oracle_sssp_bellman_ford(int32_t n, const int32_t* row_ptr, const int32_t* col,
                              const int32_t* w, int32_t source, int32_t* dist);
 int oracle_cc_warshall(int32_t n, const int32_t* row_ptr, const int32_t* col, int32_t* label);
+/* Least-key spanning forest over all edge subsets (n <= 10, m <= 20, w < 2^24). */
+int oracle_msf_brute(int32_t n, const int32_t* row_ptr, const int32_t* col, const int32_t* w,
+                     uint8_t* in_msf);
 
 /* Certificates.
  * SSSP (w == NULL checks BFS levels, every weight taken as 1):
@@ -72,6 +84,11 @@ int oracle_cc_warshall(int32_t n, const int32_t* row_ptr, const int32_t* col, in
 int oracle_check_sssp(int32_t n, const int32_t* row_ptr, const int32_t* col, const int32_t* w,
                       int32_t source, const int32_t* dist);
 int oracle_check_cc(int32_t n, const int32_t* row_ptr, const int32_t* col, const int32_t* label);
+/* MSF: 1 the selected edges hold a self-loop or a cycle; 2 they do not span
+ * (their count differs from n minus the number of components); 3 an edge
+ * left out closes a cycle holding a larger key (cycle property). */
+int oracle_check_msf(int32_t n, const int32_t* row_ptr, const int32_t* col, const int32_t* w,
+                     const uint8_t* in_msf);
 
 #ifdef __cplusplus
 }

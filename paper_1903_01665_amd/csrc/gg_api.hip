@@ -628,7 +628,7 @@ int gg_graph_upload(int32_t n, int64_t m, const int32_t* row_ptr, const int32_t*
         return (int)std::max(1LL, std::min<long long>(units, device().max_blocks));
     };
     if (e == hipSuccess)
-        e = launch_fill_src(g->row, n, g->src, grid((ntiles + wpb - 1) / wpb), kBlock, s);
+        e = launch_fill_src(g->row, n, (int)m, g->src, grid((m + 4095) / 4096), kBlock, s);
     if (e != hipSuccess) return bail(e == hipErrorOutOfMemory ? GG_ENOMEM : GG_EHIP);
     if (on_dev) {
         // validate device input on the host after copying it back
@@ -710,7 +710,7 @@ int gg_graph_upload(int32_t n, int64_t m, const int32_t* row_ptr, const int32_t*
             e = launch_sym_fill(g->row, g->col, g->src, n, (int)m, g->srow, indeg, g->scol,
                                 grid((m + kBlock - 1) / kBlock), kBlock, s);
         if (e == hipSuccess)
-            e = launch_fill_src(g->srow, n, g->ssrc, grid((ntiles + wpb - 1) / wpb), kBlock, s);
+            e = launch_fill_src(g->srow, n, (int)ms, g->ssrc, grid((ms + 4095) / 4096), kBlock, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         dfree(indeg);
         if (e != hipSuccess) return bail(e == hipErrorOutOfMemory ? GG_ENOMEM : GG_EHIP);

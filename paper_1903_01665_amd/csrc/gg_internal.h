@@ -118,7 +118,8 @@ hipError_t launch_jump(const Round& R, int grid, int block, hipStream_t s);
 hipError_t launch_cc_diropt(const Round& R, int grid, int block, hipStream_t s);
 
 // Graph build helpers (gg_kernels.hip).
-hipError_t launch_fill_src(const int* row, int n, int* src, int grid, int block, hipStream_t s);
+hipError_t launch_fill_src(const int* row, int n, int m, int* src, int grid, int block,
+                           hipStream_t s);
 hipError_t launch_count_in(const int* col, int m, int* indeg, int grid, int block, hipStream_t s);
 hipError_t launch_sym_fill(const int* row, const int* col, const int* src, int n, int m,
                            const int* srow, int* cursor, int* scol, int grid, int block,

@@ -1075,20 +1075,71 @@ __global__ __launch_bounds__(256) void k_cc_diropt(Round R) {
 
 // ------------------------------------------------------- graph build ----
 
-__global__ __launch_bounds__(256) void k_fill_src(const int* row, int n, int* src) {
-    const int lane = threadIdx.x & 63;
-    const int wpb = blockDim.x >> 6;
-    const long long gw = (long long)blockIdx.x * wpb + (threadIdx.x >> 6);
-    const long long tw = (long long)gridDim.x * wpb;
-    const long long ntiles = (n + 63) / 64;
-    for (long long t = gw; t < ntiles; t += tw) {
-        const int u = (int)(t * 64 + lane);
-        int rb = 0, deg = 0;
-        if (u < n) {
-            rb = row[u];
-            deg = row[u + 1] - rb;
+// Edge-list sources: src[e] = the row u with row[u] <= e < row[u+1].  A
+// block takes kFillWin consecutive edges.  The row of the window's first edge
+// comes from a binary search of row[]; every row that starts inside the
+// window writes its number at its first edge (in LDS); a running maximum over
+// the window then carries each row number to the rest of its edges.  The
+// work per window is the same whatever the degrees are.
+constexpr int kFillWin = 4096;
+__device__ __forceinline__ int fill_slot(int i) { return i + (i >> 4); }  // 16 + 1 padding
+
+__device__ __forceinline__ int row_of_edge(const int* row, int n, long long e) {
+    // invariant row[lo] <= e < row[hi]; row[0] = 0 and row[n] = m > e
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = lo + ((hi - lo) >> 1);
+        if (row[mid] <= e) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_fill_src(const int* row, int n, int m, int* src) {
+    constexpr int PT = kFillWin / 256;
+    __shared__ int s_row[kFillWin + kFillWin / 16];
+    __shared__ int s_r[2];
+    __shared__ int s_wmax[4];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (long long wb = blockIdx.x; wb * kFillWin < m; wb += gridDim.x) {
+        const long long e0 = wb * kFillWin;
+        const int len = (int)min((long long)kFillWin, (long long)m - e0);
+        if (threadIdx.x < 2) s_r[threadIdx.x] = row_of_edge(row, n, threadIdx.x ? e0 + len - 1 : e0);
+        for (int i = threadIdx.x; i < kFillWin; i += 256) s_row[fill_slot(i)] = -1;
+        __syncthreads();
+        const int r0 = s_r[0], r1 = s_r[1];
+        // rows r0+1..r1 start inside the window, after its first edge
+        for (long long u = (long long)r0 + 1 + threadIdx.x; u <= r1; u += 256) {
+            const int b = row[u];
+            if (row[u + 1] > b) s_row[fill_slot((int)(b - e0))] = (int)u;
         }
-        wave_rows_balanced(rb, deg, u, [&](int e, int s) { src[e] = s; });
+        __syncthreads();
+        // thread t owns entries [t*PT, t*PT + PT): block-wide exclusive
+        // maximum of the per-thread maxima, then the running maximum
+        int mx = -1;
+#pragma unroll
+        for (int j = 0; j < PT; ++j) mx = max(mx, s_row[fill_slot(threadIdx.x * PT + j)]);
+        int x = mx;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(x, d, 64);
+            if (lane >= d) x = max(x, y);
+        }
+        if (lane == 63) s_wmax[wid] = x;
+        __syncthreads();
+        int c = r0;
+        for (int i = 0; i < wid; ++i) c = max(c, s_wmax[i]);
+        const int before = __shfl_up(x, 1, 64);
+        if (lane > 0) c = max(c, before);
+#pragma unroll
+        for (int j = 0; j < PT; ++j) {
+            const int k = fill_slot(threadIdx.x * PT + j);
+            c = max(c, s_row[k]);
+            s_row[k] = c;
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < len; i += 256) src[e0 + i] = s_row[fill_slot(i)];
+        __syncthreads();
     }
 }
 
@@ -1213,8 +1264,9 @@ hipError_t launch_jump(const Round& R, int grid, int block, hipStream_t s) {
     GG_LAUNCH(k_jump, grid, block, s, R);
 }
 
-hipError_t launch_fill_src(const int* row, int n, int* src, int grid, int block, hipStream_t s) {
-    GG_LAUNCH(k_fill_src, grid, block, s, row, n, src);
+hipError_t launch_fill_src(const int* row, int n, int m, int* src, int grid, int block,
+                           hipStream_t s) {
+    GG_LAUNCH(k_fill_src, grid, block, s, row, n, m, src);
 }
 
 hipError_t launch_count_in(const int* col, int m, int* indeg, int grid, int block, hipStream_t s) {

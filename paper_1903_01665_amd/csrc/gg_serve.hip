@@ -6,13 +6,18 @@
 // reused; the bytes of the workspaces held by queries in flight are bounded
 // by the memory budget.  Admission is first-come first-served: when the
 // head of the queue does not fit (no slot, or its state would exceed the
-// budget), later queries wait behind it.  Every poll advances each query in
-// flight by at most one batch of rounds, using non-blocking event queries,
-// so the kernels of different queries overlap on the device.
+// budget), later queries wait behind it.  A driver thread of the server
+// admits queries and advances each one in flight by a batch of rounds as
+// soon as its previous batch completes (non-blocking event queries), so the
+// kernels of different queries overlap on the device and no caller thread
+// sits on the path between two batches; gg_server_poll only hands out the
+// finished queries.
 
+#include <condition_variable>
 #include <deque>
 #include <map>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "gg_runtime.h"
@@ -51,7 +56,11 @@ long long ws_bytes_of(gg_graph g) {
 }  // namespace
 
 struct gg_server_s {
-    std::mutex mu;  // queue and graph table (submit/add/remove vs poll)
+    std::mutex mu;  // everything below (callers vs the driver thread)
+    std::condition_variable wake;  // work arrived, or stop
+    std::thread driver;
+    bool stop = false;
+    int device = 0;
     std::map<int, SGraph> graphs;
     int next_graph = 0;
     long long next_query = 0;
@@ -120,6 +129,85 @@ int admit(gg_server s, Query* q, SGraph& G) {
     return GG_OK;
 }
 
+// One pass of the driver with the lock held: admission (first come, first
+// served, while a slot and the memory budget allow), then every query in
+// flight advances by at most one batch.  Returns whether anything changed.
+bool step_locked(gg_server s) {
+    bool moved = false;
+    while (!s->queue.empty() && (int)s->active.size() < s->slots) {
+        Query* q = s->queue.front();
+        SGraph& G = s->graphs[q->graph_id];
+        if (s->budget > 0 && s->used + G.ws_bytes > s->budget && !s->active.empty()) break;
+        int rc = admit(s, q, G);
+        if (rc == GG_EBUSY) break;
+        s->queue.pop_front();
+        moved = true;
+        q->t_admit = s->now();
+        if (rc != GG_OK) {
+            // failed to start: report at once
+            q->t_done = q->t_admit;
+            s->finished.push_back(gg_query_result{q->id, rc, 0, q->t_submit, q->t_admit, q->t_done});
+            G.in_use--;
+            delete q;
+            continue;
+        }
+        s->used += G.ws_bytes;
+        s->active.push_back(q);
+    }
+    for (size_t i = 0; i < s->active.size();) {
+        Query* q = s->active[i];
+        const long long r_before = q->d.r;
+        const int rc = drive_step(q->d, false);
+        if (rc == 0) {
+            moved |= q->d.r != r_before;
+            ++i;
+            continue;
+        }
+        moved = true;
+        q->t_done = s->now();
+        const int status = rc < 0 ? rc : q->d.status;
+        Plan& p = q->d.p;
+        if (hipEventRecord(q->ws->finished, p.s) != hipSuccess && rc >= 0) {
+            // keep going: the status of this query reports the failure
+        }
+        record_last(p, status, q->d.r);
+        // stamps of the workspace's next query start after every round used
+        q->ws->epoch = std::max(q->ws->epoch,
+                                (int)std::min<long long>(q->d.stamp_base + q->d.r + 1, 1LL << 30));
+        SGraph& G = s->graphs[q->graph_id];
+        G.pool.push_back(q->ws);
+        s->used -= G.ws_bytes;
+        s->stream_busy[q->stream] = 0;
+        s->finished.push_back(gg_query_result{q->id, status, (int32_t)q->d.r, q->t_submit,
+                                              q->t_admit, q->t_done});
+        G.in_use--;
+        delete q;
+        s->active[i] = s->active.back();
+        s->active.pop_back();
+    }
+    return moved;
+}
+
+// The driver: sleeps while there is nothing to do; otherwise steps, and
+// between steps that change nothing releases the lock and yields (a batch
+// of rounds takes microseconds to milliseconds; polling keeps the gap
+// between a batch's end and the next launch short).
+void drive_loop(gg_server s) {
+    (void)hipSetDevice(s->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    while (!s->stop) {
+        if (s->queue.empty() && s->active.empty()) {
+            s->wake.wait(lk);
+            continue;
+        }
+        if (!step_locked(s)) {
+            lk.unlock();
+            std::this_thread::yield();
+            lk.lock();
+        }
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -133,13 +221,22 @@ int gg_server_create(int32_t slots, int64_t mem_budget_bytes, gg_server* out) {
     s->t0 = std::chrono::steady_clock::now();
     s->streams.assign(slots, nullptr);
     s->stream_busy.assign(slots, 0);
-    for (int i = 0; i < slots; ++i)
-        if (hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) != hipSuccess) {
-            for (hipStream_t st : s->streams)
-                if (st) (void)hipStreamDestroy(st);
-            delete s;
-            return GG_EHIP;
+    bool ok = hipGetDevice(&s->device) == hipSuccess;
+    for (int i = 0; ok && i < slots; ++i)
+        ok = hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) == hipSuccess;
+    if (ok) {
+        try {
+            s->driver = std::thread(drive_loop, s);
+        } catch (...) {
+            ok = false;
         }
+    }
+    if (!ok) {
+        for (hipStream_t st : s->streams)
+            if (st) (void)hipStreamDestroy(st);
+        delete s;
+        return GG_EHIP;
+    }
     *out = s;
     return GG_OK;
 }
@@ -187,61 +284,13 @@ int gg_server_submit(gg_server s, int32_t graph_id, int32_t algo, int32_t source
     it->second.in_use++;
     s->queue.push_back(q);
     if (query_id) *query_id = q->id;
+    s->wake.notify_one();
     return GG_OK;
 }
 
 int gg_server_poll(gg_server s, gg_query_result* results, int32_t cap, int32_t* n_done) {
     if (!s || cap < 0 || (cap > 0 && !results)) return GG_EINVAL;
     std::lock_guard<std::mutex> lk(s->mu);
-    // admission: first come, first served, while a slot and memory allow
-    while (!s->queue.empty() && (int)s->active.size() < s->slots) {
-        Query* q = s->queue.front();
-        SGraph& G = s->graphs[q->graph_id];
-        if (s->budget > 0 && s->used + G.ws_bytes > s->budget && !s->active.empty()) break;
-        int rc = admit(s, q, G);
-        if (rc == GG_EBUSY) break;
-        s->queue.pop_front();
-        q->t_admit = s->now();
-        if (rc != GG_OK) {
-            // failed to start: report at once
-            q->t_done = q->t_admit;
-            s->finished.push_back(gg_query_result{q->id, rc, 0, q->t_submit, q->t_admit, q->t_done});
-            G.in_use--;
-            delete q;
-            continue;
-        }
-        s->used += G.ws_bytes;
-        s->active.push_back(q);
-    }
-    // advance every query in flight by at most one batch
-    for (size_t i = 0; i < s->active.size();) {
-        Query* q = s->active[i];
-        const int rc = drive_step(q->d, false);
-        if (rc == 0) {
-            ++i;
-            continue;
-        }
-        q->t_done = s->now();
-        const int status = rc < 0 ? rc : q->d.status;
-        Plan& p = q->d.p;
-        if (hipEventRecord(q->ws->finished, p.s) != hipSuccess && rc >= 0) {
-            // keep going: the status of this query reports the failure
-        }
-        record_last(p, status, q->d.r);
-        // stamps of the workspace's next query start after every round used
-        q->ws->epoch = std::max(q->ws->epoch,
-                                (int)std::min<long long>(q->d.stamp_base + q->d.r + 1, 1LL << 30));
-        SGraph& G = s->graphs[q->graph_id];
-        G.pool.push_back(q->ws);
-        s->used -= G.ws_bytes;
-        s->stream_busy[q->stream] = 0;
-        s->finished.push_back(gg_query_result{q->id, status, (int32_t)q->d.r, q->t_submit,
-                                              q->t_admit, q->t_done});
-        G.in_use--;
-        delete q;
-        s->active[i] = s->active.back();
-        s->active.pop_back();
-    }
     int nd = 0;
     while (nd < cap && !s->finished.empty()) {
         results[nd++] = s->finished.front();
@@ -265,6 +314,12 @@ double gg_server_now(gg_server s) { return s ? s->now() : 0.0; }
 
 int gg_server_free(gg_server s) {
     if (!s) return GG_EINVAL;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->wake.notify_one();
+    if (s->driver.joinable()) s->driver.join();
     (void)hipDeviceSynchronize();
     for (Query* q : s->queue) delete q;
     for (Query* q : s->active) delete q;

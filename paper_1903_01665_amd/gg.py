@@ -441,8 +441,9 @@ class Server:
 
     ``add_graph`` hands an uploaded :class:`Graph` to the server (which owns
     it from then on); ``submit`` queues a query whose result goes to a
-    caller-owned int32 cuda tensor; ``poll`` admits, advances and returns the
-    queries that finished since the last poll.
+    caller-owned int32 cuda tensor; the server's own native thread admits and
+    advances queries; ``poll`` returns the queries that finished since the
+    last poll as (id, status, rounds, t_submit, t_admit, t_done).
     """
 
     def __init__(self, slots=16, mem_budget_bytes=0):

@@ -3,8 +3,9 @@
 Two ways to serve the same arrival trace:
 
 served  the continuous-batching server of libgg (gg_server_*): queries are
-        submitted at their arrival time, admitted while a slot and the memory
-        budget allow, and advanced together on a pool of streams; a new graph
+        submitted at their arrival time; the server's native driver thread
+        admits them while a slot and the memory budget allow and advances
+        them together on a pool of streams; a new graph
         is uploaded on a background thread every `upload_every` seconds and the
         oldest graph is retired (its queued queries still finish).
 plain   one query at a time in arrival order, each a blocking single-query
@@ -81,9 +82,11 @@ def percentile(x, q):
 
 
 def run_served(hosts, trace, slots=32, mem_budget=8 << 30, upload_every=5.0, n_pool=None,
-               log=None):
-    """Serve the trace; returns per-query latencies (s) in trace order and
-    the wall time of the run."""
+               log=None, service=None):
+    """Serve the trace; returns per-query latencies (s) in trace order, the
+    per-query status and the wall time of the run.  With `service` (an array
+    of the trace's length) the time from admission to completion of each
+    query is stored there."""
     import torch
     n_pool = n_pool or len(hosts)
     srv = gg.Server(slots, mem_budget)
@@ -152,6 +155,8 @@ def run_served(hosts, trace, slots=32, mem_budget=8 << 30, upload_every=5.0, n_p
             k, gi, b = inflight.pop(qid)
             lat[k] = tnow - trace.t[k]
             status[k] = st
+            if service is not None:
+                service[k] = td - ta
             free_bufs[gi].append(b)
             done += 1
         if not res and nxt < nq and trace.t[nxt] > now + 0.0005:
@@ -164,9 +169,10 @@ def run_served(hosts, trace, slots=32, mem_budget=8 << 30, upload_every=5.0, n_p
     return lat, status, wall
 
 
-def run_plain(hosts, trace, n_pool=None, upload_every=5.0):
+def run_plain(hosts, trace, n_pool=None, upload_every=5.0, service=None):
     """One blocking query at a time in arrival order, graphs uploaded when
-    they first appear in the trace (upload time not charged to queries)."""
+    they first appear in the trace (upload time not charged to queries).
+    With `service` the time of each call is stored there."""
     import torch
     graphs = {}
     lat = np.full(len(trace.t), np.nan)
@@ -186,12 +192,16 @@ def run_plain(hosts, trace, n_pool=None, upload_every=5.0):
         if now < trace.t[k]:
             time.sleep(trace.t[k] - now)
         g = graphs[gi]
+        tq = time.perf_counter()
         if trace.algo[k] == 0:
             g.sssp(int(trace.source[k]), out=out[gi])
         else:
             g.bfs(int(trace.source[k]), out=out[gi])
         torch.cuda.synchronize()
-        lat[k] = time.perf_counter() - t0 - upload_s - trace.t[k]
+        tn = time.perf_counter()
+        if service is not None:
+            service[k] = tn - tq
+        lat[k] = tn - t0 - upload_s - trace.t[k]
     wall = time.perf_counter() - t0 - upload_s
     for g in graphs.values():
         g.free()

@@ -11,8 +11,10 @@ import subprocess
 import numpy as np
 import pytest
 
+import oracle
 from helpers import random_graph
 from test_oracle import scipy_cc, scipy_sssp
+from test_oracle_msf import scipy_msf_weight
 
 pytestmark = pytest.mark.timeout(120)
 
@@ -38,6 +40,15 @@ MUTANTS = {
     "cc_max_label": ("if (v < minid[r]) minid[r] = v;", "if (minid[r] == n || v > minid[r]) minid[r] = v;"),
     "cc_self_union": ("int32_t a = uf_find(parent, u), b = uf_find(parent, col[e]);",
                       "int32_t a = uf_find(parent, u), b = uf_find(parent, u);"),
+    # MSF: edge index dropped from the key, order reversed, union skipped,
+    # one end of the edge taken twice
+    "msf_key_no_index": ("return ((uint64_t)w[e] << 32) | (uint64_t)e;",
+                         "return ((uint64_t)w[e] << 32);"),
+    "msf_descending": ("return x < y ? -1 : x > y;", "return x > y ? -1 : x < y;"),
+    "msf_no_union": ("parent[b] = a;\n        size[a] += size[b];\n        in_msf[e] = 1;",
+                     "size[a] += size[b];\n        in_msf[e] = 1;"),
+    "msf_same_end": ("int32_t a = uf_find(parent, src[e]), b = uf_find(parent, col[e]);",
+                     "int32_t a = uf_find(parent, src[e]), b = uf_find(parent, src[e]);"),
 }
 
 
@@ -51,7 +62,7 @@ def _build_mutant(tmp_path, name, old, new):
     subprocess.run(["gcc", "-O1", "-shared", "-fPIC", f"-I{hdr_dir}", str(src), "-o", str(so)],
                    check=True)
     lib = ctypes.CDLL(str(so))
-    for f in ("oracle_sssp", "oracle_bfs", "oracle_cc"):
+    for f in ("oracle_sssp", "oracle_bfs", "oracle_cc", "oracle_msf"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
@@ -77,6 +88,25 @@ def _pins_fail(lib) -> bool:
             return True
         if lib.oracle_cc(n, _p(row), _p(col), _p(out)) != 0 or \
                 not np.array_equal(out, scipy_cc(g)):
+            return True
+    # MSF against exhaustive search (tiny graphs) and scipy's weight
+    for i in range(60):
+        n = int(rng.integers(2, 9))
+        g = random_graph(rng, n, int(rng.integers(1, 15)), 1, 4)
+        sel = np.zeros(max(g.m, 1), np.uint8)
+        total = ctypes.c_int64()
+        if lib.oracle_msf(n, _p(g.row_ptr), _p(g.col), _p(g.w), _p(sel),
+                          ctypes.byref(total)) != 0:
+            return True
+        if not np.array_equal(sel[: g.m], oracle.msf_brute(g.n, g.row_ptr, g.col, g.w)):
+            return True
+    for i in range(20):
+        n = int(rng.integers(2, 200))
+        g = random_graph(rng, n, int(rng.integers(n, 4 * n)), 1, 99)
+        sel = np.zeros(max(g.m, 1), np.uint8)
+        total = ctypes.c_int64()
+        if lib.oracle_msf(n, _p(g.row_ptr), _p(g.col), _p(g.w), _p(sel),
+                          ctypes.byref(total)) != 0 or total.value != scipy_msf_weight(g):
             return True
     return False
 
