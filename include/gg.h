@@ -106,7 +106,10 @@ typedef enum { GG_ALGO_SSSP = 0, GG_ALGO_BFS = 1, GG_ALGO_CC = 2 } gg_algo;
 typedef struct gg_graph_s* gg_graph;
 typedef struct gg_ws_s* gg_ws;
 
-/* Per-call options.  Zero-initialise, then set what you need. */
+/* Per-call options.  Zero-initialise, then set what you need.  Note that a
+ * zeroed struct names vertex-based synchronous sweeps (GG_VERTEX and
+ * GG_SYNC are 0); GG_MODE_AUTO, GG_SCHED_AUTO and GG_MAP_AUTO ask for the
+ * tuned choice, and a NULL opts pointer asks for it in every field. */
 typedef struct {
     int32_t mode;          /* gg_mode */
     int32_t sched;         /* gg_sched */

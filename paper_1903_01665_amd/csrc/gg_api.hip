@@ -19,6 +19,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "gg_internal.h"
@@ -101,6 +102,7 @@ int make_ws(gg_graph g, gg_ws_s** out) {
     ws->dev.tflag[0] = ws->vflag_mem + 2 * vbytes;
     ws->dev.tflag[1] = ws->vflag_mem + 2 * vbytes + tbytes;
     ws->h_done[0] = -1;
+    *prog_word(ws) = 0;
     *out = ws;
     return GG_OK;
 }
@@ -213,7 +215,11 @@ bool diropt_ok(gg_graph g, int algo, int mode) {
 // AUTO fields resolve through the tuning table (else built-in rules) for
 // the graph's class; explicit fields are kept.
 void resolve(gg_graph g, int algo, const gg_opts* in, gg_opts* out) {
+    // no options: the tuned choice of every field
     gg_opts o{};
+    o.mode = GG_MODE_AUTO;
+    o.sched = GG_SCHED_AUTO;
+    o.mapping = GG_MAP_AUTO;
     if (in) o = *in;
     const bool auto_mode = o.mode != GG_VERTEX && o.mode != GG_EDGE;
     const bool auto_sched = o.sched != GG_SYNC && o.sched != GG_ASYNC && o.sched != GG_NEARFAR &&
@@ -438,7 +444,13 @@ int drive_enqueue(Drive& d) {
     Plan& p = d.p;
     const long long stop = std::min(d.r + d.batch, d.max_rounds);
     for (; d.r < stop; ++d.r) HIPCHK(p.g, plan_round(p, (int)d.r, d.stamp_base + (int)d.r));
-    HIPCHK(p.g, hipEventRecord(p.ws->ev[d.k & 1], p.s));
+    if (d.poll) {
+        const unsigned long long v = ++p.ws->prog_seq;
+        HIPCHK(p.g, launch_mark(prog_word(p.ws), v, p.s));
+        d.seq[d.k & 1] = v;
+    } else {
+        HIPCHK(p.g, hipEventRecord(p.ws->ev[d.k & 1], p.s));
+    }
     ++d.k;
     d.batch = std::min(d.batch * 2, kMaxBatch);
     return GG_OK;
@@ -448,15 +460,24 @@ int drive_step(Drive& d, bool block) {
     if (d.finished) return 1;
     Plan& p = d.p;
     gg_ws ws = p.ws;
-    hipEvent_t older = ws->ev[d.k & 1];  // batch k-2 (k-1 is the newer one)
-    if (block) {
-        HIPCHK(p.g, hipEventSynchronize(older));
+    auto reported = [&] { return __atomic_load_n(ws->h_done, __ATOMIC_ACQUIRE) == d.tag; };
+    auto completed = [&](int slot) { return __atomic_load_n(prog_word(ws), __ATOMIC_ACQUIRE) >= d.seq[slot]; };
+    // batch k-2 is the older of the two outstanding (k-1 the newer one)
+    if (d.poll) {
+        if (reported()) {
+            // the values are final once the end is found; rounds still queued
+            // return at their first instruction
+            d.finished = true;
+            return 1;
+        }
+        if (!completed(d.k & 1)) return 0;
+    } else if (block) {
+        HIPCHK(p.g, hipEventSynchronize(ws->ev[d.k & 1]));
     } else {
-        const hipError_t q = hipEventQuery(older);
+        const hipError_t q = hipEventQuery(ws->ev[d.k & 1]);
         if (q == hipErrorNotReady) return 0;
         HIPCHK(p.g, q);
     }
-    auto reported = [&] { return __atomic_load_n(ws->h_done, __ATOMIC_ACQUIRE) == d.tag; };
     if (reported()) {
         d.finished = true;
         return 1;
@@ -464,7 +485,11 @@ int drive_step(Drive& d, bool block) {
     const long long ms = std::chrono::duration_cast<std::chrono::milliseconds>(
                              std::chrono::steady_clock::now() - d.t0).count();
     if (d.r >= d.max_rounds || ms > p.o.time_limit_ms) {
-        HIPCHK(p.g, hipEventSynchronize(ws->ev[(d.k + 1) & 1]));
+        if (d.poll) {
+            while (!completed((d.k + 1) & 1)) std::this_thread::yield();
+        } else {
+            HIPCHK(p.g, hipEventSynchronize(ws->ev[(d.k + 1) & 1]));
+        }
         if (!reported()) d.status = d.r >= d.max_rounds ? GG_EITER : GG_ETIMEOUT;
         d.finished = true;
         return 1;

@@ -116,6 +116,9 @@ hipError_t launch_heavy(const Round& R, int algo, int grid, int block, hipStream
 hipError_t launch_bfs_diropt(const Round& R, int grid, int block, hipStream_t s);
 hipError_t launch_jump(const Round& R, int grid, int block, hipStream_t s);
 hipError_t launch_cc_diropt(const Round& R, int grid, int block, hipStream_t s);
+// One thread stores v into the pinned host word *p (system scope) once every
+// earlier kernel of the stream has completed.
+hipError_t launch_mark(unsigned long long* p, unsigned long long v, hipStream_t s);
 
 // Graph build helpers (gg_kernels.hip).
 hipError_t launch_fill_src(const int* row, int n, int m, int* src, int grid, int block,

@@ -662,8 +662,95 @@ __global__ __launch_bounds__(256) void k_esync(Round R) {
 // Asynchronous vertex round: the frontier of round r is the set of flagged
 // vertices; each wavefront scans 64 tile flags at a time and serves the
 // flagged tiles it finds.
+// Serve the np vertices listed in pend[0, np) of this wavefront (lane k takes
+// entry k): the tail value, far vertices of the near-far schedule back onto
+// the frontier, heavy rows stamped for the chunk kernel, light rows walked by
+// the balanced mapping.
+template <int A>
+__device__ __forceinline__ void serve_list(const Round& R, const int* row, const int* col,
+                                           const int* pend, int np, int nxt, bool nf, int bound,
+                                           Acc& acc) {
+    const int lane = threadIdx.x & 63;
+    __builtin_amdgcn_wave_barrier();
+    const int u = lane < np ? pend[lane] : -1;
+    __builtin_amdgcn_wave_barrier();
+    bool on = u >= 0;
+    int rb = 0, re = 0, sv = 0;
+    if (on) {
+        tail_value<A, true>(R, u, sv, acc);
+        if (nf && sv >= bound) {
+            // a far vertex waits on the frontier for a later bound
+            push(R, nxt, u);
+            acc.u++;
+            on = false;
+        } else {
+            rb = row[u];
+            re = row[u + 1];
+            acc.v++;
+        }
+    }
+    const bool hv = on && re - rb > R.g.heavy;
+    if (hv) R.ws.hstamp[u] = R.stamp;
+    wave_relax_rows<A, true>(R, col, on && !hv ? rb : 0, on && !hv ? re - rb : 0, sv, nxt, acc,
+                             bound);
+}
+
+// Balanced worklist round with the frontier packed per wavefront: the
+// wavefront collects the flagged vertices of the tiles it scans into a
+// 64-entry list in LDS and serves a full list at a time.  (A tile of a
+// sparse frontier holds a few flagged vertices; serving the tiles one by one
+// leaves most lanes idle in every step of the edge walk.)
+template <int A>
+__device__ __forceinline__ void vasync_packed(const Round& R, Acc& acc, bool nf, int bound) {
+    const DevGraph& g = R.g;
+    const int* row = A == CC ? g.srow : g.row;
+    const int* col = A == CC ? g.scol : g.col;
+    const int n = g.n;
+    const int cur = R.r & 1, nxt = cur ^ 1;
+    unsigned char* vf = R.ws.vflag[cur];
+    unsigned char* tf = R.ws.tflag[cur];
+    const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    const long long gw = (long long)blockIdx.x * wpb + (threadIdx.x >> 6);
+    const long long tw = (long long)gridDim.x * wpb;
+    const long long ntiles = (n + 63) / 64;
+    const long long nitems = (ntiles + 63) / 64 * kParts;
+    __shared__ int s_pend[4][64];  // blocks of 256 threads: four wavefronts
+    int* pend = s_pend[threadIdx.x >> 6];
+    int np = 0;  // vertices in the list (the same in every lane)
+    for (long long it = gw; it < nitems; it += tw) {
+        const long long st = it / kParts;
+        const int part = (int)(it % kParts);
+        const long long t = st * 64 + lane;
+        const bool mine = lane / (64 / kParts) == part;
+        const bool tfl = mine && t < ntiles && tf[t] != 0;
+        unsigned long long tm = __ballot(tfl);
+        if (tfl) tf[t] = 0;
+        while (tm) {
+            const int b = __ffsll(tm) - 1;
+            tm &= tm - 1;
+            const int u = (int)((st * 64 + b) * 64 + lane);
+            const bool on = u < n && vf[u] != 0;
+            if (on) vf[u] = 0;
+            const unsigned long long om = __ballot(on);
+            const int c = __popcll(om);
+            if (np + c > 64) {
+                serve_list<A>(R, row, col, pend, np, nxt, nf, bound, acc);
+                np = 0;
+            }
+            if (on) pend[np + __popcll(om & ((1ull << lane) - 1))] = u;
+            np += c;
+        }
+    }
+    if (np > 0) serve_list<A>(R, row, col, pend, np, nxt, nf, bound, acc);
+}
+
 template <int A, int MAP>
 __device__ __forceinline__ void vasync_body(const Round& R, Acc& acc, bool nf, int bound) {
+    if (MAP == MAP_BALANCED) {
+        vasync_packed<A>(R, acc, nf, bound);
+        return;
+    }
     const DevGraph& g = R.g;
     const int* row = A == CC ? g.srow : g.row;
     const int* col = A == CC ? g.scol : g.col;
@@ -705,13 +792,7 @@ __device__ __forceinline__ void vasync_body(const Round& R, Acc& acc, bool nf, i
                     acc.v++;
                 }
             }
-            if (MAP == MAP_BALANCED) {
-                // heavy rows are served by the chunk kernel of this round
-                const bool hv = on && re - rb > g.heavy;
-                if (hv) R.ws.hstamp[u] = R.stamp;
-                wave_relax_rows<A, true>(R, col, on && !hv ? rb : 0, on && !hv ? re - rb : 0, sv,
-                                         nxt, acc, bound);
-            } else if (MAP == MAP_THREAD) {
+            if (MAP == MAP_THREAD) {
                 if (on)
                     for (int e = rb; e < re; ++e) {
                         int t2;
@@ -742,10 +823,12 @@ __device__ __forceinline__ void vasync_body(const Round& R, Acc& acc, bool nf, i
     }
 }
 
-template <int A, int MAP>
+// NF: the near-far schedule (SSSP, balanced mapping, R.delta > 0); a
+// separate instantiation keeps its bookkeeping out of the plain rounds.
+template <int A, int MAP, bool NF = false>
 __global__ __launch_bounds__(256) void k_vasync(Round R) {
     if (!round_begin(R)) return;
-    const bool nf = A == SSSP && MAP == MAP_BALANCED && R.delta > 0;
+    const bool nf = NF;
     const int bound = nf ? nearfar_bound(R) : kInf;
     Acc acc;
     vasync_body<A, MAP>(R, acc, nf, bound);
@@ -865,36 +948,8 @@ __global__ __launch_bounds__(256) void k_bfs_diropt(Round R) {
     const long long ntiles = (n + 63) / 64;
     Acc acc;
     if (!pull) {
-        // push: the balanced frontier round of k_vasync, inlined for BFS
-        unsigned char* vf = R.ws.vflag[cur];
-        unsigned char* tf = R.ws.tflag[cur];
-        const long long nitems = (ntiles + 63) / 64 * kParts;
-        for (long long it = gw; it < nitems; it += tw) {
-            const long long st = it / kParts;
-            const int part = (int)(it % kParts);
-            const long long t = st * 64 + lane;
-            const bool mine = lane / (64 / kParts) == part;
-            const bool tfl = mine && t < ntiles && tf[t] != 0;
-            unsigned long long tm = __ballot(tfl);
-            if (tfl) tf[t] = 0;
-            while (tm) {
-                const int b = __ffsll(tm) - 1;
-                tm &= tm - 1;
-                const int u = (int)((st * 64 + b) * 64 + lane);
-                const bool on = u < n && vf[u] != 0;
-                if (on) vf[u] = 0;
-                int rb = 0, re = 0;
-                if (on) {
-                    rb = g.row[u];
-                    re = g.row[u + 1];
-                    acc.v++;
-                }
-                const bool hv = on && re - rb > g.heavy;
-                if (hv) R.ws.hstamp[u] = R.stamp;
-                wave_relax_rows<BFS, true>(R, g.col, on && !hv ? rb : 0,
-                                           on && !hv ? re - rb : 0, lev, nxt, acc);
-            }
-        }
+        // push: the balanced frontier round of k_vasync
+        vasync_packed<BFS>(R, acc, false, kInf);
     } else {
         // pull: one tile of 64 vertices per wavefront step; the frontier flags
         // of this round are cleared on the way (they are not read)
@@ -1224,7 +1279,10 @@ static hipError_t vasync_a(const Round& R, int grid, int block, hipStream_t s) {
     switch (R.mapping) {
         case MAP_THREAD: GG_LAUNCH((k_vasync<A, MAP_THREAD>), grid, block, s, R);
         case MAP_WAVE: GG_LAUNCH((k_vasync<A, MAP_WAVE>), grid, block, s, R);
-        default: GG_LAUNCH((k_vasync<A, MAP_BALANCED>), grid, block, s, R);
+        default:
+            if constexpr (A == SSSP)
+                if (R.delta > 0) GG_LAUNCH((k_vasync<A, MAP_BALANCED, true>), grid, block, s, R);
+            GG_LAUNCH((k_vasync<A, MAP_BALANCED>), grid, block, s, R);
     }
 }
 
@@ -1258,6 +1316,15 @@ hipError_t launch_bfs_diropt(const Round& R, int grid, int block, hipStream_t s)
 
 hipError_t launch_cc_diropt(const Round& R, int grid, int block, hipStream_t s) {
     GG_LAUNCH(k_cc_diropt, grid, block, s, R);
+}
+
+__global__ __launch_bounds__(64) void k_mark(unsigned long long* p, unsigned long long v) {
+    if (threadIdx.x == 0) __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+hipError_t launch_mark(unsigned long long* p, unsigned long long v, hipStream_t s) {
+    hipLaunchKernelGGL(k_mark, dim3(1), dim3(64), 0, s, p, v);
+    return hipGetLastError();
 }
 
 hipError_t launch_jump(const Round& R, int grid, int block, hipStream_t s) {

@@ -63,7 +63,11 @@ struct gg_ws_s {
     gg::DevWs dev{};
     unsigned char* vflag_mem = nullptr;
     int epoch = 0;  // round stamps of the next traversal start here
-    int* h_done = nullptr;  // pinned word written by the kernel that finds the end
+    // pinned host words: [0] the tag written by the kernel that finds the
+    // end; [2..3] (64 bits) the sequence number of the last batch of rounds
+    // completed, written by a marker kernel (non-blocking driving)
+    int* h_done = nullptr;
+    unsigned long long prog_seq = 0;  // last sequence number enqueued
     hipEvent_t ev[2] = {nullptr, nullptr};
     hipEvent_t finished = nullptr;
     hipStream_t last_stream = nullptr;
@@ -77,6 +81,11 @@ struct gg_ws_s {
     bool profiled = false;
     int rounds = 0;
 };
+
+// The 64-bit batch sequence word inside a workspace's pinned block.
+inline unsigned long long* prog_word(gg_ws ws) {
+    return reinterpret_cast<unsigned long long*>(ws->h_done + 2);
+}
 
 struct gg_graph_s {
     int n = 0;
@@ -145,6 +154,11 @@ struct Drive {
     Plan p;
     long long r = 0, max_rounds = 0;
     int batch = 2, k = 0;
+    // poll: batches end with a marker kernel that stores their sequence
+    // number into pinned memory (read without any runtime call); otherwise
+    // with an event the host waits on
+    bool poll = false;
+    unsigned long long seq[2] = {0, 0};
     int stamp_base = 0, tag = 0;
     std::chrono::steady_clock::time_point t0;
     int status = GG_OK;

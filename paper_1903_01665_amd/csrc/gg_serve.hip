@@ -118,6 +118,7 @@ int admit(gg_server s, Query* q, SGraph& G) {
         p.R.epoch = base;
         if (plan_init(p) != hipSuccess) rc = GG_EHIP;
     }
+    q->d.poll = true;
     if (rc == GG_OK) rc = drive_start(q->d, 0, base, base);
     if (rc != GG_OK) {
         G.pool.push_back(ws);

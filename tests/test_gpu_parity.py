@@ -371,3 +371,34 @@ def test_auto_never_picks_an_unavailable_variant(gg):
             g.free()
     finally:
         gg.tune_set(saved)
+
+
+def test_null_options_mean_auto(gg):
+    """A NULL opts pointer resolves every field through the tuning table, as
+    explicit AUTO fields do (a zeroed struct would name vertex-sync)."""
+    import ctypes
+    hg = gen.workload("rmat12")
+    g = gg.Graph.from_host(hg, symmetrize=True)
+    try:
+        for algo in (gg.ALGO_SSSP, gg.ALGO_BFS, gg.ALGO_CC):
+            a, b = gg.Opts(), gg.Opts()
+            assert gg.lib().gg_resolve(g.handle, algo, None, ctypes.byref(a)) == 0
+            assert gg.lib().gg_resolve(g.handle, algo, ctypes.byref(gg.make_opts()),
+                                       ctypes.byref(b)) == 0
+            assert (a.mode, a.sched, a.mapping, a.delta) == (b.mode, b.sched, b.mapping, b.delta)
+        # the server runs its queries with the tuned variant
+        import torch
+        srv = gg.Server(2, 0)
+        try:
+            gid = srv.add_graph(gg.Graph.from_host(hg, symmetrize=True))
+            out = torch.empty(hg.n, dtype=torch.int32, device="cuda")
+            srv.submit(gid, gg.ALGO_SSSP, 0, out)
+            while not srv.poll():
+                pass
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(out.cpu().numpy(),
+                                          oracle.sssp(hg.n, hg.row_ptr, hg.col, hg.w, 0))
+        finally:
+            srv.free()
+    finally:
+        g.free()
