@@ -29,6 +29,7 @@ VARIANTS = [(gg.VERTEX, gg.SYNC, gg.MAP_THREAD, 0), (gg.VERTEX, gg.SYNC, gg.MAP_
             (gg.EDGE, gg.SYNC, gg.MAP_AUTO, 0), (gg.EDGE, gg.ASYNC, gg.MAP_AUTO, 0)]
 NEARFAR = [(gg.VERTEX, gg.NEARFAR, gg.MAP_BALANCED, dm) for dm in (1, 2, 4, 8, 16, 64)]
 DIROPT = [(gg.VERTEX, gg.DIROPT, gg.MAP_BALANCED, 0)]
+CC_DIROPT = [(gg.EDGE, gg.DIROPT, gg.MAP_BALANCED, 0)]
 
 # calibration graphs: the size classes of the workloads, from a seed stream of
 # their own so that no benchmark graph is itself in the set
@@ -87,7 +88,7 @@ def main(argv=None):
         avg_w = float(hg.w.mean()) if hg.w is not None and hg.m else 1.0
         for algo in ALGOS:
             times = {}
-            extra = NEARFAR if algo == "sssp" else DIROPT if algo == "bfs" else []
+            extra = NEARFAR if algo == "sssp" else DIROPT if algo == "bfs" else CC_DIROPT
             for v in VARIANTS + extra:
                 times[v] = time_variant(g, algo, src, v, args.reps, out, avg_w)
             best = min(times.values())
