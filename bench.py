@@ -141,7 +141,7 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--config", default="single",
-                    choices=["single", "batched", "serve", "concurrent"])
+                    choices=["single", "batched", "serve", "concurrent", "msf"])
     ap.add_argument("--workloads", default="er16k,rmat16,rmat22",
                     help="concurrent: workloads to run")
     ap.add_argument("--instances", type=int, default=512, help="batched: instance count")
@@ -160,6 +160,8 @@ def main():
         return bench_serve(args)
     if args.config == "concurrent":
         return bench_concurrent(args)
+    if args.config == "msf":
+        return bench_msf(args)
 
     import torch
 
@@ -431,6 +433,49 @@ def bench_batched(args):
                  "traversed_edges": m_trav, "groups": groups},
                 plain={"GTEPS": round(m_trav / tp / 1e9, 4), "ms_per_pass": round(tp * 1e3, 3)},
                 speedup_vs_plain=round(tp / tb, 3), results_identical_to_plain=same)
+
+
+def bench_msf(args):
+    """Minimum spanning forest of one workload graph (every stored edge taken
+    as undirected): device Boruvka rounds vs the oracle's Kruskal."""
+    import torch
+
+    from paper_1903_01665_amd import gen, gg
+
+    hg = gen.workload(args.workload)
+    g = gg.Graph.from_host(hg)
+    out = torch.empty(max(hg.m, 1), dtype=torch.uint8, device="cuda")
+    for _ in range(max(1, args.warmup)):
+        g.msf(out=out)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        sel, tw, ne = g.msf(out=out)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    st = g.stats()
+    tm = float(np.median(ts))
+    log(f"[bench] msf {args.workload}: {tm * 1e3:.3f} ms, {st['iterations']} rounds, "
+        f"{ne} edges, weight {tw}")
+    cpu = verified = None
+    if not args.no_cpu:
+        import oracle
+        t0 = time.perf_counter()
+        want, total = oracle.msf(hg.n, hg.row_ptr, hg.col, hg.w)
+        tc = time.perf_counter() - t0
+        verified = bool(np.array_equal(sel.cpu().numpy(), want) and total == tw)
+        cpu = {"value": round(hg.m / tc / 1e9, 4), "unit": "G edges/s", "cores": 1,
+               "kind": "oracle", "seconds": round(tc, 3),
+               "sample": f"full {args.workload} graph: Kruskal (sort by key, union-find), "
+                         f"one thread"}
+        log(f"[bench] oracle {tc:.2f}s; GPU forest matches: {verified}")
+    g.free()
+    common_line(args, "G edges/s (minimum spanning forest)", hg.m / tm / 1e9, "G edges/s",
+                tm * 1e3, {"workload": args.workload, "n": hg.n, "m": hg.m,
+                           "rounds": st["iterations"], "forest_edges": ne,
+                           "forest_weight": tw, "verified_vs_oracle": verified},
+                cpu_baseline=cpu)
 
 
 def bench_concurrent(args):

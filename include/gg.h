@@ -96,7 +96,7 @@ typedef enum {
  * grid.  Ignored for edge-based work. */
 typedef enum { GG_MAP_AUTO = 0, GG_MAP_THREAD = 1, GG_MAP_WAVE = 2, GG_MAP_BALANCED = 3 } gg_mapping;
 
-typedef enum { GG_ALGO_SSSP = 0, GG_ALGO_BFS = 1, GG_ALGO_CC = 2 } gg_algo;
+typedef enum { GG_ALGO_SSSP = 0, GG_ALGO_BFS = 1, GG_ALGO_CC = 2, GG_ALGO_MSF = 3 } gg_algo;
 
 /* gg_graph_upload flags */
 #define GG_SYMMETRIZE 1u      /* also build the both-directions CSR needed by vertex-based CC */
@@ -219,6 +219,23 @@ int gg_sssp_ex(gg_graph g, gg_ws ws, int32_t source, const gg_opts* opts, int32_
 int gg_bfs_ex(gg_graph g, gg_ws ws, int32_t source, const gg_opts* opts, int32_t* dist_out_dev,
               void* stream);
 int gg_cc_ex(gg_graph g, gg_ws ws, const gg_opts* opts, int32_t* label_out_dev, void* stream);
+
+/* Minimum spanning forest (MST is the fourth algorithm of Sec. 4.1, Table 3;
+ * the DSL's Set type is a union-find structure, Sec. 2).  Every stored edge e
+ * is taken as an undirected edge with key (w[e], e) -- weight first, then
+ * the edge's index in the uploaded CSR -- so the forest of least keys is
+ * unique; self-loops never belong to it.  Boruvka rounds on the device: each
+ * component offers its least crossing edge (64-bit atomic minimum), the
+ * offered edges join the forest and their components merge in a lock-free
+ * union-find.  in_msf_dev: caller-owned device uint8[m], set to 1 for the
+ * forest's edges and 0 for the others.  total_weight, n_edges (host,
+ * nullable): the forest's summed weight and edge count.  ws NULL = the
+ * graph's default workspace (the first call on a workspace allocates 12
+ * bytes per vertex for the union-find, kept until the workspace is freed).
+ * GG_EINVAL for an unweighted graph or a NULL output with m > 0.  Returns
+ * when the forest is complete. */
+int gg_msf(gg_graph g, gg_ws ws, uint8_t* in_msf_dev, int64_t* total_weight, int64_t* n_edges,
+           void* stream);
 
 /* Statistics of the last traversal on a workspace (NULL = default).  Waits
  * for that traversal to finish.  Returns the traversal's device-side status

@@ -58,6 +58,10 @@ void free_ws_arrays(gg_ws_s* ws) {
     if (ws->dev.stat) hipFree(ws->dev.stat);
     if (ws->dev.pcount) hipFree(ws->dev.pcount);
     if (ws->h_done) hipHostFree(ws->h_done);
+    if (ws->msf_parent) hipFree(ws->msf_parent);
+    if (ws->msf_best) hipFree(ws->msf_best);
+    ws->msf_parent = nullptr;
+    ws->msf_best = nullptr;
     for (auto& e : ws->ev)
         if (e) hipEventDestroy(e);
     for (auto& e : ws->pev)

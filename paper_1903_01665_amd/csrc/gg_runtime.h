@@ -68,6 +68,10 @@ struct gg_ws_s {
     // completed, written by a marker kernel (non-blocking driving)
     int* h_done = nullptr;
     unsigned long long prog_seq = 0;  // last sequence number enqueued
+    // minimum spanning forest: union-find parents and per-root offers,
+    // allocated by the first gg_msf call on the workspace
+    int* msf_parent = nullptr;
+    unsigned long long* msf_best = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
     hipEvent_t finished = nullptr;
     hipStream_t last_stream = nullptr;

@@ -20,7 +20,7 @@ INF = 2**31 - 1
 VERTEX, EDGE, MODE_AUTO = 0, 1, 2
 SYNC, ASYNC, SCHED_AUTO, NEARFAR, DIROPT = 0, 1, 2, 3, 4
 MAP_AUTO, MAP_THREAD, MAP_WAVE, MAP_BALANCED = 0, 1, 2, 3
-ALGO_SSSP, ALGO_BFS, ALGO_CC = 0, 1, 2
+ALGO_SSSP, ALGO_BFS, ALGO_CC, ALGO_MSF = 0, 1, 2, 3
 SYMMETRIZE, INPUT_ON_DEVICE, SYMMETRIC = 1, 2, 4
 OPT_CC_NO_JUMP = 1
 OPT_PROFILE = 2
@@ -32,7 +32,7 @@ STATUS = {0: "GG_OK", -1: "GG_EINVAL", -2: "GG_ENOMEM", -3: "GG_EHIP", -4: "GG_E
 # every symbol include/gg.h declares
 EXPORTS = ["gg_graph_upload", "gg_graph_free", "gg_graph_info", "gg_graph_error", "gg_sssp",
            "gg_bfs", "gg_cc", "gg_ws_create", "gg_ws_free", "gg_sssp_ex", "gg_bfs_ex",
-           "gg_cc_ex", "gg_last_stats", "gg_last_profile", "gg_resolve", "gg_status_str",
+           "gg_cc_ex", "gg_msf", "gg_last_stats", "gg_last_profile", "gg_resolve", "gg_status_str",
            "gg_version", "gg_tune_set", "gg_tune_get", "gg_class_of", "gg_tune_lookup",
            "gg_graph_probe", "gg_graph_class", "gg_batch_create", "gg_batch_run",
            "gg_batch_offsets", "gg_batch_info", "gg_batch_group", "gg_batch_free",
@@ -131,6 +131,7 @@ def lib():
     L.gg_sssp_ex.argtypes = [vp, vp, i32, P(Opts), vp, vp]
     L.gg_bfs_ex.argtypes = [vp, vp, i32, P(Opts), vp, vp]
     L.gg_cc_ex.argtypes = [vp, vp, P(Opts), vp, vp]
+    L.gg_msf.argtypes = [vp, vp, vp, P(i64), P(i64), vp]
     L.gg_last_stats.argtypes = [vp, vp, P(Stats)]
     L.gg_last_profile.argtypes = [vp, vp, P(Profile)]
     L.gg_resolve.argtypes = [vp, i32, P(Opts), P(Opts)]
@@ -333,6 +334,22 @@ class Graph:
            stream=None, opts=None):
         o = opts or make_opts(mode, sched, mapping)
         return self._run(lib().gg_cc_ex, "gg_cc", [], o, out, ws, stream)
+
+    def msf(self, out=None, ws=None, stream=None):
+        """Minimum spanning forest: (uint8 cuda tensor marking the forest's
+        edges in CSR order, total weight, edge count)."""
+        import torch
+        m = self.m
+        if out is None:
+            out = torch.empty(max(m, 1), dtype=torch.uint8, device="cuda")
+        if out.dtype != torch.uint8 or not out.is_cuda or out.numel() < m or \
+                not out.is_contiguous():
+            raise ValueError("output must be a contiguous uint8 cuda tensor of >= m elements")
+        tw, ne = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().gg_msf(self.handle, ws.handle if ws is not None else None,
+                            ctypes.c_void_p(out.data_ptr()), ctypes.byref(tw), ctypes.byref(ne),
+                            _stream_ptr(stream)), "gg_msf")
+        return out[:m], tw.value, ne.value
 
     def stats(self, ws=None) -> dict:
         s = Stats()

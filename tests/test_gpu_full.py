@@ -69,3 +69,23 @@ def test_grid4096_all_variants():
 
 def test_er23_all_variants():
     run_full("er23", COMBOS)
+
+
+@pytest.mark.parametrize("name", ["rmat22", "grid4096", "er23"])
+def test_msf_full_size(name):
+    """The forest on the full benchmark graphs, edge by edge."""
+    import torch
+
+    import oracle
+    from paper_1903_01665_amd import gg
+    hg = gen.workload(name)
+    want, total = oracle.msf(hg.n, hg.row_ptr, hg.col, hg.w)
+    g = gg.Graph.from_host(hg)
+    try:
+        sel, tw, ne = g.msf()
+        torch.cuda.synchronize()
+        got = sel.cpu().numpy()
+        assert np.array_equal(got, want), (name, int((got != want).sum()))
+        assert tw == total and ne == int(want.sum())
+    finally:
+        g.free()
