@@ -108,7 +108,10 @@ def kernel_symbol(algo, kind, mode, sched, mapping):
         return f"gg::k_{algo}_diropt(gg::Round)"
     if mode == 1:
         return f"void gg::k_{'esync' if sched == 0 else 'easync'}<{a}>(gg::Round)"
-    return f"void gg::k_{'vsync' if sched == 0 else 'vasync'}<{a}, {mapping}>(gg::Round)"  # async, near-far
+    if sched == 0:
+        return f"void gg::k_vsync<{a}, {mapping}>(gg::Round)"
+    nf = "true" if sched == 3 else "false"  # the near-far schedule has its own instantiation
+    return f"void gg::k_vasync<{a}, {mapping}, {nf}>(gg::Round)"
 
 
 def measured_traffic(symbol, workload):
