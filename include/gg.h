@@ -75,11 +75,14 @@ typedef enum { GG_VERTEX = 0, GG_EDGE = 1, GG_MODE_AUTO = 2 } gg_mode;
  *   does; a frontier of more than n/20 vertices is pulled -- every unvisited
  *   vertex scans its in-neighbours (the DSL's innbrs iterator, Sec. 2) and
  *   stops at the first one on the level.
- *   CC (edge-based): rounds sweep every stored edge (GG_SYNC's edge form)
- *   while the rows of the vertices lowered by the previous round hold more
- *   than 1/8 of the both-directions edges, then serve those vertices as a
- *   worklist (GG_ASYNC's vertex form) -- the paper's synchronous and
- *   asynchronous schedules (Sec. 3.3) chosen per round instead of per run.
+ *   CC (edge-based): round 0 takes one synchronous step from the ids
+ *   (label = min(id, smallest neighbour id), read from the both-directions
+ *   rows without atomics); later rounds sweep every stored edge (GG_SYNC's
+ *   edge form) while the rows of the vertices lowered by the previous round
+ *   hold more than 1/8 of the both-directions edges, then serve those
+ *   vertices as a worklist (GG_ASYNC's vertex form) -- the paper's
+ *   synchronous and asynchronous schedules (Sec. 3.3) chosen per round
+ *   instead of per run.
  * With GG_MODE_AUTO an explicit GG_DIROPT takes the mode it runs in. */
 typedef enum {
     GG_SYNC = 0,

@@ -651,6 +651,68 @@ __device__ __forceinline__ void esync_body(const Round& R, Acc& acc) {
     }
 }
 
+// Round 0 of the per-round CC schedule.  Labels start as the vertex ids, so
+// one synchronous step is label[v] = min(v, smallest neighbour id): a
+// segmented minimum over the both-directions rows that reads the column
+// indices only -- no label gathers, and no atomics except one per heavy-row
+// chunk.  Light rows: a wavefront takes a tile of 64 rows, walks their edges
+// with the balanced mapping and reduces per row in LDS.  Heavy rows: one
+// wavefront per 256-edge chunk, one atomic minimum per chunk.  Every vertex
+// whose label drops is pushed (with its row length counted), as a sweep
+// does.  (An in-place edge sweep carries labels further than this one
+// synchronous step, so the plain sweep schedule keeps its first sweep: on a
+// uniform graph the step costs it one extra sweep.)
+__device__ void cc_first_pass(const Round& R, Acc& acc) {
+    const DevGraph& g = R.g;
+    const int n = g.n;
+    const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    const long long gw = (long long)blockIdx.x * wpb + (threadIdx.x >> 6);
+    const long long tw = (long long)gridDim.x * wpb;
+    const long long ntiles = (n + 63) / 64;
+    __shared__ int s_min[4][64];  // blocks of 256 threads: four wavefronts
+    int* smin = s_min[threadIdx.x >> 6];
+    for (long long t = gw; t < ntiles; t += tw) {
+        const int v = (int)(t * 64 + lane);
+        int rb = 0, deg = 0;
+        if (v < n) {
+            rb = g.srow[v];
+            deg = g.srow[v + 1] - rb;
+        }
+        const bool light = deg <= g.heavy;
+        smin[lane] = v;
+        __builtin_amdgcn_wave_barrier();
+        wave_rows_balanced(rb, light ? deg : 0, lane,
+                           [&](int e, int slot) { atomicMin(&smin[slot], g.scol[e]); });
+        __builtin_amdgcn_wave_barrier();
+        if (v < n && light) {
+            const int x = smin[lane];
+            acc.e += deg;
+            if (x < v) {
+                R.val[v] = x;
+                acc.u++;
+                sweep_push(R, v, acc);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    for (long long k = gw; k < g.n_shchunks; k += tw) {
+        const int2 c = g.shchunks[k];
+        const int e1 = min(c.y + g.chunk, g.srow[c.x + 1]);
+        int x = kInf;
+        for (int e = c.y + lane; e < e1; e += 64) x = min(x, g.scol[e]);
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) x = min(x, __shfl_xor(x, d, 64));
+        if (lane == 0) {
+            acc.e += e1 - c.y;
+            if (x < atomicMin(&R.val[c.x], x)) {
+                acc.u++;
+                sweep_push(R, c.x, acc);
+            }
+        }
+    }
+}
+
 template <int A>
 __global__ __launch_bounds__(256) void k_esync(Round R) {
     if (!round_begin(R)) return;
@@ -1120,8 +1182,12 @@ __global__ __launch_bounds__(256) void k_cc_diropt(Round R) {
         uint4* tf = reinterpret_cast<uint4*>(R.ws.tflag[cur]);
         for (long long i = tid; i < groups * 256; i += tt) vf[i] = make_uint4(0, 0, 0, 0);
         for (long long i = tid; i < groups * 4; i += tt) tf[i] = make_uint4(0, 0, 0, 0);
-        esync_body<CC, true>(R, acc);
-        acc.d = acc.e;
+        if (R.r == 0) {
+            cc_first_pass(R, acc);
+        } else {
+            esync_body<CC, true>(R, acc);
+            acc.d = acc.e;
+        }
     } else {
         vasync_body<CC, MAP_BALANCED>(R, acc, false, kInf);
     }
