@@ -119,7 +119,9 @@ typedef struct {
     int32_t mapping;       /* gg_mapping */
     int32_t block_threads; /* 0 = library default (256); else 64..1024, multiple of 64 */
     int32_t max_blocks;    /* 0 = fill the device; else a cap on the persistent grid */
-    int32_t heavy_threshold; /* 0 = default; rows longer than this are chunked (BALANCED) */
+    int32_t heavy_threshold; /* ignored: the rows chunked by the BALANCED mapping are
+                                fixed per graph at upload (longer than 16 edges when the
+                                largest out-degree is >= 128x the mean, else 32) */
     int32_t time_limit_ms; /* 0 = default (60000); no round is launched after it (GG_ETIMEOUT) */
     int32_t flags;         /* GG_OPT_* bits */
     int32_t delta;         /* GG_NEARFAR bucket width; 0 = default (from the average weight) */

@@ -632,6 +632,8 @@ int gg_graph_upload(int32_t n, int64_t m, const int32_t* row_ptr, const int32_t*
     g->m = m;
     g->max_deg = max_deg;
     g->argmax_deg = argmax_deg;
+    g->heavy = (double)max_deg >= 128.0 * ((double)m / (double)n) && m > 0 ? kHeavySkewed
+                                                                            : kHeavyUniform;
     g->avg_w = avg_w;
     g->max_w = max_w;
     g->weighted = w != nullptr;

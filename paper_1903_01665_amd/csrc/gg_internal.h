@@ -11,7 +11,13 @@ constexpr int kInf = 2147483647;
 constexpr int kWave = 64;
 constexpr int kTile = 64;            // vertices per frontier tile (one wavefront)
 constexpr int kMaxStatBlocks = 4096; // per-block statistics slots
-constexpr int kDefaultHeavy = 64;    // rows longer than this are chunked (balanced mapping)
+// rows longer than the graph's heavy threshold are chunked (balanced
+// mapping): 16 on graphs whose largest out-degree is at least 128 times the
+// mean, 32 on the others (measured on MI355X: a lower threshold moves more
+// edges of a skewed graph into full-wavefront chunks, while on a uniform
+// graph it cuts short rows into underfilled chunks)
+constexpr int kHeavySkewed = 16;
+constexpr int kHeavyUniform = 32;
 constexpr int kChunk = 256;          // edges per heavy-row chunk
 constexpr int kKinds = 3;            // statistics kinds: round, heavy chunks, auxiliary
 constexpr int kParts = 32;           // frontier work items per 64-tile group (2 tiles each)

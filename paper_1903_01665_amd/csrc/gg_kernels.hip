@@ -39,6 +39,12 @@ namespace gg {
 // Edges each lane keeps in flight in the relaxation loops.
 constexpr int kBatch = 4;
 
+// Edges per lane in flight in the worklist kernels, by algorithm (measured on
+// MI355X): BFS stores levels without atomics and gains from more wavefronts
+// at once (2); SSSP and CC use 4; the near-far SSSP rounds, whose frontiers
+// are small and latency-bound, 8.
+constexpr int batch_for(int A, bool nf) { return nf ? 8 : A == BFS ? 2 : 4; }
+
 // Direction-optimizing BFS pulls a level when its frontier holds more than
 // n / kPullRatio vertices.
 constexpr int kPullRatio = 20;
@@ -312,40 +318,40 @@ __device__ __forceinline__ void relax_batch(const Round& R, const int* col, cons
 }
 
 // The edges [e0, e1) of one row, all with tail value sv, relaxed by the
-// whole wavefront kBatch x 64 edges per step.
-template <int A, bool PUSH>
+// whole wavefront U x 64 edges per step.
+template <int A, bool PUSH, int U = kBatch>
 __device__ __forceinline__ void wave_relax_range(const Round& R, const int* col, int e0, int e1,
                                                  int sv, int nxt, Acc& acc, int bound = kInf) {
     const int lane = threadIdx.x & 63;
-    for (int eb = e0; eb < e1; eb += 64 * kBatch) {
-        int e[kBatch], s[kBatch];
-        bool ok[kBatch];
+    for (int eb = e0; eb < e1; eb += 64 * U) {
+        int e[U], s[U];
+        bool ok[U];
 #pragma unroll
-        for (int j = 0; j < kBatch; ++j) {
+        for (int j = 0; j < U; ++j) {
             e[j] = eb + j * 64 + lane;
             ok[j] = e[j] < e1;
             s[j] = sv;
         }
-        relax_batch<A, kBatch, PUSH>(R, col, e, s, ok, nxt, acc, bound);
+        relax_batch<A, U, PUSH>(R, col, e, s, ok, nxt, acc, bound);
     }
 }
 
 // Lanes hold one row each, [beg, beg + deg), with tail value sv.  The
-// wavefront walks the concatenation of the 64 rows kBatch x 64 edges per
+// wavefront walks the concatenation of the 64 rows U x 64 edges per
 // step; edge k of a step belongs to the row found by a six-step search over
 // the exclusive prefix of the degrees.
-template <int A, bool PUSH>
+template <int A, bool PUSH, int U = kBatch>
 __device__ __forceinline__ void wave_relax_rows(const Round& R, const int* col, int beg, int deg,
                                                 int sv, int nxt, Acc& acc, int bound = kInf) {
     const int lane = threadIdx.x & 63;
     const int incl = wave_incl_scan(deg);
     const int total = __shfl(incl, 63, 64);
     const int excl = incl - deg;
-    for (int base = 0; base < total; base += 64 * kBatch) {
-        int e[kBatch], s[kBatch];
-        bool ok[kBatch];
+    for (int base = 0; base < total; base += 64 * U) {
+        int e[U], s[U];
+        bool ok[U];
 #pragma unroll
-        for (int j = 0; j < kBatch; ++j) {
+        for (int j = 0; j < U; ++j) {
             const int k = base + j * 64 + lane;
             int o = 0;
 #pragma unroll
@@ -357,7 +363,7 @@ __device__ __forceinline__ void wave_relax_rows(const Round& R, const int* col, 
             s[j] = __shfl(sv, o, 64);
             ok[j] = k < total;
         }
-        relax_batch<A, kBatch, PUSH>(R, col, e, s, ok, nxt, acc, bound);
+        relax_batch<A, U, PUSH>(R, col, e, s, ok, nxt, acc, bound);
     }
 }
 
@@ -728,7 +734,7 @@ __global__ __launch_bounds__(256) void k_esync(Round R) {
 // entry k): the tail value, far vertices of the near-far schedule back onto
 // the frontier, heavy rows stamped for the chunk kernel, light rows walked by
 // the balanced mapping.
-template <int A>
+template <int A, int U>
 __device__ __forceinline__ void serve_list(const Round& R, const int* row, const int* col,
                                            const int* pend, int np, int nxt, bool nf, int bound,
                                            Acc& acc) {
@@ -753,8 +759,8 @@ __device__ __forceinline__ void serve_list(const Round& R, const int* row, const
     }
     const bool hv = on && re - rb > R.g.heavy;
     if (hv) R.ws.hstamp[u] = R.stamp;
-    wave_relax_rows<A, true>(R, col, on && !hv ? rb : 0, on && !hv ? re - rb : 0, sv, nxt, acc,
-                             bound);
+    wave_relax_rows<A, true, U>(R, col, on && !hv ? rb : 0, on && !hv ? re - rb : 0, sv, nxt, acc,
+                                bound);
 }
 
 // Balanced worklist round with the frontier packed per wavefront: the
@@ -762,7 +768,7 @@ __device__ __forceinline__ void serve_list(const Round& R, const int* row, const
 // 64-entry list in LDS and serves a full list at a time.  (A tile of a
 // sparse frontier holds a few flagged vertices; serving the tiles one by one
 // leaves most lanes idle in every step of the edge walk.)
-template <int A>
+template <int A, int U>
 __device__ __forceinline__ void vasync_packed(const Round& R, Acc& acc, bool nf, int bound) {
     const DevGraph& g = R.g;
     const int* row = A == CC ? g.srow : g.row;
@@ -797,20 +803,20 @@ __device__ __forceinline__ void vasync_packed(const Round& R, Acc& acc, bool nf,
             const unsigned long long om = __ballot(on);
             const int c = __popcll(om);
             if (np + c > 64) {
-                serve_list<A>(R, row, col, pend, np, nxt, nf, bound, acc);
+                serve_list<A, U>(R, row, col, pend, np, nxt, nf, bound, acc);
                 np = 0;
             }
             if (on) pend[np + __popcll(om & ((1ull << lane) - 1))] = u;
             np += c;
         }
     }
-    if (np > 0) serve_list<A>(R, row, col, pend, np, nxt, nf, bound, acc);
+    if (np > 0) serve_list<A, U>(R, row, col, pend, np, nxt, nf, bound, acc);
 }
 
-template <int A, int MAP>
+template <int A, int MAP, int U = batch_for(A, false)>
 __device__ __forceinline__ void vasync_body(const Round& R, Acc& acc, bool nf, int bound) {
     if (MAP == MAP_BALANCED) {
-        vasync_packed<A>(R, acc, nf, bound);
+        vasync_packed<A, U>(R, acc, nf, bound);
         return;
     }
     const DevGraph& g = R.g;
@@ -893,7 +899,7 @@ __global__ __launch_bounds__(256) void k_vasync(Round R) {
     const bool nf = NF;
     const int bound = nf ? nearfar_bound(R) : kInf;
     Acc acc;
-    vasync_body<A, MAP>(R, acc, nf, bound);
+    vasync_body<A, MAP, batch_for(A, NF)>(R, acc, nf, bound);
     if (nf) nearfar_finish(R, acc);
     block_finish(R, acc, R.r % 3, KIND_ROUND);
 }
@@ -1011,7 +1017,7 @@ __global__ __launch_bounds__(256) void k_bfs_diropt(Round R) {
     Acc acc;
     if (!pull) {
         // push: the balanced frontier round of k_vasync
-        vasync_packed<BFS>(R, acc, false, kInf);
+        vasync_packed<BFS, batch_for(BFS, false)>(R, acc, false, kInf);
     } else {
         // pull: one tile of 64 vertices per wavefront step; the frontier flags
         // of this round are cleared on the way (they are not read)
@@ -1120,7 +1126,7 @@ __global__ __launch_bounds__(256) void k_heavy(Round R) {
             const int e0 = __shfl(c.y, o, 64);
             const int e1 = min(e0 + g.chunk, row[u + 1]);
             const int sv = A == BFS ? R.r : R.val[u];
-            wave_relax_range<A, true>(R, col, e0, e1, sv, nxt, acc, bound);
+            wave_relax_range<A, true, batch_for(A, false)>(R, col, e0, e1, sv, nxt, acc, bound);
         }
     }
     if (nf) nearfar_finish(R, acc);

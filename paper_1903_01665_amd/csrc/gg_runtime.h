@@ -108,7 +108,7 @@ struct gg_graph_s {
     int2 *hchunks = nullptr, *shchunks = nullptr;
     int n_hchunks = 0, n_shchunks = 0;
     long long ms = 0;
-    int heavy = gg::kDefaultHeavy, chunk = gg::kChunk;
+    int heavy = gg::kHeavyUniform, chunk = gg::kChunk;
     int *psrc = nullptr, *pcol = nullptr, *pw = nullptr;  // head-partitioned edge list
     int poff[gg::kXcd + 1] = {};
     double avg_w = 0;  // mean edge weight (0 when unweighted)

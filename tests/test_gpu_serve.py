@@ -81,13 +81,16 @@ def test_memory_budget_limits_admission(gg):
         gid = srv.add_graph(gg.Graph.from_host(h))
         outs = [torch.empty(h.n, dtype=torch.int32, device="cuda") for _ in srcs]
         ids = {srv.submit(gid, 1, int(s), o): i for i, (s, o) in enumerate(zip(srcs, outs))}
-        done, peak = 0, 0
-        while done < len(srcs):
-            res = srv.poll()
-            st = srv.state()
-            peak = max(peak, st["in_flight"])
-            done += len(res)
-        assert 1 <= peak <= 2
+        spans = []
+        while len(spans) < len(srcs):
+            for qid, st, rounds, ts, ta, td in srv.poll():
+                assert st == 0 and ts <= ta <= td
+                spans.append((ta, td))
+            assert srv.state()["in_flight"] <= 2
+        # the server's own admission and completion times: at no moment were
+        # more than two queries admitted and not yet done
+        peak = max(sum(1 for a, d in spans if a <= t < d) for t, _ in spans)
+        assert 1 <= peak <= 2, spans
         torch.cuda.synchronize()
         for i, o in enumerate(outs):
             np.testing.assert_array_equal(o.cpu().numpy(), want[i])
