@@ -212,12 +212,13 @@ def main():
         g.cc(out=outs["cc"], opts=opts)
 
     # traversed edges per source (from the GPU results of a warm-up pass)
-    m_trav = {}
+    m_trav, n_reach = {}, {}
     for i, s in enumerate(sources):
         step(i)
         torch.cuda.synchronize()
         m_trav[s] = (traversed_edges(deg, outs["sssp"].cpu().numpy()),
                      traversed_edges(deg, outs["bfs"].cpu().numpy()))
+        n_reach[s] = int((outs["sssp"].cpu().numpy() < INF).sum())
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
@@ -232,6 +233,14 @@ def main():
                 + m_sym for i in range(args.steps))
     gteps = edges / elapsed / 1e9
     log(f"[bench] {args.steps} steps in {elapsed * 1e3:.1f} ms -> {gteps:.2f} GTEPS")
+    # work-efficient bytes: what one pass over the reached part needs --
+    # SSSP 12 B per traversed edge + 8 B per reached vertex, BFS and CC 8 B
+    # per edge + 8 B per vertex (n for CC) -- over the step time; redundant
+    # relaxations and extra sweeps lower it
+    we_bytes = sum(12 * m_trav[sources[i % len(sources)]][0] + 8 * n_reach[sources[i % len(sources)]]
+                   + 8 * m_trav[sources[i % len(sources)]][1] + 8 * n_reach[sources[i % len(sources)]]
+                   + 8 * m_sym + 8 * hg.n for i in range(args.steps))
+    work_efficient = round(we_bytes / elapsed / 1e9 / HBM_PEAK_GBS, 4)
 
     # ----------------------------------------- profiled repeat: roofline --
     per_kernel = []
@@ -287,7 +296,7 @@ def main():
                     mode = 1  # CC's per-round choice starts from edge sweeps
                 o = gg.make_opts(mode, sched, mp)
                 times = []
-                for _ in range(args.reps):
+                for _ in range(max(args.reps, 5 if hg.m >= 1 << 20 else 100)):
                     torch.cuda.synchronize()
                     t1 = time.perf_counter()
                     if a == "cc":
@@ -300,6 +309,8 @@ def main():
                 tm = float(np.median(times))
                 me = m_sym if a == "cc" else m_trav[s][0 if a == "sssp" else 1]
                 variants[f"{a}/{vname}"] = {"ms": round(tm * 1e3, 3),
+                                            "p99_ms": round(float(np.percentile(times, 99)) * 1e3, 3),
+                                            "reps": len(times),
                                             "GTEPS": round(me / tm / 1e9, 3),
                                             "iterations": st["iterations"],
                                             "edges_processed": st["edges_processed"]}
@@ -348,6 +359,7 @@ def main():
                    "graph_class": list(gclass),
                    "verified_vs_oracle": verified},
         "roofline": roofline,
+        "work_efficient_frac": work_efficient,
         "cpu_baseline": cpu,
         "kernels": kernel_table,
         "variants": variants,

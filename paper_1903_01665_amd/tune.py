@@ -34,9 +34,9 @@ CC_DIROPT = [(gg.EDGE, gg.DIROPT, gg.MAP_BALANCED, 0)]
 # calibration graphs: the size classes of the workloads, from a seed stream of
 # their own so that no benchmark graph is itself in the set
 CALIB_STREAM = 0xCA11B
-CALIBRATION = [("rmat", 12), ("rmat", 16), ("rmat", 20), ("rmat", 21),
-               ("er", 14), ("er", 18), ("er", 22),
-               ("grid", 128), ("grid", 512), ("grid", 2048)]
+CALIBRATION = [("rmat", 12), ("rmat", 16), ("rmat", 20), ("rmat", 21), ("rmat", 22),
+               ("er", 14), ("er", 18), ("er", 22), ("er", 23),
+               ("grid", 128), ("grid", 512), ("grid", 2048), ("grid", 4100)]
 
 
 def make(kind, p, seed):
