@@ -20,7 +20,7 @@ constexpr int kHeavySkewed = 16;
 constexpr int kHeavyUniform = 32;
 constexpr int kChunk = 256;          // edges per heavy-row chunk
 constexpr int kKinds = 3;            // statistics kinds: round, heavy chunks, auxiliary
-constexpr int kParts = 32;           // frontier work items per 64-tile group (2 tiles each)
+constexpr int kParts = 8;            // frontier work items per 64-tile group (8 tiles each)
 constexpr int kXcd = 8;              // accelerator dies; workgroups go to them round-robin
 enum Kind { KIND_ROUND = 0, KIND_HEAVY = 1, KIND_AUX = 2 };
 

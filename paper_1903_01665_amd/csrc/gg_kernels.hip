@@ -33,8 +33,10 @@
 namespace gg {
 
 // A frontier work item is one kParts-th of a 64-tile group: the wavefront
-// loads the 64 tile flags of the group at once and serves the 2 tiles of its
-// part.
+// checks the tile flags of its part (64 / kParts tiles) and serves the
+// flagged ones.  Fewer, larger items make the scan of a sparse frontier
+// cheaper (deep graphs run thousands of rounds with small frontiers) at the
+// price of balance on dense ones; 8 tiles per item measured best.
 
 // Edges each lane keeps in flight in the relaxation loops.
 constexpr int kBatch = 4;
