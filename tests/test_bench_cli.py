@@ -1,0 +1,36 @@
+"""bench.py's command line on the CPU: the one-GPU build refuses --gpus N > 1
+with a message, before touching a device."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_algorithmic_bytes_model():
+    """The per-unit byte figures of the roofline (documented beside the
+    kernels): a vertex-async SSSP round over E edges, V vertices, P pushes."""
+    sys.path.insert(0, ROOT)
+    import bench
+    prof = {"edges_processed": 1000, "vertices_processed": 100, "updates": 0, "pushes": 50,
+            "swept_edges": 0}
+    n = 6400
+    # tile flags per launch + 16 B per vertex + 12 B per edge + 2 B per push
+    assert bench.algorithmic_bytes("sssp", 0, 1, "round", n, prof, 2) == \
+        2 * (n // 64) + 16 * 100 + 12 * 1000 + 2 * 50
+    assert bench.algorithmic_bytes("sssp", 0, 1, "heavy", n, prof, 2) == 12 * 1000 + 2 * 50
+    # edge sweep: 20 B per SSSP edge, 16 B per BFS/CC edge, 4 B per update
+    prof["updates"] = 7
+    assert bench.algorithmic_bytes("cc", 1, 0, "round", n, prof, 3) == 16 * 1000 + 4 * 7
+    # CC per-round schedule: swept edges at 16 B, the rest at 8 B
+    prof["swept_edges"] = 600
+    assert bench.algorithmic_bytes("cc", 1, 4, "round", n, prof, 3) == \
+        16 * 600 + 8 * 400 + 16 * 100 + 3 * (n // 64) + 4 * 7 + 10 * 50
