@@ -212,8 +212,10 @@ int gg_cc(gg_graph g, int32_t mode, int32_t sched, int32_t* label_out_dev, void*
 
 /* Workspaces: per-query scratch (worklists, stamps, counters) so that
  * several traversals of one graph can be in flight on different streams.
- * A workspace serves one traversal at a time; a call on a workspace whose
- * previous traversal ran on another stream waits for it on the device. */
+ * A workspace serves one traversal at a time: a call on a workspace that
+ * another host thread is using at that moment returns GG_EBUSY (the graph's
+ * default workspace included), and a call on a workspace whose previous
+ * traversal ran on another stream waits for it on the device. */
 int gg_ws_create(gg_graph g, gg_ws* out);
 int gg_ws_free(gg_ws ws);
 

@@ -538,6 +538,8 @@ int run_multi(gg_graph g, gg_ws ws, int algo, int source, const int* sources_dev
     int rc = plan_make(g, ws, algo, source, sources_dev, nsrc, opts, out, s, &p);
     if (rc != GG_OK) return rc;
     ws = p.ws;
+    WsClaim claim(ws);
+    if (!claim.held()) return GG_EBUSY;
     // a workspace serves one traversal at a time: order after its last one
     if (ws->used && ws->last_stream != s) HIPCHK(g, hipStreamWaitEvent(s, ws->finished, 0));
     p.prof = (p.o.flags & GG_OPT_PROFILE) != 0;

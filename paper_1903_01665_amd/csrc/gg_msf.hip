@@ -290,6 +290,8 @@ int gg_msf(gg_graph g, gg_ws ws, uint8_t* in_msf_dev, int64_t* total_weight, int
     if (g->err != GG_OK) return g->err;
     if (!ws) ws = g->ws0;
     if (ws->owner != g || !g->weighted || (g->m > 0 && !in_msf_dev)) return GG_EINVAL;
+    WsClaim claim(ws);
+    if (!claim.held()) return GG_EBUSY;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int n = g->n;
     const int m = (int)g->m;

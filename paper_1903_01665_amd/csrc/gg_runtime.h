@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <mutex>
 #include <vector>
@@ -60,6 +61,7 @@ void dfree(T*& p) {
 
 struct gg_ws_s {
     gg_graph owner = nullptr;
+    std::atomic<bool> busy{false};  // a host call is using the workspace
     gg::DevWs dev{};
     unsigned char* vflag_mem = nullptr;
     int epoch = 0;  // round stamps of the next traversal start here
@@ -117,6 +119,20 @@ struct gg_graph_s {
 };
 
 namespace gg {
+
+// Holds a workspace for one host call; a second concurrent call on the same
+// workspace finds it taken (GG_EBUSY).
+struct WsClaim {
+    gg_ws_s* ws = nullptr;
+    explicit WsClaim(gg_ws_s* w) {
+        bool f = false;
+        if (w && w->busy.compare_exchange_strong(f, true)) ws = w;
+    }
+    ~WsClaim() {
+        if (ws) ws->busy.store(false);
+    }
+    bool held() const { return ws != nullptr; }
+};
 
 inline int fail_hip(gg_graph g, hipError_t e) {
     if (e == hipSuccess) return GG_OK;

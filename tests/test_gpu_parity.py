@@ -354,6 +354,49 @@ def test_partitioned_edge_sweep(gg):
             g.free()
 
 
+def test_one_workspace_one_host_call_at_a_time(gg):
+    """Host threads sharing a graph's default workspace: each call either
+    runs alone on it and returns the exact result, or returns GG_EBUSY."""
+    import threading
+
+    import torch
+    hg = gen.workload("rmat14")
+    srcs = [int(x) for x in gen.pick_sources(hg, 8, stream=gen.STREAM["sources"])]
+    want = {s: oracle.bfs(hg.n, hg.row_ptr, hg.col, s) for s in srcs}
+    g = gg.Graph.from_host(hg, symmetrize=True)
+    results, busy, errors = [], [], []
+    lock = threading.Lock()
+
+    def worker(k):
+        st = torch.cuda.Stream()
+        out = torch.empty(hg.n, dtype=torch.int32, device="cuda")
+        for i in range(6):
+            s = srcs[(k + i) % len(srcs)]
+            try:
+                g.bfs(s, out=out, stream=st)
+                st.synchronize()
+                with lock:
+                    results.append((s, out.cpu().numpy().copy()))
+            except gg.GGError as e:
+                with lock:
+                    (busy if e.code == -4 else errors).append(e)
+
+    try:
+        threads = [threading.Thread(target=worker, args=(k,)) for k in range(6)]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        torch.cuda.synchronize()
+        say(f"[gpu] shared workspace: {len(results)} calls ran, {len(busy)} busy")
+        assert not errors, errors
+        assert results
+        for s, got in results:
+            np.testing.assert_array_equal(got, want[s])
+    finally:
+        g.free()
+
+
 def test_auto_never_picks_an_unavailable_variant(gg):
     """A tuning table may name the direction-optimizing BFS; on a graph without
     in-neighbours AUTO falls back instead of failing."""
