@@ -152,6 +152,9 @@ def main():
     ap.add_argument("--rate", type=float, default=2000.0, help="serve: queries per second")
     ap.add_argument("--slots", type=int, default=8, help="serve: queries in flight at most")
     ap.add_argument("--no-plain", action="store_true", help="serve: skip the plain run")
+    ap.add_argument("--sequential", action="store_true",
+                    help="single: run a step's SSSP, BFS and CC one after the other on one "
+                         "stream (default: at the same time on three streams)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported",
@@ -205,11 +208,35 @@ def main():
     auto = gg.make_opts()
     chosen = {a: g.resolve(i, auto) for i, a in enumerate(ALGOS)}
 
-    def step(i, opts=None):
+    def step_sequential(i, opts=None):
         s = sources[i % len(sources)]
         g.sssp(s, out=outs["sssp"], opts=opts)
         g.bfs(s, out=outs["bfs"], opts=opts)
         g.cc(out=outs["cc"], opts=opts)
+
+    # the three traversals of a step are independent: by default they run at
+    # the same time, each on its own stream with its own workspace and no
+    # barrier between them (the paper's barrier-free independent kernels,
+    # Sec. 3.2), issued from a pool of three host threads (each call blocks
+    # until its traversal ends; the calls release the interpreter lock)
+    from concurrent.futures import ThreadPoolExecutor
+    pool = ThreadPoolExecutor(max_workers=3)
+    wss = {a: gg.Workspace(g) for a in ALGOS}
+    streams = {a: torch.cuda.Stream() for a in ALGOS}
+
+    def step_concurrent(i, opts=None):
+        s = sources[i % len(sources)]
+        futs = [pool.submit(g.sssp, s, out=outs["sssp"], opts=opts, ws=wss["sssp"],
+                            stream=streams["sssp"]),
+                pool.submit(g.bfs, s, out=outs["bfs"], opts=opts, ws=wss["bfs"],
+                            stream=streams["bfs"]),
+                pool.submit(g.cc, out=outs["cc"], opts=opts, ws=wss["cc"], stream=streams["cc"])]
+        for f in futs:
+            f.result()
+        for st in streams.values():
+            torch.cuda.current_stream().wait_stream(st)
+
+    step = step_sequential if args.sequential else step_concurrent
 
     # traversed edges per source (from the GPU results of a warm-up pass)
     m_trav, n_reach = {}, {}
@@ -351,7 +378,9 @@ def main():
         "ms_per_step": round(elapsed * 1e3 / args.steps, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": args.workload, "n": hg.n, "m": hg.m, "m_sym": m_sym,
-                   "step": "sssp+bfs+cc, AUTO variants",
+                   "step": "sssp+bfs+cc, AUTO variants, " + (
+                       "one after the other on one stream" if args.sequential
+                       else "at the same time on three streams"),
                    "variant": {a: {"mode": ["vertex", "edge"][chosen[a].mode],
                                    "sched": ["sync", "async", "auto", "nearfar", "diropt"][chosen[a].sched],
                                    "mapping": chosen[a].mapping} for a in ALGOS},
@@ -365,6 +394,9 @@ def main():
         "variants": variants,
     }
     print(json.dumps(line), flush=True)
+    pool.shutdown()
+    for w in wss.values():
+        w.free()
     g.free()
 
 
