@@ -241,7 +241,7 @@ def main():
     # traversed edges per source (from the GPU results of a warm-up pass)
     m_trav, n_reach = {}, {}
     for i, s in enumerate(sources):
-        step(i)
+        step_sequential(i)
         torch.cuda.synchronize()
         m_trav[s] = (traversed_edges(deg, outs["sssp"].cpu().numpy()),
                      traversed_edges(deg, outs["bfs"].cpu().numpy()))
