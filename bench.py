@@ -43,8 +43,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 INF = 2**31 - 1
 ALGOS = ("sssp", "bfs", "cc")
-VARIANTS = {"vertex-sync": (0, 0, 3), "vertex-async": (0, 1, 3), "edge-sync": (1, 0, 0),
-            "edge-async": (1, 1, 0), "nearfar": (0, 3, 3), "diropt": (0, 4, 3)}
+# (mode, schedule, mapping, passes of local expansion)
+VARIANTS = {"vertex-sync": (0, 0, 3, 0), "vertex-async": (0, 1, 3, 0), "edge-sync": (1, 0, 0, 0),
+            "edge-async": (1, 1, 0, 0), "nearfar": (0, 3, 3, 0), "diropt": (0, 4, 3, 0),
+            "vertex-async-h8": (0, 1, 3, 8), "nearfar-h32": (0, 3, 3, 32)}
 
 
 def log(*a):
@@ -62,6 +64,9 @@ def log(*a):
 #   vertex async  1 B per tile flag scanned; 16 B per frontier vertex (flag,
 #                 row pair, value); per edge 12 B SSSP / 8 B BFS, CC;
 #                 2 B per push (vertex and tile flag bytes)
+#                 (local expansion: a vertex served again from the
+#                 wavefront's own list reads only its row pair, 8 B; it is
+#                 counted at 16 B here, an upper bound)
 #   edge async    as vertex async, plus the 4 B edge-list source per edge
 #   CC diropt     swept edges as edge sync (16 B), the other edges, vertices
 #                 and tiles as vertex async; 4 B per update; per push 2 B of
@@ -97,7 +102,7 @@ def algorithmic_bytes(algo, mode, sched, kind, n, prof_kind, launches):
     return (4 + (2 if sched == 1 else 0)) * n + 8 * n * max(0, launches - 1)
 
 
-def kernel_symbol(algo, kind, mode, sched, mapping):
+def kernel_symbol(algo, kind, mode, sched, mapping, hops=0):
     """HIP symbol of the kernel that runs (algo, kind) in a variant."""
     a = {"sssp": 0, "bfs": 1, "cc": 2}[algo]
     if kind == "heavy":
@@ -111,6 +116,8 @@ def kernel_symbol(algo, kind, mode, sched, mapping):
     if sched == 0:
         return f"void gg::k_vsync<{a}, {mapping}>(gg::Round)"
     nf = "true" if sched == 3 else "false"  # the near-far schedule has its own instantiation
+    if hops > 0 and mapping == 3:  # worklist rounds with local expansion
+        return f"void gg::k_vlocal<{a}, {nf}>(gg::Round)"
     return f"void gg::k_vasync<{a}, {mapping}, {nf}>(gg::Round)"
 
 
@@ -296,8 +303,10 @@ def main():
     (da, dk), (dl, dms, db) = max(agg.items(), key=lambda kv: kv[1][1])
     c = chosen[da]
     mname = ["vertex", "edge"][c.mode] + "-" + ["sync", "async", "auto", "nearfar", "diropt"][c.sched]
+    if c.hops:
+        mname += f"-h{c.hops}"
     achieved = db / (dms * 1e-3) / 1e9
-    sym = kernel_symbol(da, dk, c.mode, c.sched, c.mapping)
+    sym = kernel_symbol(da, dk, c.mode, c.sched, c.mapping, c.hops)
     traffic = measured_traffic(sym, args.workload)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -316,12 +325,14 @@ def main():
     if not args.no_variants:
         s = sources[0]
         for a in ALGOS:
-            for vname, (mode, sched, mp) in VARIANTS.items():
+            for vname, (mode, sched, mp, hops) in VARIANTS.items():
                 if (sched == 3 and a != "sssp") or (sched == 4 and a == "sssp"):
                     continue  # near-far is an SSSP schedule, the per-round choice BFS/CC
+                if hops and a == "cc":
+                    continue  # label propagation gains nothing from local expansion
                 if sched == 4 and a == "cc":
                     mode = 1  # CC's per-round choice starts from edge sweeps
-                o = gg.make_opts(mode, sched, mp)
+                o = gg.make_opts(mode, sched, mp, hops=hops)
                 times = []
                 for _ in range(max(args.reps, 5 if hg.m >= 1 << 20 else 100)):
                     torch.cuda.synchronize()
@@ -383,7 +394,8 @@ def main():
                        else "at the same time on three streams"),
                    "variant": {a: {"mode": ["vertex", "edge"][chosen[a].mode],
                                    "sched": ["sync", "async", "auto", "nearfar", "diropt"][chosen[a].sched],
-                                   "mapping": chosen[a].mapping} for a in ALGOS},
+                                   "mapping": chosen[a].mapping,
+                                   "hops": chosen[a].hops} for a in ALGOS},
                    "sources": sources, "upload_s": round(upload_s, 2),
                    "graph_class": list(gclass),
                    "verified_vs_oracle": verified},

@@ -125,7 +125,16 @@ typedef struct {
     int32_t time_limit_ms; /* 0 = default (60000); no round is launched after it (GG_ETIMEOUT) */
     int32_t flags;         /* GG_OPT_* bits */
     int32_t delta;         /* GG_NEARFAR bucket width; 0 = default (from the average weight) */
-    int32_t reserved[3];
+    int32_t hops;          /* local expansion of worklist rounds (GG_ASYNC or GG_NEARFAR,
+                              vertex-based, BALANCED mapping), 0..64; 0 = off.  A wavefront
+                              serves the vertices it has just lowered (those below the
+                              near-far bound) again in the same round, up to `hops` times,
+                              from a 64-entry list of its own; what does not fit, and the
+                              list left after the last pass, goes to the next round's
+                              frontier.  Fewer rounds on high-diameter graphs; the result
+                              is the same.  Ignored by other variants; with
+                              GG_SCHED_AUTO the tuned choice sets it. */
+    int32_t reserved[2];
 } gg_opts;
 
 /* gg_opts.flags */
@@ -274,6 +283,8 @@ typedef struct {
     int32_t algo, size_class, skew_class, depth_class; /* depth -1 = any */
     int32_t mode, sched, mapping;
     int32_t delta_mult; /* GG_NEARFAR: bucket width in mean edge weights (0 = 4) */
+    int32_t hops;       /* gg_opts.hops of the variant, 0..64; nonzero only for vertex-based
+                           GG_ASYNC or GG_NEARFAR with the BALANCED (or AUTO) mapping */
 } gg_tune_entry;
 
 /* Replace the process-wide tuning table (count 0 clears it).  The entries
@@ -290,9 +301,10 @@ int gg_class_of(int64_t m, int32_t n, int32_t max_out_degree, int32_t levels,
                 int32_t* size_class, int32_t* skew_class, int32_t* depth_class);
 
 /* Variant the table (else the built-in rules) picks for an algorithm and a
- * class, as gg_resolve would.  Outputs may not be NULL. */
+ * class, as gg_resolve would.  Outputs may not be NULL, except `hops`. */
 int gg_tune_lookup(int32_t algo, int32_t size_class, int32_t skew_class, int32_t depth_class,
-                   int32_t* mode, int32_t* sched, int32_t* mapping, int32_t* delta_mult);
+                   int32_t* mode, int32_t* sched, int32_t* mapping, int32_t* delta_mult,
+                   int32_t* hops);
 
 /* Measure the graph's depth class (one BFS on `stream`, waited for) and keep
  * it on the handle; later AUTO resolutions use it. */

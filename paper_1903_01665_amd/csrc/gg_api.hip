@@ -230,10 +230,15 @@ void resolve(gg_graph g, int algo, const gg_opts* in, gg_opts* out) {
                             o.sched != GG_DIROPT;
     const bool auto_map = o.mapping < GG_MAP_THREAD || o.mapping > GG_MAP_BALANCED;
     int32_t sc = 0, kc = 0, dc = -1, tm = GG_VERTEX, ts = GG_ASYNC, tp = GG_MAP_BALANCED, td = 0;
+    int32_t th = 0;
     gg_class_of(g->m, g->n, g->max_deg, g->levels, &sc, &kc, &dc);
-    gg_tune_lookup(algo, sc, kc, dc, &tm, &ts, &tp, &td);
+    gg_tune_lookup(algo, sc, kc, dc, &tm, &ts, &tp, &td, &th);
     if (auto_mode) o.mode = tm;
-    if (auto_sched) o.sched = ts;
+    // the tuned schedule comes with its local expansion
+    if (auto_sched) {
+        o.sched = ts;
+        o.hops = th;
+    }
     // an explicit per-round schedule fixes the mode it runs in
     if (!auto_sched && o.sched == GG_DIROPT && auto_mode)
         o.mode = algo == GG_ALGO_CC ? GG_EDGE : GG_VERTEX;
@@ -287,7 +292,7 @@ int plan_make(gg_graph g, gg_ws ws, int algo, int source, const int* sources_dev
     const bool nearfar = o.sched == GG_NEARFAR;
     if (nearfar && (algo != GG_ALGO_SSSP || o.mode != GG_VERTEX || o.mapping != GG_MAP_BALANCED))
         return GG_ENOTSUP;
-    if (o.delta < 0) return GG_EINVAL;
+    if (o.delta < 0 || o.hops < 0 || o.hops > 64) return GG_EINVAL;
     const bool diropt = o.sched == GG_DIROPT;
     if (diropt && !diropt_ok(g, algo, o.mode)) return GG_ENOTSUP;
     const Dev& dv = device();
@@ -313,6 +318,7 @@ int plan_make(gg_graph g, gg_ws ws, int algo, int source, const int* sources_dev
     // of several light edges)
     R.delta = nearfar ? std::max(1, o.delta) : 0;
     R.fedges = p.cc && diropt;
+    R.hops = p.async && !p.edge && !diropt && o.mapping == GG_MAP_BALANCED ? o.hops : 0;
 
     const int wpb = kBlock / 64;
     const long long n = g->n;

@@ -108,6 +108,7 @@ struct Round {
     int delta;   // SSSP near-far schedule: bucket width (0 = plain worklist rounds)
     int fedges;  // CC per-round dense/sparse choice: push counts are the row lengths
                  // (both-directions CSR) of the pushed vertices, and edge sweeps push
+    int hops;    // worklist rounds (balanced mapping): passes of local expansion (0 = off)
 };
 
 // Launch entry points (gg_kernels.hip).  Each returns the hipError_t of the

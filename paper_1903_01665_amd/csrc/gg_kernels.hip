@@ -272,7 +272,10 @@ __device__ __forceinline__ bool relax_edge(const Round& R, const int* col, int e
 // first compare: column indices (and weights), then head values, then the
 // atomics.  Reading every head value before any atomic of the batch is safe
 // because values only decrease.  ok[j] masks the lanes that own an edge.
-template <int A, int U, bool PUSH>
+// ATOM: BFS lowers levels with atomicMin instead of a plain store (needed
+// when the tails of one round hold different levels, as under local
+// expansion; a plain store could then overwrite a lower level).
+template <int A, int U, bool PUSH, bool ATOM = false>
 __device__ __forceinline__ void relax_batch(const Round& R, const int* col, const int (&e)[U],
                                             const int (&sv)[U], const bool (&ok)[U], int nxt,
                                             Acc& acc, int bound = kInf) {
@@ -297,8 +300,12 @@ __device__ __forceinline__ void relax_batch(const Round& R, const int* col, cons
         } else if (A == BFS) {
             const int nl = sv[j] + 1;
             if (cur[j] > nl) {
-                val[t[j]] = nl;
-                hit = true;
+                if (ATOM) {
+                    hit = nl < atomicMin(&val[t[j]], nl);
+                } else {
+                    val[t[j]] = nl;
+                    hit = true;
+                }
             }
         } else {
             if (sv[j] < cur[j]) hit = sv[j] < atomicMin(&val[t[j]], sv[j]);
@@ -321,7 +328,7 @@ __device__ __forceinline__ void relax_batch(const Round& R, const int* col, cons
 
 // The edges [e0, e1) of one row, all with tail value sv, relaxed by the
 // whole wavefront U x 64 edges per step.
-template <int A, bool PUSH, int U = kBatch>
+template <int A, bool PUSH, int U = kBatch, bool ATOM = false>
 __device__ __forceinline__ void wave_relax_range(const Round& R, const int* col, int e0, int e1,
                                                  int sv, int nxt, Acc& acc, int bound = kInf) {
     const int lane = threadIdx.x & 63;
@@ -334,7 +341,7 @@ __device__ __forceinline__ void wave_relax_range(const Round& R, const int* col,
             ok[j] = e[j] < e1;
             s[j] = sv;
         }
-        relax_batch<A, U, PUSH>(R, col, e, s, ok, nxt, acc, bound);
+        relax_batch<A, U, PUSH, ATOM>(R, col, e, s, ok, nxt, acc, bound);
     }
 }
 
@@ -401,6 +408,95 @@ __device__ __forceinline__ bool tail_value(const Round& R, int u, int& sv, Acc& 
 __device__ __forceinline__ void push(const Round& R, int nxt, int t) {
     R.ws.vflag[nxt][t] = 1;
     R.ws.tflag[nxt][t >> 6] = 1;
+}
+
+// ------------------------------------------------------ local expansion ----
+// A worklist round with local expansion (Round::hops > 0) lets a wavefront
+// serve again, within the same round, the vertices it has just lowered: a
+// successful relaxation whose new value is below the round's bound goes,
+// with that value, to a list of kLocalCap entries in the wavefront's LDS
+// instead of the next frontier, and the wavefront serves the list up to
+// `hops` times.  Entries past the capacity, and the list left after the last
+// pass, go to the next frontier.  Serving a vertex with the value this lane
+// wrote is safe: if another lane lowered it further since, that lane put it
+// on a list or the frontier itself.  On a high-diameter graph this advances
+// the frontier several steps per launch; the fixpoint is the same.
+constexpr int kLocalCap = 64;
+
+template <int A, int U>
+__device__ __forceinline__ void relax_batch_local(const Round& R, const int* col,
+                                                  const int (&e)[U], const int (&sv)[U],
+                                                  const bool (&ok)[U], int nxt, Acc& acc,
+                                                  int bound, int2* lst, int& ln) {
+    int* val = R.val;
+    const int lane = threadIdx.x & 63;
+    int t[U], wt[U], cur[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) t[j] = ok[j] ? col[e[j]] : 0;
+    if (A == SSSP) {
+#pragma unroll
+        for (int j = 0; j < U; ++j) wt[j] = ok[j] ? R.g.w[e[j]] : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) cur[j] = ok[j] ? val[t[j]] : 0;
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+        bool hit = false;
+        int nv = 0;
+        if (ok[j]) {
+            acc.e++;
+            if (A == SSSP) {
+                const unsigned cand = (unsigned)sv[j] + (unsigned)wt[j];
+                if (cand < (unsigned)cur[j]) {
+                    nv = (int)cand;
+                    hit = nv < atomicMin(&val[t[j]], nv);
+                }
+            } else {
+                nv = A == BFS ? sv[j] + 1 : sv[j];
+                if (nv < cur[j]) hit = nv < atomicMin(&val[t[j]], nv);
+            }
+        }
+        const bool keep = hit && nv < bound;
+        const unsigned long long km = __ballot(keep);
+        const int pos = ln + __popcll(km & ((1ull << lane) - 1));
+        if (keep && pos < kLocalCap) {
+            lst[pos] = make_int2(t[j], nv);
+        } else if (hit) {
+            push(R, nxt, t[j]);
+            acc.p++;
+            if (nv < bound) acc.nr = 1;
+        }
+        ln = min(ln + __popcll(km), kLocalCap);
+    }
+}
+
+// wave_relax_rows with relax_batch_local.
+template <int A, int U>
+__device__ __forceinline__ void wave_relax_rows_local(const Round& R, const int* col, int beg,
+                                                      int deg, int sv, int nxt, Acc& acc,
+                                                      int bound, int2* lst, int& ln) {
+    const int lane = threadIdx.x & 63;
+    const int incl = wave_incl_scan(deg);
+    const int total = __shfl(incl, 63, 64);
+    const int excl = incl - deg;
+    for (int base = 0; base < total; base += 64 * U) {
+        int e[U], s[U];
+        bool ok[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int k = base + j * 64 + lane;
+            int o = 0;
+#pragma unroll
+            for (int step = 32; step > 0; step >>= 1) {
+                const int cand = o + step;
+                if (__shfl(excl, cand, 64) <= k) o = cand;
+            }
+            e[j] = __shfl(beg, o, 64) + (k - __shfl(excl, o, 64));
+            s[j] = __shfl(sv, o, 64);
+            ok[j] = k < total;
+        }
+        relax_batch_local<A, U>(R, col, e, s, ok, nxt, acc, bound, lst, ln);
+    }
 }
 
 // ------------------------------------------------------------ kernels ----
@@ -906,6 +1002,131 @@ __global__ __launch_bounds__(256) void k_vasync(Round R) {
     block_finish(R, acc, R.r % 3, KIND_ROUND);
 }
 
+// serve_list under local expansion: the frontier vertices in pend (their
+// current values read here; BFS too, since levels differ within a round),
+// then up to R.hops passes over the wavefront's own list.  lb holds two
+// lists of kLocalCap (vertex, value) entries that the passes alternate.
+template <int A, int U>
+__device__ __forceinline__ void serve_local(const Round& R, const int* row, const int* col,
+                                            const int* pend, int np, int nxt, bool nf, int bound,
+                                            Acc& acc, int2* lb) {
+    const int lane = threadIdx.x & 63;
+    __builtin_amdgcn_wave_barrier();
+    int u = lane < np ? pend[lane] : -1;
+    __builtin_amdgcn_wave_barrier();
+    bool on = u >= 0;
+    int rb = 0, re = 0, sv = 0;
+    if (on) {
+        if (A == BFS) sv = R.val[u];
+        else tail_value<A, true>(R, u, sv, acc);
+        if (nf && sv >= bound) {
+            push(R, nxt, u);
+            acc.u++;
+            on = false;
+        } else {
+            rb = row[u];
+            re = row[u + 1];
+            acc.v++;
+        }
+    }
+    bool hv = on && re - rb > R.g.heavy;
+    if (hv) R.ws.hstamp[u] = R.stamp;
+    int ln = 0;
+    wave_relax_rows_local<A, U>(R, col, on && !hv ? rb : 0, on && !hv ? re - rb : 0, sv, nxt, acc,
+                                bound, lb, ln);
+    for (int pass = 1; ln > 0; ++pass) {
+        const int2* cur = lb + ((pass - 1) & 1) * kLocalCap;
+        int2* nx = lb + (pass & 1) * kLocalCap;
+        const int cn = ln;
+        ln = 0;
+        __builtin_amdgcn_wave_barrier();
+        const int2 x = lane < cn ? cur[lane] : make_int2(-1, 0);
+        __builtin_amdgcn_wave_barrier();
+        if (pass > R.hops) {
+            // out of passes: the list goes to the next frontier
+            if (x.x >= 0) {
+                push(R, nxt, x.x);
+                acc.p++;
+                acc.nr = 1;
+            }
+            break;
+        }
+        u = x.x;
+        sv = x.y;
+        on = u >= 0;
+        rb = re = 0;
+        if (on) {
+            rb = row[u];
+            re = row[u + 1];
+            acc.v++;
+        }
+        hv = on && re - rb > R.g.heavy;
+        if (hv) R.ws.hstamp[u] = R.stamp;
+        wave_relax_rows_local<A, U>(R, col, on && !hv ? rb : 0, on && !hv ? re - rb : 0, sv, nxt,
+                                    acc, bound, nx, ln);
+    }
+}
+
+// vasync_packed with serve_local.
+template <int A, int U>
+__device__ __forceinline__ void vasync_local(const Round& R, Acc& acc, bool nf, int bound) {
+    const DevGraph& g = R.g;
+    const int* row = A == CC ? g.srow : g.row;
+    const int* col = A == CC ? g.scol : g.col;
+    const int n = g.n;
+    const int cur = R.r & 1, nxt = cur ^ 1;
+    unsigned char* vf = R.ws.vflag[cur];
+    unsigned char* tf = R.ws.tflag[cur];
+    const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    const long long gw = (long long)blockIdx.x * wpb + (threadIdx.x >> 6);
+    const long long tw = (long long)gridDim.x * wpb;
+    const long long ntiles = (n + 63) / 64;
+    const long long nitems = (ntiles + 63) / 64 * kParts;
+    __shared__ int s_pend[4][64];  // blocks of 256 threads: four wavefronts
+    __shared__ int2 s_loc[4][2 * kLocalCap];
+    int* pend = s_pend[threadIdx.x >> 6];
+    int2* lb = s_loc[threadIdx.x >> 6];
+    int np = 0;
+    for (long long it = gw; it < nitems; it += tw) {
+        const long long st = it / kParts;
+        const int part = (int)(it % kParts);
+        const long long t = st * 64 + lane;
+        const bool mine = lane / (64 / kParts) == part;
+        const bool tfl = mine && t < ntiles && tf[t] != 0;
+        unsigned long long tm = __ballot(tfl);
+        if (tfl) tf[t] = 0;
+        while (tm) {
+            const int b = __ffsll(tm) - 1;
+            tm &= tm - 1;
+            const int u = (int)((st * 64 + b) * 64 + lane);
+            const bool on = u < n && vf[u] != 0;
+            if (on) vf[u] = 0;
+            const unsigned long long om = __ballot(on);
+            const int c = __popcll(om);
+            if (np + c > 64) {
+                serve_local<A, U>(R, row, col, pend, np, nxt, nf, bound, acc, lb);
+                np = 0;
+            }
+            if (on) pend[np + __popcll(om & ((1ull << lane) - 1))] = u;
+            np += c;
+        }
+    }
+    if (np > 0) serve_local<A, U>(R, row, col, pend, np, nxt, nf, bound, acc, lb);
+}
+
+// Worklist round with local expansion (balanced mapping; NF: near-far).
+template <int A, bool NF>
+__global__ __launch_bounds__(256) void k_vlocal(Round R) {
+    if (!round_begin(R)) return;
+    const int bound = NF ? nearfar_bound(R) : kInf;
+    Acc acc;
+    // the plain rounds' edges in flight: eight (near-far) spill here
+    vasync_local<A, batch_for(A, false)>(R, acc, NF, bound);
+    if (NF) nearfar_finish(R, acc);
+    block_finish(R, acc, R.r % 3, KIND_ROUND);
+}
+
 // Asynchronous edge round: for every flagged tile the wavefront walks the
 // tile's edge-list range lane by lane (one lane per edge, source from the
 // edge list) and relaxes the edges whose source is on the frontier.  Runs of
@@ -1127,8 +1348,14 @@ __global__ __launch_bounds__(256) void k_heavy(Round R) {
             const int u = __shfl(c.x, o, 64);
             const int e0 = __shfl(c.y, o, 64);
             const int e1 = min(e0 + g.chunk, row[u + 1]);
-            const int sv = A == BFS ? R.r : R.val[u];
-            wave_relax_range<A, true, batch_for(A, false)>(R, col, e0, e1, sv, nxt, acc, bound);
+            // BFS: the round's level, or under local expansion (levels
+            // differ within a round) the row's own level, lowered atomically
+            if (A == BFS && R.hops > 0)
+                wave_relax_range<A, true, batch_for(A, false), true>(R, col, e0, e1, R.val[u], nxt,
+                                                                     acc, bound);
+            else
+                wave_relax_range<A, true, batch_for(A, false)>(
+                    R, col, e0, e1, A == BFS ? R.r : R.val[u], nxt, acc, bound);
         }
     }
     if (nf) nearfar_finish(R, acc);
@@ -1355,7 +1582,11 @@ static hipError_t vasync_a(const Round& R, int grid, int block, hipStream_t s) {
         case MAP_WAVE: GG_LAUNCH((k_vasync<A, MAP_WAVE>), grid, block, s, R);
         default:
             if constexpr (A == SSSP)
-                if (R.delta > 0) GG_LAUNCH((k_vasync<A, MAP_BALANCED, true>), grid, block, s, R);
+                if (R.delta > 0) {
+                    if (R.hops > 0) GG_LAUNCH((k_vlocal<A, true>), grid, block, s, R);
+                    GG_LAUNCH((k_vasync<A, MAP_BALANCED, true>), grid, block, s, R);
+                }
+            if (R.hops > 0) GG_LAUNCH((k_vlocal<A, false>), grid, block, s, R);
             GG_LAUNCH((k_vasync<A, MAP_BALANCED>), grid, block, s, R);
     }
 }

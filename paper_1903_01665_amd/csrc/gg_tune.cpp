@@ -22,7 +22,9 @@ bool valid(const gg_tune_entry& e) {
             (e.sched == GG_DIROPT && e.algo == GG_ALGO_BFS && e.mode == GG_VERTEX) ||
             (e.sched == GG_DIROPT && e.algo == GG_ALGO_CC && e.mode == GG_EDGE)) &&
            e.mapping >= GG_MAP_AUTO && e.mapping <= GG_MAP_BALANCED && e.delta_mult >= 0 &&
-           e.delta_mult <= 1 << 20;
+           e.delta_mult <= 1 << 20 && e.hops >= 0 && e.hops <= 64 &&
+           (e.hops == 0 || (e.mode == GG_VERTEX && (e.sched == GG_ASYNC || e.sched == GG_NEARFAR) &&
+                            (e.mapping == GG_MAP_AUTO || e.mapping == GG_MAP_BALANCED)));
 }
 
 // Built-in choice, from the measured behaviour of the variants on the
@@ -30,9 +32,10 @@ bool valid(const gg_tune_entry& e) {
 // rounds for SSSP everywhere; BFS synchronous on shallow graphs and
 // asynchronous on deep ones; CC by edge sweeps with the shortcut.
 void builtin(int algo, int depth, int32_t* mode, int32_t* sched, int32_t* mapping,
-             int32_t* delta_mult) {
+             int32_t* delta_mult, int32_t* hops) {
     *mapping = GG_MAP_BALANCED;
     *delta_mult = 0;
+    *hops = 0;
     if (algo == GG_ALGO_SSSP) {
         *mode = GG_VERTEX;
         *sched = GG_ASYNC;
@@ -80,8 +83,10 @@ int gg_tune_get(gg_tune_entry* out, int32_t cap) {
 }
 
 int gg_tune_lookup(int32_t algo, int32_t size_class, int32_t skew_class, int32_t depth_class,
-                   int32_t* mode, int32_t* sched, int32_t* mapping, int32_t* delta_mult) {
+                   int32_t* mode, int32_t* sched, int32_t* mapping, int32_t* delta_mult,
+                   int32_t* hops) {
     if (algo < 0 || algo > 2 || !mode || !sched || !mapping || !delta_mult) return GG_EINVAL;
+    int32_t h = 0;
     std::lock_guard<std::mutex> lk(g_mu);
     int best = -1, best_score = 1 << 30;
     for (int i = 0; i < (int)g_table.size(); ++i) {
@@ -96,13 +101,15 @@ int gg_tune_lookup(int32_t algo, int32_t size_class, int32_t skew_class, int32_t
         }
     }
     if (best < 0) {
-        builtin(algo, depth_class, mode, sched, mapping, delta_mult);
+        builtin(algo, depth_class, mode, sched, mapping, delta_mult, &h);
     } else {
         *mode = g_table[best].mode;
         *sched = g_table[best].sched;
         *mapping = g_table[best].mapping == GG_MAP_AUTO ? GG_MAP_BALANCED : g_table[best].mapping;
         *delta_mult = g_table[best].delta_mult;
+        h = g_table[best].hops;
     }
+    if (hops) *hops = h;
     return GG_OK;
 }
 

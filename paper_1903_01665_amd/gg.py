@@ -55,7 +55,7 @@ class Opts(ctypes.Structure):
                 ("block_threads", ctypes.c_int32), ("max_blocks", ctypes.c_int32),
                 ("heavy_threshold", ctypes.c_int32), ("time_limit_ms", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("delta", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("hops", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class Stats(ctypes.Structure):
@@ -74,7 +74,7 @@ class TuneEntry(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("size_class", ctypes.c_int32),
                 ("skew_class", ctypes.c_int32), ("depth_class", ctypes.c_int32),
                 ("mode", ctypes.c_int32), ("sched", ctypes.c_int32), ("mapping", ctypes.c_int32),
-                ("delta_mult", ctypes.c_int32)]
+                ("delta_mult", ctypes.c_int32), ("hops", ctypes.c_int32)]
 
 
 class Instance(ctypes.Structure):
@@ -138,7 +138,7 @@ def lib():
     L.gg_tune_set.argtypes = [P(TuneEntry), i32]
     L.gg_tune_get.argtypes = [P(TuneEntry), i32]
     L.gg_class_of.argtypes = [i64, i32, i32, i32, P(i32), P(i32), P(i32)]
-    L.gg_tune_lookup.argtypes = [i32, i32, i32, i32, P(i32), P(i32), P(i32), P(i32)]
+    L.gg_tune_lookup.argtypes = [i32, i32, i32, i32, P(i32), P(i32), P(i32), P(i32), P(i32)]
     L.gg_graph_probe.argtypes = [vp, vp]
     L.gg_graph_class.argtypes = [vp, P(i32), P(i32), P(i32)]
     L.gg_batch_create.argtypes = [P(Instance), i32, u32, vp, P(vp)]
@@ -174,12 +174,14 @@ def lib():
 # ------------------------------------------------------------- tuning ------
 def tune_set(entries):
     """Install a tuning table: a list of dicts with algo, size_class,
-    skew_class, depth_class, mode, sched, mapping."""
+    skew_class, depth_class, mode, sched, mapping (and optionally delta_mult,
+    hops)."""
     arr = (TuneEntry * max(1, len(entries)))()
     for i, e in enumerate(entries):
         for k in ("algo", "size_class", "skew_class", "depth_class", "mode", "sched", "mapping"):
             setattr(arr[i], k, int(e[k]))
         arr[i].delta_mult = int(e.get("delta_mult", 0))
+        arr[i].hops = int(e.get("hops", 0))
     _check(lib().gg_tune_set(arr, len(entries)), "gg_tune_set")
 
 
@@ -204,11 +206,14 @@ def class_of(m, n, max_out_degree, levels=-1):
 
 
 def tune_lookup(algo, size_class, skew_class, depth_class, with_delta=False):
-    a, b, c, d = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    """(mode, sched, mapping), or with_delta (mode, sched, mapping,
+    delta_mult, hops)."""
+    a, b, c, d, h = (ctypes.c_int32() for _ in range(5))
     _check(lib().gg_tune_lookup(algo, size_class, skew_class, depth_class, ctypes.byref(a),
-                                ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)),
-           "gg_tune_lookup")
-    return (a.value, b.value, c.value, d.value) if with_delta else (a.value, b.value, c.value)
+                                ctypes.byref(b), ctypes.byref(c), ctypes.byref(d),
+                                ctypes.byref(h)), "gg_tune_lookup")
+    return ((a.value, b.value, c.value, d.value, h.value) if with_delta
+            else (a.value, b.value, c.value))
 
 
 def _check(rc, what):
@@ -229,10 +234,11 @@ def _arr(a):
 
 
 def make_opts(mode=MODE_AUTO, sched=SCHED_AUTO, mapping=MAP_AUTO, max_blocks=0, flags=0,
-              time_limit_ms=0, delta=0) -> Opts:
+              time_limit_ms=0, delta=0, hops=0) -> Opts:
     o = Opts()
     o.mode, o.sched, o.mapping = mode, sched, mapping
     o.max_blocks, o.flags, o.time_limit_ms, o.delta = max_blocks, flags, time_limit_ms, delta
+    o.hops = hops
     return o
 
 

@@ -6,8 +6,11 @@ from one program and picks the variant per input by a compile-time switch
 runs on a calibration set of synthetic graphs of each class (size, degree
 skew, BFS depth: see gg_class_of in include/gg.h); for each (algorithm,
 class) the variant with the lowest geometric mean of its time relative to
-the best variant of each graph wins.  The table is written as JSON and the
-binding installs it when the library loads.
+the best variant of each graph wins.  A graph's time for a variant is the sum
+over a few sources of the median of repeated runs (traversal times vary with
+the source).  Variants include the near-far bucket width and the passes of
+local expansion.  The table is written as JSON and the binding installs it
+when the library loads.
 
     python -m paper_1903_01665_amd.tune --out paper_1903_01665_amd/tune_table.json
 """
@@ -22,14 +25,18 @@ import time
 from . import gen, gg
 
 ALGOS = ("sssp", "bfs", "cc")
-# (mode, schedule, mapping, near-far bucket width in mean weights)
-VARIANTS = [(gg.VERTEX, gg.SYNC, gg.MAP_THREAD, 0), (gg.VERTEX, gg.SYNC, gg.MAP_WAVE, 0),
-            (gg.VERTEX, gg.SYNC, gg.MAP_BALANCED, 0), (gg.VERTEX, gg.ASYNC, gg.MAP_THREAD, 0),
-            (gg.VERTEX, gg.ASYNC, gg.MAP_WAVE, 0), (gg.VERTEX, gg.ASYNC, gg.MAP_BALANCED, 0),
-            (gg.EDGE, gg.SYNC, gg.MAP_AUTO, 0), (gg.EDGE, gg.ASYNC, gg.MAP_AUTO, 0)]
-NEARFAR = [(gg.VERTEX, gg.NEARFAR, gg.MAP_BALANCED, dm) for dm in (1, 2, 4, 8, 16, 64)]
-DIROPT = [(gg.VERTEX, gg.DIROPT, gg.MAP_BALANCED, 0)]
-CC_DIROPT = [(gg.EDGE, gg.DIROPT, gg.MAP_BALANCED, 0)]
+# (mode, schedule, mapping, near-far bucket width in mean weights, passes of
+# local expansion)
+VARIANTS = [(gg.VERTEX, gg.SYNC, gg.MAP_THREAD, 0, 0), (gg.VERTEX, gg.SYNC, gg.MAP_WAVE, 0, 0),
+            (gg.VERTEX, gg.SYNC, gg.MAP_BALANCED, 0, 0), (gg.VERTEX, gg.ASYNC, gg.MAP_THREAD, 0, 0),
+            (gg.VERTEX, gg.ASYNC, gg.MAP_WAVE, 0, 0), (gg.VERTEX, gg.ASYNC, gg.MAP_BALANCED, 0, 0),
+            (gg.EDGE, gg.SYNC, gg.MAP_AUTO, 0, 0), (gg.EDGE, gg.ASYNC, gg.MAP_AUTO, 0, 0)]
+LOCAL = [(gg.VERTEX, gg.ASYNC, gg.MAP_BALANCED, 0, h) for h in (2, 8)]
+NEARFAR = ([(gg.VERTEX, gg.NEARFAR, gg.MAP_BALANCED, dm, 0) for dm in (1, 2, 4, 8, 16, 64)] +
+           [(gg.VERTEX, gg.NEARFAR, gg.MAP_BALANCED, dm, h) for dm in (1, 2, 4, 8, 16)
+            for h in (2, 8, 32)])
+DIROPT = [(gg.VERTEX, gg.DIROPT, gg.MAP_BALANCED, 0, 0)]
+CC_DIROPT = [(gg.EDGE, gg.DIROPT, gg.MAP_BALANCED, 0, 0)]
 
 # calibration graphs: the size classes of the workloads, from a seed stream of
 # their own so that no benchmark graph is itself in the set
@@ -49,33 +56,69 @@ def make(kind, p, seed):
                     seed=seed, name=f"grid{p}")
 
 
-def time_variant(g, algo, src, v, reps, out, avg_w):
+def time_variant(g, algo, srcs, v, reps, out, avg_w):
+    """Sum over the sources of the median time of `reps` runs (CC: one
+    source-free run set)."""
     import torch
-    mode, sched, mapping, dm = v
+    mode, sched, mapping, dm, hops = v
     o = gg.make_opts(mode, sched, mapping, time_limit_ms=4000,
-                     delta=max(1, int(dm * avg_w)) if sched == gg.NEARFAR else 0)
-    ts = []
-    for _ in range(reps):
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        try:
-            if algo == "cc":
-                g.cc(opts=o, out=out)
-            else:
-                getattr(g, algo)(src, opts=o, out=out)
+                     delta=max(1, int(dm * avg_w)) if sched == gg.NEARFAR else 0, hops=hops)
+    total = 0.0
+    for src in srcs[:1] if algo == "cc" else srcs:
+        ts = []
+        for _ in range(reps):
             torch.cuda.synchronize()
-        except gg.GGError:
-            return math.inf
-        ts.append(time.perf_counter() - t)
-    return sorted(ts)[len(ts) // 2]
+            t = time.perf_counter()
+            try:
+                if algo == "cc":
+                    g.cc(opts=o, out=out)
+                else:
+                    getattr(g, algo)(src, opts=o, out=out)
+                torch.cuda.synchronize()
+            except gg.GGError:
+                return math.inf
+            ts.append(time.perf_counter() - t)
+        total += sorted(ts)[len(ts) // 2]
+    return total
 
 
-def main(argv=None):
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--out", default=gg.TUNE_TABLE)
-    ap.add_argument("--reps", type=int, default=3)
-    ap.add_argument("--seed", type=int, default=gen.MASTER_SEED)
-    args = ap.parse_args(argv)
+# Two variants whose scores differ by less than this factor are a tie
+# (repeated calibration runs differ by a few per cent); a tie goes to the
+# variant with fewer schedule knobs.
+TIE = 1.03
+
+
+def knobs(v):
+    """Schedule knobs a variant sets: near-far buckets, local expansion."""
+    return int(v[1] == gg.NEARFAR) + int(v[4] > 0)
+
+
+def choose(results):
+    """Table entries from (algo, class, {variant: seconds}) measurements: per
+    (algo, class) the lowest geometric mean of time / best-of-graph over the
+    graphs of the class; ties (within TIE) go to fewer knobs."""
+    groups = {}
+    for algo, cls, times in results:
+        best = min(times.values())
+        for v, t in times.items():
+            r = t / best if math.isfinite(t) else 1e6
+            groups.setdefault((algo, tuple(cls)), {}).setdefault(v, []).append(math.log(r))
+    entries, detail = [], []
+    for (algo, cls), per_v in sorted(groups.items()):
+        score = {v: sum(x) / len(x) for v, x in per_v.items()}
+        top = min(score.values())
+        near = [v for v in score if score[v] <= top + math.log(TIE)]
+        v = min(near, key=lambda u: (knobs(u), score[u]))
+        entries.append({"algo": ALGOS.index(algo), "size_class": cls[0], "skew_class": cls[1],
+                        "depth_class": cls[2], "mode": v[0], "sched": v[1], "mapping": v[2],
+                        "delta_mult": v[3], "hops": v[4]})
+        detail.append({"algo": algo, "class": list(cls),
+                       "relative_to_best": {"/".join(map(str, k)): round(math.exp(x), 3)
+                                            for k, x in score.items()}})
+    return entries, detail
+
+
+def measure(args):
     import torch
     gg.tune_set([])  # measure with the built-in rules in place
     results = []  # (algo, class, {variant: time})
@@ -83,40 +126,47 @@ def main(argv=None):
         hg = make(kind, p, args.seed)
         g = gg.Graph.from_host(hg, symmetrize=True)
         cls = g.probe()
-        src = int(gen.pick_sources(hg, 1, stream=CALIB_STREAM)[0])
+        # traversal times vary with the source: every variant runs from the
+        # same few
+        srcs = [int(x) for x in gen.pick_sources(hg, args.sources, stream=CALIB_STREAM)]
         out = torch.empty(hg.n, dtype=torch.int32, device="cuda")
         avg_w = float(hg.w.mean()) if hg.w is not None and hg.m else 1.0
         for algo in ALGOS:
             times = {}
             extra = NEARFAR if algo == "sssp" else DIROPT if algo == "bfs" else CC_DIROPT
-            for v in VARIANTS + extra:
-                times[v] = time_variant(g, algo, src, v, args.reps, out, avg_w)
+            for v in VARIANTS + LOCAL + extra:
+                times[v] = time_variant(g, algo, srcs, v, args.reps, out, avg_w)
             best = min(times.values())
             print(f"[tune] {hg.name:8s} class={cls} {algo:4s} best "
                   f"{min(times, key=times.get)} {best * 1e3:.3f} ms", file=sys.stderr, flush=True)
             results.append((algo, cls, times))
         g.free()
         del out
-    # per (algo, class): geometric mean of time / best-of-graph over the graphs
-    groups = {}
-    for algo, cls, times in results:
-        best = min(times.values())
-        for v, t in times.items():
-            r = t / best if math.isfinite(t) else 1e6
-            groups.setdefault((algo, cls), {}).setdefault(v, []).append(math.log(r))
-    entries, detail = [], []
-    for (algo, cls), per_v in sorted(groups.items()):
-        score = {v: sum(x) / len(x) for v, x in per_v.items()}
-        v = min(score, key=score.get)
-        entries.append({"algo": ALGOS.index(algo), "size_class": cls[0], "skew_class": cls[1],
-                        "depth_class": cls[2], "mode": v[0], "sched": v[1], "mapping": v[2],
-                        "delta_mult": v[3]})
-        detail.append({"algo": algo, "class": list(cls),
-                       "relative_to_best": {f"{m}/{s}/{mp}/{dm}": round(math.exp(x), 3)
-                                            for (m, s, mp, dm), x in score.items()}})
-    raw = [{"algo": a, "class": list(c), "ms": {f"{m}/{s}/{mp}/{dm}": (round(t * 1e3, 4)
-                                                                    if math.isfinite(t) else None)
-                                                 for (m, s, mp, dm), t in ts.items()}}
+    return results
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=gg.TUNE_TABLE)
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--sources", type=int, default=3)
+    ap.add_argument("--seed", type=int, default=gen.MASTER_SEED)
+    ap.add_argument("--from-measurements", metavar="TABLE_JSON",
+                    help="re-derive the entries from the measurements of an earlier table "
+                         "(no GPU needed)")
+    args = ap.parse_args(argv)
+    if args.from_measurements:
+        with open(args.from_measurements) as f:
+            raw = json.load(f)["measurements"]
+        results = [(r["algo"], tuple(r["class"]),
+                    {tuple(int(x) for x in k.split("/")): (t * 1e-3 if t is not None else math.inf)
+                     for k, t in r["ms"].items()}) for r in raw]
+    else:
+        results = measure(args)
+    entries, detail = choose(results)
+    raw = [{"algo": a, "class": list(c),
+            "ms": {"/".join(map(str, k)): (round(t * 1e3, 4) if math.isfinite(t) else None)
+                   for k, t in ts.items()}}
            for a, c, ts in results]
     with open(args.out, "w") as f:
         json.dump({"entries": entries, "scores": detail, "measurements": raw,

@@ -251,6 +251,47 @@ def test_nearfar_sssp(gg):
             g.free()
 
 
+def test_local_expansion(gg):
+    """Worklist rounds whose wavefronts serve their own updates again in the
+    same round (opts.hops) give the same distances, levels and labels; on a
+    path they cover many levels per round."""
+    rng = np.random.default_rng(1665)
+    graphs = [read_golden(f)[:2] for f in golden_files()]
+    for i in range(6):
+        n = int(rng.integers(1, 400))
+        graphs.append((random_graph(rng, n, int(rng.integers(0, 5 * n + 1)), 1, 9,
+                                    name=f"loc{i}"), int(rng.integers(0, n))))
+    hub = gen.workload("rmat14")  # heavy rows: the chunk kernel under local expansion
+    graphs += [(gen.workload("er16k"), 0), (gen.workload("grid96"), 0),
+               (hub, int(gen.pick_sources(hub, 1, stream=gen.STREAM["sources"])[0])),
+               (path_graph(700, np.arange(1, 700) % 5 + 1), 0),
+               (star(200, [[5, 3, 9]] * 200), 0)]
+    for hg, s in graphs:
+        want = expected(hg, s)
+        g = gg.Graph.from_host(hg, symmetrize=True)
+        try:
+            for hops in (1, 3, 64):
+                for algo, sched, delta in (("sssp", gg.ASYNC, 0), ("sssp", gg.NEARFAR, 0),
+                                           ("sssp", gg.NEARFAR, 5), ("bfs", gg.ASYNC, 0),
+                                           ("cc", gg.ASYNC, 0)):
+                    say(f"[gpu] local {hg.name} n={hg.n} {algo} sched={sched} delta={delta} "
+                        f"hops={hops}")
+                    o = gg.make_opts(gg.VERTEX, sched, gg.MAP_BALANCED, delta=delta, hops=hops)
+                    got = (g.cc(opts=o) if algo == "cc" else getattr(g, algo)(s, opts=o))
+                    st = g.stats()
+                    assert st["rc"] == 0, st
+                    np.testing.assert_array_equal(got.cpu().numpy()[: hg.n], want[algo],
+                                                  err_msg=f"{hg.name} {algo} hops={hops}")
+                    if hg.name == "path" and algo == "bfs":
+                        # one wavefront walks hops + 1 levels per round
+                        assert st["iterations"] <= 700 // (hops + 1) + 2, st
+            for bad in (-1, 65):
+                with pytest.raises(gg.GGError):
+                    g.bfs(s, opts=gg.make_opts(gg.VERTEX, gg.ASYNC, gg.MAP_BALANCED, hops=bad))
+        finally:
+            g.free()
+
+
 def test_diropt_bfs(gg):
     """Direction-optimizing BFS (push small frontiers, pull large ones) gives
     the same levels; both directions run on these graphs."""
