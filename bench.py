@@ -43,10 +43,13 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 INF = 2**31 - 1
 ALGOS = ("sssp", "bfs", "cc")
-# (mode, schedule, mapping, passes of local expansion)
-VARIANTS = {"vertex-sync": (0, 0, 3, 0), "vertex-async": (0, 1, 3, 0), "edge-sync": (1, 0, 0, 0),
-            "edge-async": (1, 1, 0, 0), "nearfar": (0, 3, 3, 0), "diropt": (0, 4, 3, 0),
-            "vertex-async-h8": (0, 1, 3, 8), "nearfar-h32": (0, 3, 3, 32)}
+# (mode, schedule, mapping, passes of local expansion, near-far far_degree,
+# near-far bucket width in quarters of the mean weight; 0 = the tuned width)
+VARIANTS = {"vertex-sync": (0, 0, 3, 0, 0, 0), "vertex-async": (0, 1, 3, 0, 0, 0),
+            "edge-sync": (1, 0, 0, 0, 0, 0), "edge-async": (1, 1, 0, 0, 0, 0),
+            "nearfar": (0, 3, 3, 0, 0, 0), "diropt": (0, 4, 3, 0, 0, 0),
+            "vertex-async-h8": (0, 1, 3, 8, 0, 0), "nearfar-h32": (0, 3, 3, 32, 0, 0),
+            "nearfar-long64-h8": (0, 3, 3, 8, 64, 1)}
 
 
 def log(*a):
@@ -305,6 +308,8 @@ def main():
     mname = ["vertex", "edge"][c.mode] + "-" + ["sync", "async", "auto", "nearfar", "diropt"][c.sched]
     if c.hops:
         mname += f"-h{c.hops}"
+    if c.sched == 3 and c.far_degree:
+        mname += f"-long{c.far_degree}"
     achieved = db / (dms * 1e-3) / 1e9
     sym = kernel_symbol(da, dk, c.mode, c.sched, c.mapping, c.hops)
     traffic = measured_traffic(sym, args.workload)
@@ -322,17 +327,19 @@ def main():
 
     # ------------------------------------------------ per-variant table --
     variants = {}
+    avg_w = float(hg.w.mean()) if hg.w is not None and hg.m else 1.0
     if not args.no_variants:
         s = sources[0]
         for a in ALGOS:
-            for vname, (mode, sched, mp, hops) in VARIANTS.items():
+            for vname, (mode, sched, mp, hops, far, dq) in VARIANTS.items():
                 if (sched == 3 and a != "sssp") or (sched == 4 and a == "sssp"):
                     continue  # near-far is an SSSP schedule, the per-round choice BFS/CC
                 if hops and a == "cc":
                     continue  # label propagation gains nothing from local expansion
                 if sched == 4 and a == "cc":
                     mode = 1  # CC's per-round choice starts from edge sweeps
-                o = gg.make_opts(mode, sched, mp, hops=hops)
+                o = gg.make_opts(mode, sched, mp, hops=hops, far_degree=far,
+                                 delta=max(1, int(dq * avg_w / 4)) if dq else 0)
                 times = []
                 for _ in range(max(args.reps, 5 if hg.m >= 1 << 20 else 100)):
                     torch.cuda.synchronize()
@@ -395,7 +402,9 @@ def main():
                    "variant": {a: {"mode": ["vertex", "edge"][chosen[a].mode],
                                    "sched": ["sync", "async", "auto", "nearfar", "diropt"][chosen[a].sched],
                                    "mapping": chosen[a].mapping,
-                                   "hops": chosen[a].hops} for a in ALGOS},
+                                   "hops": chosen[a].hops,
+                                   "delta": chosen[a].delta if chosen[a].sched == 3 else 0,
+                                   "far_degree": chosen[a].far_degree} for a in ALGOS},
                    "sources": sources, "upload_s": round(upload_s, 2),
                    "graph_class": list(gclass),
                    "verified_vs_oracle": verified},

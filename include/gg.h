@@ -134,7 +134,13 @@ typedef struct {
                               frontier.  Fewer rounds on high-diameter graphs; the result
                               is the same.  Ignored by other variants; with
                               GG_SCHED_AUTO the tuned choice sets it. */
-    int32_t reserved[2];
+    int32_t far_degree;    /* GG_NEARFAR: only frontier vertices with more than far_degree
+                              out-edges wait for the bound; shorter rows are served at once.
+                              0 = every vertex waits (plain near-far).  On skewed graphs the
+                              long rows are where a premature expansion costs most, so
+                              deferring only them saves most of the repeated work in fewer
+                              rounds.  >= 0; with GG_SCHED_AUTO the tuned choice sets it. */
+    int32_t reserved[1];
 } gg_opts;
 
 /* gg_opts.flags */
@@ -282,9 +288,12 @@ int gg_resolve(gg_graph g, int32_t algo, const gg_opts* in, gg_opts* out);
 typedef struct {
     int32_t algo, size_class, skew_class, depth_class; /* depth -1 = any */
     int32_t mode, sched, mapping;
-    int32_t delta_mult; /* GG_NEARFAR: bucket width in mean edge weights (0 = 4) */
+    int32_t delta_q;    /* GG_NEARFAR: bucket width in quarters of the mean edge weight,
+                           0..2^22 (0 = 16, four mean weights) */
     int32_t hops;       /* gg_opts.hops of the variant, 0..64; nonzero only for vertex-based
                            GG_ASYNC or GG_NEARFAR with the BALANCED (or AUTO) mapping */
+    int32_t far_degree; /* gg_opts.far_degree of the variant, >= 0; nonzero only for
+                           GG_NEARFAR */
 } gg_tune_entry;
 
 /* Replace the process-wide tuning table (count 0 clears it).  The entries
@@ -301,10 +310,10 @@ int gg_class_of(int64_t m, int32_t n, int32_t max_out_degree, int32_t levels,
                 int32_t* size_class, int32_t* skew_class, int32_t* depth_class);
 
 /* Variant the table (else the built-in rules) picks for an algorithm and a
- * class, as gg_resolve would.  Outputs may not be NULL, except `hops`. */
+ * class, as gg_resolve would: `out` receives the query's algorithm and class
+ * and the chosen variant fields (mapping AUTO reported as BALANCED). */
 int gg_tune_lookup(int32_t algo, int32_t size_class, int32_t skew_class, int32_t depth_class,
-                   int32_t* mode, int32_t* sched, int32_t* mapping, int32_t* delta_mult,
-                   int32_t* hops);
+                   gg_tune_entry* out);
 
 /* Measure the graph's depth class (one BFS on `stream`, waited for) and keep
  * it on the handle; later AUTO resolutions use it. */
@@ -321,7 +330,9 @@ int gg_graph_class(gg_graph g, int32_t* size_class, int32_t* skew_class, int32_t
  * per-instance vertex offsets, so every instance is a separate component
  * and one multi-source traversal of the group computes all of them exactly
  * as separate calls would (bit-identical).  Each group runs in the variant
- * the tuner picks for the group's graph, on a stream of its own; after the
+ * the tuner picks for the group's graph (a near-far pick runs as the plain
+ * worklist: the buckets pay off on large single-source traversals, not on a
+ * group of small ones), on a stream of its own; after the
  * first run the group's launch sequence is captured in a HIP graph and later
  * runs replay it (rounds past the end return at once; a replay that stops
  * short is continued with eager launches).  Not thread-safe per batch. */

@@ -229,24 +229,29 @@ void resolve(gg_graph g, int algo, const gg_opts* in, gg_opts* out) {
     const bool auto_sched = o.sched != GG_SYNC && o.sched != GG_ASYNC && o.sched != GG_NEARFAR &&
                             o.sched != GG_DIROPT;
     const bool auto_map = o.mapping < GG_MAP_THREAD || o.mapping > GG_MAP_BALANCED;
-    int32_t sc = 0, kc = 0, dc = -1, tm = GG_VERTEX, ts = GG_ASYNC, tp = GG_MAP_BALANCED, td = 0;
-    int32_t th = 0;
+    int32_t sc = 0, kc = 0, dc = -1;
     gg_class_of(g->m, g->n, g->max_deg, g->levels, &sc, &kc, &dc);
-    gg_tune_lookup(algo, sc, kc, dc, &tm, &ts, &tp, &td, &th);
+    gg_tune_entry t{};
+    t.mode = GG_VERTEX;
+    t.sched = GG_ASYNC;
+    t.mapping = GG_MAP_BALANCED;
+    gg_tune_lookup(algo, sc, kc, dc, &t);
+    const int32_t tm = t.mode, ts = t.sched, tp = t.mapping, tq = t.delta_q;
     if (auto_mode) o.mode = tm;
-    // the tuned schedule comes with its local expansion
+    // the tuned schedule comes with its local expansion and deferral
     if (auto_sched) {
         o.sched = ts;
-        o.hops = th;
+        o.hops = t.hops;
+        o.far_degree = t.far_degree;
     }
     // an explicit per-round schedule fixes the mode it runs in
     if (!auto_sched && o.sched == GG_DIROPT && auto_mode)
         o.mode = algo == GG_ALGO_CC ? GG_EDGE : GG_VERTEX;
     if (auto_map) o.mapping = tp;
     // bucket width of the near-far schedule: explicit, else the table's
-    // multiple of the mean weight, else 4 mean weights
+    // quarters of the mean weight, else 4 mean weights
     if (o.sched == GG_NEARFAR && o.delta <= 0)
-        o.delta = std::max(1, (int)((td > 0 ? td : 4) * g->avg_w));
+        o.delta = std::max(1, (int)((tq > 0 ? tq : 16) * g->avg_w / 4));
     // a choice taken from the table must be one this graph can run
     if (auto_sched && o.sched == GG_DIROPT && !diropt_ok(g, algo, o.mode)) {
         o.sched = algo == GG_ALGO_CC ? GG_SYNC : GG_ASYNC;
@@ -292,7 +297,7 @@ int plan_make(gg_graph g, gg_ws ws, int algo, int source, const int* sources_dev
     const bool nearfar = o.sched == GG_NEARFAR;
     if (nearfar && (algo != GG_ALGO_SSSP || o.mode != GG_VERTEX || o.mapping != GG_MAP_BALANCED))
         return GG_ENOTSUP;
-    if (o.delta < 0 || o.hops < 0 || o.hops > 64) return GG_EINVAL;
+    if (o.delta < 0 || o.hops < 0 || o.hops > 64 || o.far_degree < 0) return GG_EINVAL;
     const bool diropt = o.sched == GG_DIROPT;
     if (diropt && !diropt_ok(g, algo, o.mode)) return GG_ENOTSUP;
     const Dev& dv = device();
@@ -319,6 +324,7 @@ int plan_make(gg_graph g, gg_ws ws, int algo, int source, const int* sources_dev
     R.delta = nearfar ? std::max(1, o.delta) : 0;
     R.fedges = p.cc && diropt;
     R.hops = p.async && !p.edge && !diropt && o.mapping == GG_MAP_BALANCED ? o.hops : 0;
+    R.far_degree = nearfar ? o.far_degree : 0;
 
     const int wpb = kBlock / 64;
     const long long n = g->n;

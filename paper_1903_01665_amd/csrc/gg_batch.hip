@@ -193,6 +193,19 @@ int gg_batch_create(const gg_instance* inst, int32_t count, uint32_t flags, void
             hipHostMalloc(reinterpret_cast<void**>(&G.h_ctl), 2 * sizeof(int)) != hipSuccess)
             return bail(GG_EHIP);
         gg_resolve(G.g, G.algo, nullptr, &G.opts);
+        // The table's choice is measured on single-source traversals.  A
+        // group is one traversal from hundreds of sources over as many small
+        // components: near-far rounds then follow the component that needs
+        // the most buckets, while the repeated hub expansions the buckets
+        // save belong to large skewed graphs (measured on 512 R-MAT
+        // instances of scales 10-18: near-far with long-row deferral 18.4 ms
+        // per run, the plain worklist 14.0 ms).  Groups run the worklist.
+        if (G.opts.sched == GG_NEARFAR) {
+            G.opts.sched = GG_ASYNC;
+            G.opts.delta = 0;
+            G.opts.far_degree = 0;
+            G.opts.hops = 0;
+        }
     }
     b->total_n = out_off;
     *out = b;

@@ -109,6 +109,7 @@ struct Round {
     int fedges;  // CC per-round dense/sparse choice: push counts are the row lengths
                  // (both-directions CSR) of the pushed vertices, and edge sweeps push
     int hops;    // worklist rounds (balanced mapping): passes of local expansion (0 = off)
+    int far_degree; // near-far: only rows longer than this wait for the bound (0 = all)
 };
 
 // Launch entry points (gg_kernels.hip).  Each returns the hipError_t of the

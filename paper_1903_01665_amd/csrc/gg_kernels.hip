@@ -844,14 +844,15 @@ __device__ __forceinline__ void serve_list(const Round& R, const int* row, const
     int rb = 0, re = 0, sv = 0;
     if (on) {
         tail_value<A, true>(R, u, sv, acc);
-        if (nf && sv >= bound) {
-            // a far vertex waits on the frontier for a later bound
+        rb = row[u];
+        re = row[u + 1];
+        if (nf && sv >= bound && (R.far_degree == 0 || re - rb > R.far_degree)) {
+            // a far vertex waits on the frontier for a later bound (with
+            // far_degree > 0 only its long rows wait; short ones go now)
             push(R, nxt, u);
             acc.u++;
             on = false;
         } else {
-            rb = row[u];
-            re = row[u + 1];
             acc.v++;
         }
     }
@@ -1019,13 +1020,13 @@ __device__ __forceinline__ void serve_local(const Round& R, const int* row, cons
     if (on) {
         if (A == BFS) sv = R.val[u];
         else tail_value<A, true>(R, u, sv, acc);
-        if (nf && sv >= bound) {
+        rb = row[u];
+        re = row[u + 1];
+        if (nf && sv >= bound && (R.far_degree == 0 || re - rb > R.far_degree)) {
             push(R, nxt, u);
             acc.u++;
             on = false;
         } else {
-            rb = row[u];
-            re = row[u + 1];
             acc.v++;
         }
     }

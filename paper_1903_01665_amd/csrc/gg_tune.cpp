@@ -21,8 +21,9 @@ bool valid(const gg_tune_entry& e) {
             (e.sched == GG_NEARFAR && e.algo == GG_ALGO_SSSP && e.mode == GG_VERTEX) ||
             (e.sched == GG_DIROPT && e.algo == GG_ALGO_BFS && e.mode == GG_VERTEX) ||
             (e.sched == GG_DIROPT && e.algo == GG_ALGO_CC && e.mode == GG_EDGE)) &&
-           e.mapping >= GG_MAP_AUTO && e.mapping <= GG_MAP_BALANCED && e.delta_mult >= 0 &&
-           e.delta_mult <= 1 << 20 && e.hops >= 0 && e.hops <= 64 &&
+           e.mapping >= GG_MAP_AUTO && e.mapping <= GG_MAP_BALANCED && e.delta_q >= 0 &&
+           e.delta_q <= 1 << 22 && e.hops >= 0 && e.hops <= 64 && e.far_degree >= 0 &&
+           (e.far_degree == 0 || e.sched == GG_NEARFAR) &&
            (e.hops == 0 || (e.mode == GG_VERTEX && (e.sched == GG_ASYNC || e.sched == GG_NEARFAR) &&
                             (e.mapping == GG_MAP_AUTO || e.mapping == GG_MAP_BALANCED)));
 }
@@ -31,20 +32,20 @@ bool valid(const gg_tune_entry& e) {
 // synthetic workloads (uniform, R-MAT, grid): asynchronous vertex-based
 // rounds for SSSP everywhere; BFS synchronous on shallow graphs and
 // asynchronous on deep ones; CC by edge sweeps with the shortcut.
-void builtin(int algo, int depth, int32_t* mode, int32_t* sched, int32_t* mapping,
-             int32_t* delta_mult, int32_t* hops) {
-    *mapping = GG_MAP_BALANCED;
-    *delta_mult = 0;
-    *hops = 0;
+void builtin(int algo, int depth, gg_tune_entry* e) {
+    e->mapping = GG_MAP_BALANCED;
+    e->delta_q = 0;
+    e->hops = 0;
+    e->far_degree = 0;
     if (algo == GG_ALGO_SSSP) {
-        *mode = GG_VERTEX;
-        *sched = GG_ASYNC;
+        e->mode = GG_VERTEX;
+        e->sched = GG_ASYNC;
     } else if (algo == GG_ALGO_BFS) {
-        *mode = GG_VERTEX;
-        *sched = depth >= 1 || depth < 0 ? GG_ASYNC : GG_SYNC;
+        e->mode = GG_VERTEX;
+        e->sched = depth >= 1 || depth < 0 ? GG_ASYNC : GG_SYNC;
     } else {
-        *mode = GG_EDGE;
-        *sched = GG_SYNC;
+        e->mode = GG_EDGE;
+        e->sched = GG_SYNC;
     }
 }
 
@@ -83,10 +84,8 @@ int gg_tune_get(gg_tune_entry* out, int32_t cap) {
 }
 
 int gg_tune_lookup(int32_t algo, int32_t size_class, int32_t skew_class, int32_t depth_class,
-                   int32_t* mode, int32_t* sched, int32_t* mapping, int32_t* delta_mult,
-                   int32_t* hops) {
-    if (algo < 0 || algo > 2 || !mode || !sched || !mapping || !delta_mult) return GG_EINVAL;
-    int32_t h = 0;
+                   gg_tune_entry* out) {
+    if (algo < 0 || algo > 2 || !out) return GG_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
     int best = -1, best_score = 1 << 30;
     for (int i = 0; i < (int)g_table.size(); ++i) {
@@ -100,16 +99,18 @@ int gg_tune_lookup(int32_t algo, int32_t size_class, int32_t skew_class, int32_t
             best = i;
         }
     }
+    gg_tune_entry r{};
     if (best < 0) {
-        builtin(algo, depth_class, mode, sched, mapping, delta_mult, &h);
+        builtin(algo, depth_class, &r);
     } else {
-        *mode = g_table[best].mode;
-        *sched = g_table[best].sched;
-        *mapping = g_table[best].mapping == GG_MAP_AUTO ? GG_MAP_BALANCED : g_table[best].mapping;
-        *delta_mult = g_table[best].delta_mult;
-        h = g_table[best].hops;
+        r = g_table[best];
+        if (r.mapping == GG_MAP_AUTO) r.mapping = GG_MAP_BALANCED;
     }
-    if (hops) *hops = h;
+    r.algo = algo;
+    r.size_class = size_class;
+    r.skew_class = skew_class;
+    r.depth_class = depth_class;
+    *out = r;
     return GG_OK;
 }
 

@@ -55,7 +55,8 @@ class Opts(ctypes.Structure):
                 ("block_threads", ctypes.c_int32), ("max_blocks", ctypes.c_int32),
                 ("heavy_threshold", ctypes.c_int32), ("time_limit_ms", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("delta", ctypes.c_int32),
-                ("hops", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("hops", ctypes.c_int32), ("far_degree", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 1)]
 
 
 class Stats(ctypes.Structure):
@@ -74,7 +75,8 @@ class TuneEntry(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("size_class", ctypes.c_int32),
                 ("skew_class", ctypes.c_int32), ("depth_class", ctypes.c_int32),
                 ("mode", ctypes.c_int32), ("sched", ctypes.c_int32), ("mapping", ctypes.c_int32),
-                ("delta_mult", ctypes.c_int32), ("hops", ctypes.c_int32)]
+                ("delta_q", ctypes.c_int32), ("hops", ctypes.c_int32),
+                ("far_degree", ctypes.c_int32)]
 
 
 class Instance(ctypes.Structure):
@@ -116,6 +118,12 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    # torch first: its wheel carries its own HIP runtime, which its libraries
+    # ask for by a name that does not match the soname libgg.so asks for.
+    # Loaded in this order there is one runtime in the process (libgg.so's
+    # request matches the loaded soname); the other order loads two, and
+    # torch's streams and device memory are then foreign to libgg.so.
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     i32, i64, u32, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p
     P = ctypes.POINTER
@@ -138,7 +146,7 @@ def lib():
     L.gg_tune_set.argtypes = [P(TuneEntry), i32]
     L.gg_tune_get.argtypes = [P(TuneEntry), i32]
     L.gg_class_of.argtypes = [i64, i32, i32, i32, P(i32), P(i32), P(i32)]
-    L.gg_tune_lookup.argtypes = [i32, i32, i32, i32, P(i32), P(i32), P(i32), P(i32), P(i32)]
+    L.gg_tune_lookup.argtypes = [i32, i32, i32, i32, P(TuneEntry)]
     L.gg_graph_probe.argtypes = [vp, vp]
     L.gg_graph_class.argtypes = [vp, P(i32), P(i32), P(i32)]
     L.gg_batch_create.argtypes = [P(Instance), i32, u32, vp, P(vp)]
@@ -174,14 +182,15 @@ def lib():
 # ------------------------------------------------------------- tuning ------
 def tune_set(entries):
     """Install a tuning table: a list of dicts with algo, size_class,
-    skew_class, depth_class, mode, sched, mapping (and optionally delta_mult,
-    hops)."""
+    skew_class, depth_class, mode, sched, mapping (and optionally delta_q,
+    hops, far_degree)."""
     arr = (TuneEntry * max(1, len(entries)))()
     for i, e in enumerate(entries):
         for k in ("algo", "size_class", "skew_class", "depth_class", "mode", "sched", "mapping"):
             setattr(arr[i], k, int(e[k]))
-        arr[i].delta_mult = int(e.get("delta_mult", 0))
+        arr[i].delta_q = int(e.get("delta_q", 0))
         arr[i].hops = int(e.get("hops", 0))
+        arr[i].far_degree = int(e.get("far_degree", 0))
     _check(lib().gg_tune_set(arr, len(entries)), "gg_tune_set")
 
 
@@ -205,15 +214,16 @@ def class_of(m, n, max_out_degree, levels=-1):
     return a.value, b.value, c.value
 
 
-def tune_lookup(algo, size_class, skew_class, depth_class, with_delta=False):
-    """(mode, sched, mapping), or with_delta (mode, sched, mapping,
-    delta_mult, hops)."""
-    a, b, c, d, h = (ctypes.c_int32() for _ in range(5))
-    _check(lib().gg_tune_lookup(algo, size_class, skew_class, depth_class, ctypes.byref(a),
-                                ctypes.byref(b), ctypes.byref(c), ctypes.byref(d),
-                                ctypes.byref(h)), "gg_tune_lookup")
-    return ((a.value, b.value, c.value, d.value, h.value) if with_delta
-            else (a.value, b.value, c.value))
+def tune_lookup(algo, size_class, skew_class, depth_class, full=False):
+    """(mode, sched, mapping), or with full=True the whole chosen entry as a
+    dict (mode, sched, mapping, delta_q, hops, far_degree)."""
+    t = TuneEntry()
+    _check(lib().gg_tune_lookup(algo, size_class, skew_class, depth_class, ctypes.byref(t)),
+           "gg_tune_lookup")
+    if full:
+        return {k: getattr(t, k) for k in ("mode", "sched", "mapping", "delta_q", "hops",
+                                           "far_degree")}
+    return (t.mode, t.sched, t.mapping)
 
 
 def _check(rc, what):
@@ -234,11 +244,11 @@ def _arr(a):
 
 
 def make_opts(mode=MODE_AUTO, sched=SCHED_AUTO, mapping=MAP_AUTO, max_blocks=0, flags=0,
-              time_limit_ms=0, delta=0, hops=0) -> Opts:
+              time_limit_ms=0, delta=0, hops=0, far_degree=0) -> Opts:
     o = Opts()
     o.mode, o.sched, o.mapping = mode, sched, mapping
     o.max_blocks, o.flags, o.time_limit_ms, o.delta = max_blocks, flags, time_limit_ms, delta
-    o.hops = hops
+    o.hops, o.far_degree = hops, far_degree
     return o
 
 

@@ -25,18 +25,20 @@ import time
 from . import gen, gg
 
 ALGOS = ("sssp", "bfs", "cc")
-# (mode, schedule, mapping, near-far bucket width in mean weights, passes of
-# local expansion)
-VARIANTS = [(gg.VERTEX, gg.SYNC, gg.MAP_THREAD, 0, 0), (gg.VERTEX, gg.SYNC, gg.MAP_WAVE, 0, 0),
-            (gg.VERTEX, gg.SYNC, gg.MAP_BALANCED, 0, 0), (gg.VERTEX, gg.ASYNC, gg.MAP_THREAD, 0, 0),
-            (gg.VERTEX, gg.ASYNC, gg.MAP_WAVE, 0, 0), (gg.VERTEX, gg.ASYNC, gg.MAP_BALANCED, 0, 0),
-            (gg.EDGE, gg.SYNC, gg.MAP_AUTO, 0, 0), (gg.EDGE, gg.ASYNC, gg.MAP_AUTO, 0, 0)]
-LOCAL = [(gg.VERTEX, gg.ASYNC, gg.MAP_BALANCED, 0, h) for h in (2, 8)]
-NEARFAR = ([(gg.VERTEX, gg.NEARFAR, gg.MAP_BALANCED, dm, 0) for dm in (1, 2, 4, 8, 16, 64)] +
-           [(gg.VERTEX, gg.NEARFAR, gg.MAP_BALANCED, dm, h) for dm in (1, 2, 4, 8, 16)
-            for h in (2, 8, 32)])
-DIROPT = [(gg.VERTEX, gg.DIROPT, gg.MAP_BALANCED, 0, 0)]
-CC_DIROPT = [(gg.EDGE, gg.DIROPT, gg.MAP_BALANCED, 0, 0)]
+# (mode, schedule, mapping, near-far bucket width in quarters of the mean
+# weight, passes of local expansion, near-far far_degree)
+V, NF, BAL = gg.VERTEX, gg.NEARFAR, gg.MAP_BALANCED
+VARIANTS = [(V, gg.SYNC, gg.MAP_THREAD, 0, 0, 0), (V, gg.SYNC, gg.MAP_WAVE, 0, 0, 0),
+            (V, gg.SYNC, BAL, 0, 0, 0), (V, gg.ASYNC, gg.MAP_THREAD, 0, 0, 0),
+            (V, gg.ASYNC, gg.MAP_WAVE, 0, 0, 0), (V, gg.ASYNC, BAL, 0, 0, 0),
+            (gg.EDGE, gg.SYNC, gg.MAP_AUTO, 0, 0, 0), (gg.EDGE, gg.ASYNC, gg.MAP_AUTO, 0, 0, 0)]
+LOCAL = [(V, gg.ASYNC, BAL, 0, h, 0) for h in (2, 8)]
+NEARFAR = ([(V, NF, BAL, dq, 0, 0) for dq in (4, 8, 16, 32, 64, 256)] +
+           [(V, NF, BAL, dq, h, 0) for dq in (4, 8, 16, 32, 64) for h in (2, 8, 32)] +
+           # narrow buckets that hold back only long rows (skewed graphs)
+           [(V, NF, BAL, dq, h, 64) for dq in (1, 2, 4) for h in (0, 8)])
+DIROPT = [(V, gg.DIROPT, BAL, 0, 0, 0)]
+CC_DIROPT = [(gg.EDGE, gg.DIROPT, BAL, 0, 0, 0)]
 
 # calibration graphs: the size classes of the workloads, from a seed stream of
 # their own so that no benchmark graph is itself in the set
@@ -60,9 +62,10 @@ def time_variant(g, algo, srcs, v, reps, out, avg_w):
     """Sum over the sources of the median time of `reps` runs (CC: one
     source-free run set)."""
     import torch
-    mode, sched, mapping, dm, hops = v
+    mode, sched, mapping, dq, hops, far = v
     o = gg.make_opts(mode, sched, mapping, time_limit_ms=4000,
-                     delta=max(1, int(dm * avg_w)) if sched == gg.NEARFAR else 0, hops=hops)
+                     delta=max(1, int(dq * avg_w / 4)) if sched == gg.NEARFAR else 0, hops=hops,
+                     far_degree=far)
     total = 0.0
     for src in srcs[:1] if algo == "cc" else srcs:
         ts = []
@@ -89,8 +92,15 @@ TIE = 1.03
 
 
 def knobs(v):
-    """Schedule knobs a variant sets: near-far buckets, local expansion."""
-    return int(v[1] == gg.NEARFAR) + int(v[4] > 0)
+    """Schedule knobs a variant sets: near-far buckets, local expansion,
+    deferral of long rows only."""
+    return int(v[1] == gg.NEARFAR) + int(v[4] > 0) + int(v[5] > 0)
+
+
+def variant_key(k):
+    """Variant tuple from a measurement key "mode/sched/mapping/delta_q/hops/
+    far_degree"."""
+    return tuple(int(x) for x in k.split("/"))
 
 
 def choose(results):
@@ -111,7 +121,7 @@ def choose(results):
         v = min(near, key=lambda u: (knobs(u), score[u]))
         entries.append({"algo": ALGOS.index(algo), "size_class": cls[0], "skew_class": cls[1],
                         "depth_class": cls[2], "mode": v[0], "sched": v[1], "mapping": v[2],
-                        "delta_mult": v[3], "hops": v[4]})
+                        "delta_q": v[3], "hops": v[4], "far_degree": v[5]})
         detail.append({"algo": algo, "class": list(cls),
                        "relative_to_best": {"/".join(map(str, k)): round(math.exp(x), 3)
                                             for k, x in score.items()}})
@@ -159,7 +169,7 @@ def main(argv=None):
         with open(args.from_measurements) as f:
             raw = json.load(f)["measurements"]
         results = [(r["algo"], tuple(r["class"]),
-                    {tuple(int(x) for x in k.split("/")): (t * 1e-3 if t is not None else math.inf)
+                    {variant_key(k): (t * 1e-3 if t is not None else math.inf)
                      for k, t in r["ms"].items()}) for r in raw]
     else:
         results = measure(args)

@@ -85,3 +85,17 @@ def test_null_handles_are_rejected():
     assert L.gg_sssp(None, 0, 0, 0, None, None) == -1
     assert L.gg_cc(None, 0, 0, None, None) == -1
     assert L.gg_last_stats(None, None, None) == -1
+
+
+def test_binding_loads_torch_first():
+    """torch's HIP runtime must be the one in the process before libgg.so is
+    loaded (see gg.lib)."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_1903_01665_amd import gg\n"
+            "assert 'torch' not in sys.modules\n"
+            "gg.lib()\n"
+            "assert 'torch' in sys.modules\n" % ROOT)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stderr[-2000:]

@@ -103,3 +103,40 @@ def test_batch_rejects_bad_instances(gg):
     uw = gen.HostGraph(hg.n, hg.row_ptr, hg.col, None)
     with pytest.raises(gg.GGError):
         gg.Batch([(0, uw, 0)])        # SSSP without weights
+
+
+@pytest.mark.parametrize("flags", [0, 1])
+def test_batch_with_local_expansion(gg, flags):
+    """Groups whose tuned variant expands locally (worklist SSSP and BFS
+    with hops > 0) still give every instance's exact result, in the
+    multi-source traversal of the group, eagerly and replayed; a near-far
+    pick runs as the plain worklist."""
+    import torch
+    saved = gg.tune_get()
+    entries = []
+    for sc in range(0, 16):
+        for kc in range(3):
+            entries.append(dict(algo=0, size_class=sc, skew_class=kc, depth_class=-1, mode=0,
+                                sched=gg.ASYNC if sc % 2 else gg.NEARFAR, mapping=3,
+                                delta_q=8 if sc % 2 == 0 else 0, hops=8,
+                                far_degree=4 if sc % 2 == 0 else 0))
+            entries.append(dict(algo=1, size_class=sc, skew_class=kc, depth_class=-1, mode=0,
+                                sched=gg.ASYNC, mapping=3, delta_q=0, hops=3))
+    gg.tune_set(entries)
+    try:
+        inst = make_instances(40, 77 + flags)
+        want = expected(inst)
+        b = gg.Batch(inst, flags=flags)
+    finally:
+        gg.tune_set(saved)
+    try:
+        info = b.info()
+        out = torch.full((info["total_n"],), -7, dtype=torch.int32, device="cuda")
+        for rep in range(3):
+            say(f"[gpu] batch local flags={flags} rep={rep} groups={info['groups']}")
+            out.fill_(-7)
+            b.run(out)
+            torch.cuda.synchronize()
+            check(b, inst, want, out)
+    finally:
+        b.free()

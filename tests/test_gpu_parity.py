@@ -251,6 +251,41 @@ def test_nearfar_sssp(gg):
             g.free()
 
 
+def test_nearfar_long_rows_only(gg):
+    """Near-far with only rows longer than far_degree held back (short rows
+    served at once), plain and with local expansion: the same distances."""
+    rng = np.random.default_rng(7)
+    graphs = [read_golden(f)[:2] for f in golden_files()]
+    for i in range(5):
+        n = int(rng.integers(1, 300))
+        graphs.append((random_graph(rng, n, int(rng.integers(0, 8 * n + 1)), 1, 50,
+                                    name=f"far{i}"), int(rng.integers(0, n))))
+    hub = gen.workload("rmat14")
+    graphs += [(hub, int(gen.pick_sources(hub, 1, stream=gen.STREAM["sources"])[0])),
+               (gen.workload("er16k"), 0), (path_graph(500, np.arange(1, 500) % 7 + 1), 0),
+               (star(300, [[4, 9, 2]] * 300), 0)]
+    for hg, s in graphs:
+        want = oracle.sssp(hg.n, hg.row_ptr, hg.col, hg.w, s)
+        g = gg.Graph.from_host(hg)
+        try:
+            for far in (1, 4, 64):
+                for delta in (1, 7, 0):
+                    for hops in (0, 3):
+                        say(f"[gpu] nearfar-long {hg.name} n={hg.n} far={far} delta={delta} "
+                            f"hops={hops}")
+                        o = gg.make_opts(gg.VERTEX, gg.NEARFAR, gg.MAP_BALANCED, delta=delta,
+                                         hops=hops, far_degree=far)
+                        got = g.sssp(s, opts=o).cpu().numpy()
+                        assert g.stats()["rc"] == 0
+                        np.testing.assert_array_equal(got, want,
+                                                      err_msg=f"{hg.name} far={far} d={delta}")
+            with pytest.raises(gg.GGError):
+                g.sssp(s, opts=gg.make_opts(gg.VERTEX, gg.NEARFAR, gg.MAP_BALANCED,
+                                            far_degree=-1))
+        finally:
+            g.free()
+
+
 def test_local_expansion(gg):
     """Worklist rounds whose wavefronts serve their own updates again in the
     same round (opts.hops) give the same distances, levels and labels; on a
@@ -486,3 +521,33 @@ def test_null_options_mean_auto(gg):
             srv.free()
     finally:
         g.free()
+
+
+def test_binding_loaded_before_torch(gg):
+    """A process that loads the library before it imports torch gets one HIP
+    runtime (torch's wheel carries its own): streams and device memory from
+    torch work in libgg.so calls, here a traversal and a small batch."""
+    import os
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "from paper_1903_01665_amd import gg, gen\n"
+        "gg.lib()\n"
+        "import numpy as np, torch, oracle\n"
+        "hg = gen.workload('er300x900')\n"
+        "g = gg.Graph.from_host(hg)\n"
+        "d = g.sssp(0).cpu().numpy()\n"
+        "assert np.array_equal(d, oracle.sssp(hg.n, hg.row_ptr, hg.col, hg.w, 0))\n"
+        "g.free()\n"
+        "b = gg.Batch([(0, hg, 0), (1, hg, 5)])\n"
+        "out = torch.empty(b.info()['total_n'], dtype=torch.int32, device='cuda')\n"
+        "b.run(out); torch.cuda.synchronize()\n"
+        "got = out.cpu().numpy(); off = b.offsets()\n"
+        "assert np.array_equal(got[off[0]:off[0] + hg.n], d)\n"
+        "assert np.array_equal(got[off[1]:off[1] + hg.n], oracle.bfs(hg.n, hg.row_ptr, hg.col, 5))\n"
+        "b.free()\n"
+        "print('one runtime ok', flush=True)\n" % root)
+    say("[gpu] library loaded before torch (subprocess)")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and "one runtime ok" in r.stdout, r.stdout[-2000:] + r.stderr[-2000:]
