@@ -800,20 +800,50 @@ __device__ void cc_first_pass(const Round& R, Acc& acc) {
         }
         __builtin_amdgcn_wave_barrier();
     }
-    for (long long k = gw; k < g.n_shchunks; k += tw) {
-        const int2 c = g.shchunks[k];
-        const int e1 = min(c.y + g.chunk, g.srow[c.x + 1]);
+    // Heavy rows, chunk by chunk.  The loop is pipelined across a
+    // wavefront's chunks: the next chunk's descriptor and row end are
+    // fetched while this chunk's columns load, the column loads of a chunk
+    // are issued together (indices clamped into the chunk, surplus lanes
+    // masked after the load), and the result of a chunk's atomicMin (did it
+    // lower the label: push the row) is read one chunk later, so that the
+    // atomic's round trip overlaps the next chunk's loads.
+    const long long nch = g.n_shchunks;
+    long long k = gw;
+    int2 c = k < nch ? g.shchunks[k] : make_int2(0, 0);
+    int rend = k < nch ? g.srow[c.x + 1] : 0;
+    int prow = -1, pold = 0, px = 0;  // lane 0: the previous chunk's atomic
+    for (; k < nch; k += tw) {
+        const long long kn = k + tw;
+        const int2 cn = kn < nch ? g.shchunks[kn] : c;
+        const int e1 = min(c.y + g.chunk, rend);
         int x = kInf;
-        for (int e = c.y + lane; e < e1; e += 64) x = min(x, g.scol[e]);
+        for (int e0 = c.y; e0 < e1; e0 += 4 * 64) {
+            int v[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[j] = g.scol[min(e0 + j * 64 + lane, e1 - 1)];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (e0 + j * 64 + lane < e1) x = min(x, v[j]);
+        }
+        const int rendn = kn < nch ? g.srow[cn.x + 1] : 0;
 #pragma unroll
         for (int d = 32; d > 0; d >>= 1) x = min(x, __shfl_xor(x, d, 64));
         if (lane == 0) {
-            acc.e += e1 - c.y;
-            if (x < atomicMin(&R.val[c.x], x)) {
+            if (prow >= 0 && px < pold) {
                 acc.u++;
-                sweep_push(R, c.x, acc);
+                sweep_push(R, prow, acc);
             }
+            acc.e += e1 - c.y;
+            pold = atomicMin(&R.val[c.x], x);
+            px = x;
+            prow = c.x;
         }
+        c = cn;
+        rend = rendn;
+    }
+    if (lane == 0 && prow >= 0 && px < pold) {
+        acc.u++;
+        sweep_push(R, prow, acc);
     }
 }
 
@@ -1342,21 +1372,26 @@ __global__ __launch_bounds__(256) void k_heavy(Round R) {
             c = chunks[it];
             on = R.ws.hstamp[c.x] == R.stamp;
         }
+        // each lane fetches its own matched chunk's end now, all in
+        // parallel, instead of one chunk at a time below.  The tail value is
+        // read when the chunk is served: read here it would miss the
+        // decreases that other wavefronts make meanwhile (measured: weaker
+        // relaxations, more rounds).  BFS: the round's level, or under local
+        // expansion (levels differ within a round) the row's own level,
+        // lowered atomically.
+        const bool lvl = A == BFS && R.hops == 0;
+        const int cend = on ? min(c.y + kChunk, row[c.x + 1]) : 0;
         unsigned long long am = __ballot(on);
         while (am) {
             const int o = __ffsll(am) - 1;
             am &= am - 1;
-            const int u = __shfl(c.x, o, 64);
-            const int e0 = __shfl(c.y, o, 64);
-            const int e1 = min(e0 + g.chunk, row[u + 1]);
-            // BFS: the round's level, or under local expansion (levels
-            // differ within a round) the row's own level, lowered atomically
-            if (A == BFS && R.hops > 0)
-                wave_relax_range<A, true, batch_for(A, false), true>(R, col, e0, e1, R.val[u], nxt,
-                                                                     acc, bound);
+            const int e0 = __shfl(c.y, o, 64), e1 = __shfl(cend, o, 64);
+            const int sv = lvl ? R.r : R.val[__shfl(c.x, o, 64)];
+            if (A == BFS && !lvl)
+                wave_relax_range<A, true, batch_for(A, false), true>(R, col, e0, e1, sv, nxt, acc,
+                                                                     bound);
             else
-                wave_relax_range<A, true, batch_for(A, false)>(
-                    R, col, e0, e1, A == BFS ? R.r : R.val[u], nxt, acc, bound);
+                wave_relax_range<A, true, batch_for(A, false)>(R, col, e0, e1, sv, nxt, acc, bound);
         }
     }
     if (nf) nearfar_finish(R, acc);
