@@ -44,12 +44,12 @@ HBM_PEAK_GBS = 8000.0
 INF = 2**31 - 1
 ALGOS = ("sssp", "bfs", "cc")
 # (mode, schedule, mapping, passes of local expansion, near-far far_degree,
-# near-far bucket width in quarters of the mean weight; 0 = the tuned width)
+# near-far bucket width in eighths of the mean weight; 0 = the tuned width)
 VARIANTS = {"vertex-sync": (0, 0, 3, 0, 0, 0), "vertex-async": (0, 1, 3, 0, 0, 0),
             "edge-sync": (1, 0, 0, 0, 0, 0), "edge-async": (1, 1, 0, 0, 0, 0),
             "nearfar": (0, 3, 3, 0, 0, 0), "diropt": (0, 4, 3, 0, 0, 0),
             "vertex-async-h8": (0, 1, 3, 8, 0, 0), "nearfar-h32": (0, 3, 3, 32, 0, 0),
-            "nearfar-long64-h8": (0, 3, 3, 8, 64, 1)}
+            "nearfar-long64-h4": (0, 3, 3, 4, 64, 3)}
 
 
 def log(*a):
@@ -331,7 +331,7 @@ def main():
     if not args.no_variants:
         s = sources[0]
         for a in ALGOS:
-            for vname, (mode, sched, mp, hops, far, dq) in VARIANTS.items():
+            for vname, (mode, sched, mp, hops, far, de) in VARIANTS.items():
                 if (sched == 3 and a != "sssp") or (sched == 4 and a == "sssp"):
                     continue  # near-far is an SSSP schedule, the per-round choice BFS/CC
                 if hops and a == "cc":
@@ -339,7 +339,7 @@ def main():
                 if sched == 4 and a == "cc":
                     mode = 1  # CC's per-round choice starts from edge sweeps
                 o = gg.make_opts(mode, sched, mp, hops=hops, far_degree=far,
-                                 delta=max(1, int(dq * avg_w / 4)) if dq else 0)
+                                 delta=max(1, int(de * avg_w / 8)) if de else 0)
                 times = []
                 for _ in range(max(args.reps, 5 if hg.m >= 1 << 20 else 100)):
                     torch.cuda.synchronize()

@@ -288,8 +288,8 @@ int gg_resolve(gg_graph g, int32_t algo, const gg_opts* in, gg_opts* out);
 typedef struct {
     int32_t algo, size_class, skew_class, depth_class; /* depth -1 = any */
     int32_t mode, sched, mapping;
-    int32_t delta_q;    /* GG_NEARFAR: bucket width in quarters of the mean edge weight,
-                           0..2^22 (0 = 16, four mean weights) */
+    int32_t delta_eighths; /* GG_NEARFAR: bucket width in eighths of the mean edge weight,
+                              0..2^23 (0 = 32, four mean weights) */
     int32_t hops;       /* gg_opts.hops of the variant, 0..64; nonzero only for vertex-based
                            GG_ASYNC or GG_NEARFAR with the BALANCED (or AUTO) mapping */
     int32_t far_degree; /* gg_opts.far_degree of the variant, >= 0; nonzero only for

@@ -236,7 +236,7 @@ void resolve(gg_graph g, int algo, const gg_opts* in, gg_opts* out) {
     t.sched = GG_ASYNC;
     t.mapping = GG_MAP_BALANCED;
     gg_tune_lookup(algo, sc, kc, dc, &t);
-    const int32_t tm = t.mode, ts = t.sched, tp = t.mapping, tq = t.delta_q;
+    const int32_t tm = t.mode, ts = t.sched, tp = t.mapping, te = t.delta_eighths;
     if (auto_mode) o.mode = tm;
     // the tuned schedule comes with its local expansion and deferral
     if (auto_sched) {
@@ -249,9 +249,9 @@ void resolve(gg_graph g, int algo, const gg_opts* in, gg_opts* out) {
         o.mode = algo == GG_ALGO_CC ? GG_EDGE : GG_VERTEX;
     if (auto_map) o.mapping = tp;
     // bucket width of the near-far schedule: explicit, else the table's
-    // quarters of the mean weight, else 4 mean weights
+    // eighths of the mean weight, else 4 mean weights
     if (o.sched == GG_NEARFAR && o.delta <= 0)
-        o.delta = std::max(1, (int)((tq > 0 ? tq : 16) * g->avg_w / 4));
+        o.delta = std::max(1, (int)((te > 0 ? te : 32) * g->avg_w / 8));
     // a choice taken from the table must be one this graph can run
     if (auto_sched && o.sched == GG_DIROPT && !diropt_ok(g, algo, o.mode)) {
         o.sched = algo == GG_ALGO_CC ? GG_SYNC : GG_ASYNC;

@@ -75,7 +75,7 @@ class TuneEntry(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("size_class", ctypes.c_int32),
                 ("skew_class", ctypes.c_int32), ("depth_class", ctypes.c_int32),
                 ("mode", ctypes.c_int32), ("sched", ctypes.c_int32), ("mapping", ctypes.c_int32),
-                ("delta_q", ctypes.c_int32), ("hops", ctypes.c_int32),
+                ("delta_eighths", ctypes.c_int32), ("hops", ctypes.c_int32),
                 ("far_degree", ctypes.c_int32)]
 
 
@@ -182,13 +182,13 @@ def lib():
 # ------------------------------------------------------------- tuning ------
 def tune_set(entries):
     """Install a tuning table: a list of dicts with algo, size_class,
-    skew_class, depth_class, mode, sched, mapping (and optionally delta_q,
+    skew_class, depth_class, mode, sched, mapping (and optionally delta_eighths,
     hops, far_degree)."""
     arr = (TuneEntry * max(1, len(entries)))()
     for i, e in enumerate(entries):
         for k in ("algo", "size_class", "skew_class", "depth_class", "mode", "sched", "mapping"):
             setattr(arr[i], k, int(e[k]))
-        arr[i].delta_q = int(e.get("delta_q", 0))
+        arr[i].delta_eighths = int(e.get("delta_eighths", 0))
         arr[i].hops = int(e.get("hops", 0))
         arr[i].far_degree = int(e.get("far_degree", 0))
     _check(lib().gg_tune_set(arr, len(entries)), "gg_tune_set")
@@ -216,12 +216,12 @@ def class_of(m, n, max_out_degree, levels=-1):
 
 def tune_lookup(algo, size_class, skew_class, depth_class, full=False):
     """(mode, sched, mapping), or with full=True the whole chosen entry as a
-    dict (mode, sched, mapping, delta_q, hops, far_degree)."""
+    dict (mode, sched, mapping, delta_eighths, hops, far_degree)."""
     t = TuneEntry()
     _check(lib().gg_tune_lookup(algo, size_class, skew_class, depth_class, ctypes.byref(t)),
            "gg_tune_lookup")
     if full:
-        return {k: getattr(t, k) for k in ("mode", "sched", "mapping", "delta_q", "hops",
+        return {k: getattr(t, k) for k in ("mode", "sched", "mapping", "delta_eighths", "hops",
                                            "far_degree")}
     return (t.mode, t.sched, t.mapping)
 

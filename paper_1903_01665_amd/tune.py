@@ -25,7 +25,7 @@ import time
 from . import gen, gg
 
 ALGOS = ("sssp", "bfs", "cc")
-# (mode, schedule, mapping, near-far bucket width in quarters of the mean
+# (mode, schedule, mapping, near-far bucket width in eighths of the mean
 # weight, passes of local expansion, near-far far_degree)
 V, NF, BAL = gg.VERTEX, gg.NEARFAR, gg.MAP_BALANCED
 VARIANTS = [(V, gg.SYNC, gg.MAP_THREAD, 0, 0, 0), (V, gg.SYNC, gg.MAP_WAVE, 0, 0, 0),
@@ -33,10 +33,10 @@ VARIANTS = [(V, gg.SYNC, gg.MAP_THREAD, 0, 0, 0), (V, gg.SYNC, gg.MAP_WAVE, 0, 0
             (V, gg.ASYNC, gg.MAP_WAVE, 0, 0, 0), (V, gg.ASYNC, BAL, 0, 0, 0),
             (gg.EDGE, gg.SYNC, gg.MAP_AUTO, 0, 0, 0), (gg.EDGE, gg.ASYNC, gg.MAP_AUTO, 0, 0, 0)]
 LOCAL = [(V, gg.ASYNC, BAL, 0, h, 0) for h in (2, 8)]
-NEARFAR = ([(V, NF, BAL, dq, 0, 0) for dq in (4, 8, 16, 32, 64, 256)] +
-           [(V, NF, BAL, dq, h, 0) for dq in (4, 8, 16, 32, 64) for h in (2, 8, 32)] +
+NEARFAR = ([(V, NF, BAL, de, 0, 0) for de in (8, 16, 32, 64, 128, 512)] +
+           [(V, NF, BAL, de, h, 0) for de in (8, 16, 32, 64, 128) for h in (2, 8, 32)] +
            # narrow buckets that hold back only long rows (skewed graphs)
-           [(V, NF, BAL, dq, h, 64) for dq in (1, 2, 4) for h in (0, 8)])
+           [(V, NF, BAL, de, 4, far) for de in (2, 3, 4, 6) for far in (32, 96)])
 DIROPT = [(V, gg.DIROPT, BAL, 0, 0, 0)]
 CC_DIROPT = [(gg.EDGE, gg.DIROPT, BAL, 0, 0, 0)]
 
@@ -62,9 +62,9 @@ def time_variant(g, algo, srcs, v, reps, out, avg_w):
     """Sum over the sources of the median time of `reps` runs (CC: one
     source-free run set)."""
     import torch
-    mode, sched, mapping, dq, hops, far = v
+    mode, sched, mapping, de, hops, far = v
     o = gg.make_opts(mode, sched, mapping, time_limit_ms=4000,
-                     delta=max(1, int(dq * avg_w / 4)) if sched == gg.NEARFAR else 0, hops=hops,
+                     delta=max(1, int(de * avg_w / 8)) if sched == gg.NEARFAR else 0, hops=hops,
                      far_degree=far)
     total = 0.0
     for src in srcs[:1] if algo == "cc" else srcs:
@@ -98,8 +98,8 @@ def knobs(v):
 
 
 def variant_key(k):
-    """Variant tuple from a measurement key "mode/sched/mapping/delta_q/hops/
-    far_degree"."""
+    """Variant tuple from a measurement key "mode/sched/mapping/delta_eighths/
+    hops/far_degree"."""
     return tuple(int(x) for x in k.split("/"))
 
 
@@ -121,7 +121,7 @@ def choose(results):
         v = min(near, key=lambda u: (knobs(u), score[u]))
         entries.append({"algo": ALGOS.index(algo), "size_class": cls[0], "skew_class": cls[1],
                         "depth_class": cls[2], "mode": v[0], "sched": v[1], "mapping": v[2],
-                        "delta_q": v[3], "hops": v[4], "far_degree": v[5]})
+                        "delta_eighths": v[3], "hops": v[4], "far_degree": v[5]})
         detail.append({"algo": algo, "class": list(cls),
                        "relative_to_best": {"/".join(map(str, k)): round(math.exp(x), 3)
                                             for k, x in score.items()}})

@@ -118,10 +118,10 @@ def test_batch_with_local_expansion(gg, flags):
         for kc in range(3):
             entries.append(dict(algo=0, size_class=sc, skew_class=kc, depth_class=-1, mode=0,
                                 sched=gg.ASYNC if sc % 2 else gg.NEARFAR, mapping=3,
-                                delta_q=8 if sc % 2 == 0 else 0, hops=8,
+                                delta_eighths=16 if sc % 2 == 0 else 0, hops=8,
                                 far_degree=4 if sc % 2 == 0 else 0))
             entries.append(dict(algo=1, size_class=sc, skew_class=kc, depth_class=-1, mode=0,
-                                sched=gg.ASYNC, mapping=3, delta_q=0, hops=3))
+                                sched=gg.ASYNC, mapping=3, delta_eighths=0, hops=3))
     gg.tune_set(entries)
     try:
         inst = make_instances(40, 77 + flags)

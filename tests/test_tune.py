@@ -81,25 +81,25 @@ def test_table_takes_only_runnable_schedules():
 
 def test_schedule_knobs_in_the_table():
     base = dict(algo=0, size_class=13, skew_class=0, depth_class=2, mode=V, sched=gg.NEARFAR,
-                mapping=3, delta_q=16)
+                mapping=3, delta_eighths=32)
     gg.tune_set([dict(base, hops=32, far_degree=64),
-                 dict(base, algo=1, sched=A, mapping=0, delta_q=0, hops=8)])
+                 dict(base, algo=1, sched=A, mapping=0, delta_eighths=0, hops=8)])
     assert gg.tune_lookup(0, 13, 0, 2, full=True) == dict(mode=V, sched=gg.NEARFAR, mapping=3,
-                                                          delta_q=16, hops=32, far_degree=64)
-    assert gg.tune_lookup(1, 13, 0, 2, full=True) == dict(mode=V, sched=A, mapping=3, delta_q=0,
+                                                          delta_eighths=32, hops=32, far_degree=64)
+    assert gg.tune_lookup(1, 13, 0, 2, full=True) == dict(mode=V, sched=A, mapping=3, delta_eighths=0,
                                                           hops=8, far_degree=0)
     # entries without the fields, and the built-in rules, set none of them
     gg.tune_set([base])
     e = gg.tune_lookup(0, 13, 0, 2, full=True)
-    assert (e["delta_q"], e["hops"], e["far_degree"]) == (16, 0, 0)
+    assert (e["delta_eighths"], e["hops"], e["far_degree"]) == (32, 0, 0)
     gg.tune_set([])
     e = gg.tune_lookup(0, 13, 0, 2, full=True)
-    assert (e["delta_q"], e["hops"], e["far_degree"]) == (0, 0, 0)
+    assert (e["delta_eighths"], e["hops"], e["far_degree"]) == (0, 0, 0)
     # out of range, or on a variant the knob does not apply to
     for bad in (dict(base, hops=-1), dict(base, hops=65), dict(base, sched=S, hops=2),
                 dict(base, mode=E, sched=A, hops=2), dict(base, sched=A, mapping=1, hops=2),
                 dict(base, far_degree=-1), dict(base, sched=A, far_degree=64),
-                dict(base, delta_q=-1), dict(base, delta_q=(1 << 22) + 1)):
+                dict(base, delta_eighths=-1), dict(base, delta_eighths=(1 << 23) + 1)):
         with pytest.raises(gg.GGError):
             gg.tune_set([bad])
 
@@ -107,13 +107,13 @@ def test_schedule_knobs_in_the_table():
 def test_calibration_ties_go_to_fewer_knobs():
     from paper_1903_01665_amd import tune
     plain = (V, A, 3, 0, 0, 0)
-    nf = (V, gg.NEARFAR, 3, 4, 8, 64)
+    nf = (V, gg.NEARFAR, 3, 3, 4, 64)
     cls = (13, 2, 0)
 
     def pick(t_plain, t_nf):
         entries, _ = tune.choose([("sssp", cls, {plain: t_plain, nf: t_nf})])
         e = entries[0]
-        return (e["mode"], e["sched"], e["mapping"], e["delta_q"], e["hops"], e["far_degree"])
+        return (e["mode"], e["sched"], e["mapping"], e["delta_eighths"], e["hops"], e["far_degree"])
 
     assert pick(1.00, 0.98) == plain   # within 3 %: the plain worklist
     assert pick(1.00, 0.90) == nf      # a clear win keeps the knobs
