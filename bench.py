@@ -124,16 +124,27 @@ def kernel_symbol(algo, kind, mode, sched, mapping, hops=0):
     return f"void gg::k_vasync<{a}, {mapping}, {nf}>(gg::Round)"
 
 
+def kernel_code_hash(src=None):
+    """SHA-256 of the kernel source (default: gg_kernels.hip) with comments
+    and blank lines removed: it changes when the code does, not when a
+    comment does."""
+    import hashlib
+    import re
+    if src is None:
+        src = open(os.path.join(ROOT, "paper_1903_01665_amd", "csrc", "gg_kernels.hip")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    lines = [re.sub(r"//.*", "", ln).rstrip() for ln in src.splitlines()]
+    return hashlib.sha256("\n".join(ln for ln in lines if ln.strip()).encode()).hexdigest()
+
+
 def measured_traffic(symbol, workload):
     """HBM bytes per dispatch from the committed counter summary, or None when
-    the summary is for another workload or the kernels changed since."""
-    import hashlib
+    the summary is for another workload or the kernel code changed since."""
     path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.json")
-    src = os.path.join(ROOT, "paper_1903_01665_amd", "csrc", "gg_kernels.hip")
     if not os.path.exists(path):
         return None
     t = json.load(open(path))
-    if t.get("kernels_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+    if t.get("kernel_code_sha256") != kernel_code_hash():
         return None
     return t["bytes_per_dispatch"].get(symbol)
 

@@ -131,9 +131,11 @@ __device__ __forceinline__ bool round_begin(const Round& R) {
 
 // Near-far schedule (SSSP, delta > 0): round r serves only the frontier
 // vertices whose distance is below the bound B_r and keeps the others on the
-// frontier.  B_0 = delta; B_r = B_{r-1} while round r-1 pushed some distance
-// below B_{r-1}, else B_{r-1} + delta.  Every block derives B_r from the slots
-// of round r-1, so the choice is the same grid-wide; block 0 records it.
+// frontier (with Round::far_degree > 0 only the rows longer than it are
+// kept; shorter ones are served whatever their distance).  B_0 = delta;
+// B_r = B_{r-1} while round r-1 pushed some distance below B_{r-1}, else
+// B_{r-1} + delta.  Every block derives B_r from the slots of round r-1, so
+// the choice is the same grid-wide; block 0 records it.
 __device__ __forceinline__ int nearfar_bound(const Round& R) {
     Ctl* ctl = R.ws.ctl;
     int b = R.delta;

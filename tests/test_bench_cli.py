@@ -34,3 +34,17 @@ def test_algorithmic_bytes_model():
     prof["swept_edges"] = 600
     assert bench.algorithmic_bytes("cc", 1, 4, "round", n, prof, 3) == \
         16 * 600 + 8 * 400 + 16 * 100 + 3 * (n // 64) + 4 * 7 + 10 * 50
+
+
+def test_traffic_summary_is_keyed_to_the_kernel_code():
+    """The committed HBM traffic summary stays valid across comment edits of
+    the kernel source and is dropped when the code changes."""
+    import bench
+    src = "__global__ void k(int* p) {\n    p[0] = 1;  // store\n}\n"
+    h = bench.kernel_code_hash(src)
+    assert bench.kernel_code_hash("// header\n" + src + "\n/* block\n comment */\n") == h
+    assert bench.kernel_code_hash(src.replace("// store", "// a different note")) == h
+    assert bench.kernel_code_hash(src.replace("p[0] = 1", "p[0] = 2")) != h
+    assert bench.kernel_code_hash() == bench.kernel_code_hash(
+        open(bench.os.path.join(bench.ROOT, "paper_1903_01665_amd", "csrc",
+                                "gg_kernels.hip")).read())
