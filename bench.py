@@ -125,13 +125,16 @@ def kernel_symbol(algo, kind, mode, sched, mapping, hops=0):
 
 
 def kernel_code_hash(src=None):
-    """SHA-256 of the kernel source (default: gg_kernels.hip) with comments
-    and blank lines removed: it changes when the code does, not when a
-    comment does."""
+    """SHA-256 of the kernel source (default: gg_internal.h, which fixes the
+    kernels' structures and constants, then gg_kernels.hip) with comments and
+    blank lines removed: it changes when the code does, not when a comment
+    does."""
     import hashlib
     import re
     if src is None:
-        src = open(os.path.join(ROOT, "paper_1903_01665_amd", "csrc", "gg_kernels.hip")).read()
+        csrc = os.path.join(ROOT, "paper_1903_01665_amd", "csrc")
+        src = "".join(open(os.path.join(csrc, f)).read() + "\n"
+                      for f in ("gg_internal.h", "gg_kernels.hip"))
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     lines = [re.sub(r"//.*", "", ln).rstrip() for ln in src.splitlines()]
     return hashlib.sha256("\n".join(ln for ln in lines if ln.strip()).encode()).hexdigest()

@@ -45,6 +45,7 @@ def test_traffic_summary_is_keyed_to_the_kernel_code():
     assert bench.kernel_code_hash("// header\n" + src + "\n/* block\n comment */\n") == h
     assert bench.kernel_code_hash(src.replace("// store", "// a different note")) == h
     assert bench.kernel_code_hash(src.replace("p[0] = 1", "p[0] = 2")) != h
-    assert bench.kernel_code_hash() == bench.kernel_code_hash(
-        open(bench.os.path.join(bench.ROOT, "paper_1903_01665_amd", "csrc",
-                                "gg_kernels.hip")).read())
+    csrc = bench.os.path.join(bench.ROOT, "paper_1903_01665_amd", "csrc")
+    both = "".join(open(bench.os.path.join(csrc, f)).read() + "\n"
+                   for f in ("gg_internal.h", "gg_kernels.hip"))
+    assert bench.kernel_code_hash() == bench.kernel_code_hash(both)
