@@ -129,7 +129,7 @@ typedef struct {
                               vertex-based, BALANCED mapping), 0..64; 0 = off.  A wavefront
                               serves the vertices it has just lowered (those below the
                               near-far bound) again in the same round, up to `hops` times,
-                              from a 64-entry list of its own; what does not fit, and the
+                              from a 256-entry list of its own; what does not fit, and the
                               list left after the last pass, goes to the next round's
                               frontier.  Fewer rounds on high-diameter graphs; the result
                               is the same.  Ignored by other variants; with
