@@ -52,22 +52,22 @@ int grid_for(long long items_per_block_unit, long long units) {
 
 void free_ws_arrays(gg_ws_s* ws) {
     if (!ws) return;
-    if (ws->vflag_mem) hipFree(ws->vflag_mem);
-    if (ws->dev.hstamp) hipFree(ws->dev.hstamp);
-    if (ws->dev.ctl) hipFree(ws->dev.ctl);
-    if (ws->dev.stat) hipFree(ws->dev.stat);
-    if (ws->dev.pcount) hipFree(ws->dev.pcount);
-    if (ws->h_done) hipHostFree(ws->h_done);
-    if (ws->msf_parent) hipFree(ws->msf_parent);
-    if (ws->msf_best) hipFree(ws->msf_best);
+    if (ws->vflag_mem) (void)hipFree(ws->vflag_mem);
+    if (ws->dev.hstamp) (void)hipFree(ws->dev.hstamp);
+    if (ws->dev.ctl) (void)hipFree(ws->dev.ctl);
+    if (ws->dev.stat) (void)hipFree(ws->dev.stat);
+    if (ws->dev.pcount) (void)hipFree(ws->dev.pcount);
+    if (ws->h_done) (void)hipHostFree(ws->h_done);
+    if (ws->msf_parent) (void)hipFree(ws->msf_parent);
+    if (ws->msf_best) (void)hipFree(ws->msf_best);
     ws->msf_parent = nullptr;
     ws->msf_best = nullptr;
     for (auto& e : ws->ev)
-        if (e) hipEventDestroy(e);
+        if (e) (void)hipEventDestroy(e);
     for (auto& e : ws->pev)
-        if (e) hipEventDestroy(e);
+        if (e) (void)hipEventDestroy(e);
     ws->pev.clear();
-    if (ws->finished) hipEventDestroy(ws->finished);
+    if (ws->finished) (void)hipEventDestroy(ws->finished);
     ws->vflag_mem = nullptr;
     ws->dev.hstamp = nullptr;
     ws->dev.ctl = nullptr;
@@ -170,9 +170,9 @@ void free_graph_arrays(gg_graph g) {
     dfree(g->psrc);
     dfree(g->pcol);
     dfree(g->pw);
-    if (g->srow && g->srow != g->row) hipFree(g->srow);
-    if (g->scol && g->scol != g->col) hipFree(g->scol);
-    if (g->ssrc && g->ssrc != g->src) hipFree(g->ssrc);
+    if (g->srow && g->srow != g->row) (void)hipFree(g->srow);
+    if (g->scol && g->scol != g->col) (void)hipFree(g->scol);
+    if (g->ssrc && g->ssrc != g->src) (void)hipFree(g->ssrc);
     dfree(g->row);
     dfree(g->col);
     dfree(g->w);
@@ -653,7 +653,7 @@ int gg_graph_upload(int32_t n, int64_t m, const int32_t* row_ptr, const int32_t*
     g->weighted = w != nullptr;
     const hipMemcpyKind kind = on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     auto bail = [&](int code) {
-        hipStreamSynchronize(s);
+        (void)hipStreamSynchronize(s);
         free_graph_arrays(g);
         delete g;
         return code;
@@ -667,8 +667,6 @@ int gg_graph_upload(int32_t n, int64_t m, const int32_t* row_ptr, const int32_t*
                                             hipMemcpyHostToDevice, s);
     if (e == hipSuccess && m) e = hipMemcpyAsync(g->col, col, sizeof(int) * m, kind, s);
     if (e == hipSuccess && m && w) e = hipMemcpyAsync(g->w, w, sizeof(int) * m, kind, s);
-    const int wpb = kBlock / 64;
-    const long long ntiles = ((long long)n + 63) / 64;
     auto grid = [&](long long units) {
         return (int)std::max(1LL, std::min<long long>(units, device().max_blocks));
     };
@@ -783,7 +781,7 @@ int gg_graph_upload(int32_t n, int64_t m, const int32_t* row_ptr, const int32_t*
 int gg_graph_free(gg_graph g) {
     if (!g) return GG_EINVAL;
     if (g->n_ws > 0) return GG_EBUSY;
-    hipDeviceSynchronize();
+    (void)hipDeviceSynchronize();
     free_ws_arrays(g->ws0);
     delete g->ws0;
     free_graph_arrays(g);
@@ -816,7 +814,7 @@ int gg_ws_create(gg_graph g, gg_ws* out) {
 
 int gg_ws_free(gg_ws ws) {
     if (!ws || ws->is_default) return GG_EINVAL;
-    if (ws->used) hipEventSynchronize(ws->finished);
+    if (ws->used) (void)hipEventSynchronize(ws->finished);
     ws->owner->n_ws--;
     free_ws_arrays(ws);
     delete ws;
@@ -928,7 +926,7 @@ int gg_graph_probe(gg_graph g, void* stream) {
     int rc = run(g, nullptr, GG_ALGO_BFS, g->argmax_deg, &o, dist, stream);
     gg_stats st{};
     if (rc == GG_OK) rc = gg_last_stats(g, nullptr, &st);
-    hipFree(dist);
+    (void)hipFree(dist);  // waits for the traversal; a failure of it shows in rc
     if (rc != GG_OK) return rc;
     g->levels = st.iterations;
     return GG_OK;

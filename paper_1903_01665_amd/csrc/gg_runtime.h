@@ -32,7 +32,7 @@ inline Dev& device() {
     static Dev d;
     static std::once_flag once;
     std::call_once(once, [] {
-        hipGetDevice(&d.id);
+        if (hipGetDevice(&d.id) != hipSuccess) d.id = 0;
         hipDeviceProp_t p;
         if (hipGetDeviceProperties(&p, d.id) == hipSuccess) {
             d.cus = p.multiProcessorCount;
