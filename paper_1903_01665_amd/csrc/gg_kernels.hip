@@ -811,14 +811,17 @@ __device__ void cc_first_pass(const Round& R, Acc& acc) {
         }
         __builtin_amdgcn_wave_barrier();
     }
-    // Heavy rows, chunk by chunk.  The loop is pipelined across a
-    // wavefront's chunks: the next chunk's descriptor and row end are
-    // fetched while this chunk's columns load, the column loads of a chunk
-    // are issued together (indices clamped into the chunk, surplus lanes
-    // masked after the load), and the result of a chunk's atomicMin (did it
-    // lower the label: push the row) is read one chunk later, so that the
-    // atomic's round trip overlaps the next chunk's loads.
+    // Heavy rows, chunk by chunk (kChunk edges, the chunk size of every
+    // graph).  The loop is pipelined across a wavefront's chunks: the next
+    // chunk's descriptor and row end are fetched while this chunk's columns
+    // load; the column loads of a chunk are issued together and need only
+    // the chunk's first edge (indices clamped to the column array, lanes
+    // past the row end masked after the load); and the result of a chunk's
+    // atomicMin (did it lower the label: push the row) is read one chunk
+    // later, so that the atomic's round trip overlaps the next chunk's loads.
+    constexpr int C = kChunk / 64;
     const long long nch = g.n_shchunks;
+    const int last = g.ms - 1;
     long long k = gw;
     int2 c = k < nch ? g.shchunks[k] : make_int2(0, 0);
     int rend = k < nch ? g.srow[c.x + 1] : 0;
@@ -826,16 +829,14 @@ __device__ void cc_first_pass(const Round& R, Acc& acc) {
     for (; k < nch; k += tw) {
         const long long kn = k + tw;
         const int2 cn = kn < nch ? g.shchunks[kn] : c;
-        const int e1 = min(c.y + g.chunk, rend);
+        int v[C];
+#pragma unroll
+        for (int j = 0; j < C; ++j) v[j] = g.scol[min(c.y + j * 64 + lane, last)];
+        const int e1 = min(c.y + kChunk, rend);
         int x = kInf;
-        for (int e0 = c.y; e0 < e1; e0 += 4 * 64) {
-            int v[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) v[j] = g.scol[min(e0 + j * 64 + lane, e1 - 1)];
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (e0 + j * 64 + lane < e1) x = min(x, v[j]);
-        }
+        for (int j = 0; j < C; ++j)
+            if (c.y + j * 64 + lane < e1) x = min(x, v[j]);
         const int rendn = kn < nch ? g.srow[cn.x + 1] : 0;
 #pragma unroll
         for (int d = 32; d > 0; d >>= 1) x = min(x, __shfl_xor(x, d, 64));
