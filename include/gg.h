@@ -72,7 +72,7 @@ typedef enum { GG_VERTEX = 0, GG_EDGE = 1, GG_MODE_AUTO = 2 } gg_mode;
  * from the size of the frontier the previous round left; it needs the
  * both-directions CSR that GG_SYMMETRIZE or GG_SYMMETRIC provide.
  *   BFS (vertex-based): a small frontier pushes along out-edges as GG_ASYNC
- *   does; a frontier of more than n/20 vertices is pulled -- every unvisited
+ *   does; a frontier of more than n/12 vertices is pulled -- every unvisited
  *   vertex scans its in-neighbours (the DSL's innbrs iterator, Sec. 2) and
  *   stops at the first one on the level.
  *   CC (edge-based): round 0 takes one synchronous step from the ids
