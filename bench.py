@@ -25,7 +25,7 @@ serve      Poisson arrivals (2000 queries/s) of SSSP/BFS queries over 32
            query at a time) on the same trace; value = GTEPS served, with
            p50/p99 latency of both.
 
-Prints one JSON line.  ``--gpus N`` with N > 1 exits: this build uses one GPU.
+Prints one JSON line.  ``--gpus N`` with N > 1 exits: the benchmark runs on one GPU.
 """
 from __future__ import annotations
 
@@ -181,7 +181,7 @@ def main():
                          "stream (default: at the same time on three streams)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported",
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported",
               file=sys.stderr)
         sys.exit(2)
     if args.config == "batched":
