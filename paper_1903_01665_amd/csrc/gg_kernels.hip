@@ -661,19 +661,16 @@ __device__ __forceinline__ void edge_sync_one(const Round& R, int u, int t, int 
             acc.u++;
         }
     } else {
+        // CC: the atomics return nothing (see edge_sync_four)
         const int lu = val[u], lt = val[t];
         if (lu < lt) {
-            const int old = atomicMin(&val[t], lu);
-            if (lu < old) {
-                acc.u++;
-                if (PUSH) sweep_push(R, t, acc);
-            }
+            atomicMin(&val[t], lu);
+            acc.u++;
+            if (PUSH) sweep_push(R, t, acc);
         } else if (lt < lu && !R.g.symmetric) {
-            const int old = atomicMin(&val[u], lt);
-            if (lt < old) {
-                acc.u++;
-                if (PUSH) sweep_push(R, u, acc);
-            }
+            atomicMin(&val[u], lt);
+            acc.u++;
+            if (PUSH) sweep_push(R, u, acc);
         }
     }
 }
@@ -721,16 +718,23 @@ __device__ __forceinline__ void edge_sync_four(const Round& R, const int* src, c
                     acc.u++;
                 }
             } else {
+                // CC sweeps lower labels with atomics that return nothing: a
+                // lane whose loads show a lower label on one end counts the
+                // change (and pushes the other end) itself.  That end's
+                // label does drop in this sweep -- by this atomic, or by a
+                // concurrent lower one whose lane counts it too -- so a sweep
+                // that reports no change saw every edge consistent, and the
+                // lane does not wait for the atomic's round trip.  (Most
+                // edges of a first sweep lower a label: er23's first sweep
+                // took 2.25 ms with returning atomics.)
                 if (vu[j] < vt[j]) {
-                    if (vu[j] < atomicMin(&val[t[j]], vu[j])) {
-                        acc.u++;
-                        if (PUSH) sweep_push(R, t[j], acc);
-                    }
+                    atomicMin(&val[t[j]], vu[j]);
+                    acc.u++;
+                    if (PUSH) sweep_push(R, t[j], acc);
                 } else if (vt[j] < vu[j] && !g.symmetric) {
-                    if (vt[j] < atomicMin(&val[u[j]], vt[j])) {
-                        acc.u++;
-                        if (PUSH) sweep_push(R, u[j], acc);
-                    }
+                    atomicMin(&val[u[j]], vt[j]);
+                    acc.u++;
+                    if (PUSH) sweep_push(R, u[j], acc);
                 }
             }
         }
