@@ -298,22 +298,32 @@ __device__ __forceinline__ void relax_batch(const Round& R, const int* col, cons
     for (int j = 0; j < U; ++j) {
         if (!ok[j]) continue;
         acc.e++;
+        // An edge whose loaded head value the candidate beats lowers that
+        // head in this round -- by this atomic, or by a concurrent lower one
+        // whose lane pushes the head too -- so the push is decided from the
+        // load and the atomic returns nothing: the lane does not wait for it
+        // (pushes are idempotent flag stores).
         bool hit = false;
         if (A == SSSP) {
             const unsigned cand = (unsigned)sv[j] + (unsigned)wt[j];
-            if (cand < (unsigned)cur[j]) hit = (int)cand < atomicMin(&val[t[j]], (int)cand);
+            if (cand < (unsigned)cur[j]) {
+                atomicMin(&val[t[j]], (int)cand);
+                hit = true;
+            }
         } else if (A == BFS) {
             const int nl = sv[j] + 1;
             if (cur[j] > nl) {
-                if (ATOM) {
-                    hit = nl < atomicMin(&val[t[j]], nl);
-                } else {
+                if (ATOM)
+                    atomicMin(&val[t[j]], nl);
+                else
                     val[t[j]] = nl;
-                    hit = true;
-                }
+                hit = true;
             }
         } else {
-            if (sv[j] < cur[j]) hit = sv[j] < atomicMin(&val[t[j]], sv[j]);
+            if (sv[j] < cur[j]) {
+                atomicMin(&val[t[j]], sv[j]);
+                hit = true;
+            }
         }
         if (hit) {
             if (PUSH) {
