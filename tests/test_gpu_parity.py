@@ -551,3 +551,36 @@ def test_binding_loaded_before_torch(gg):
     say("[gpu] library loaded before torch (subprocess)")
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0 and "one runtime ok" in r.stdout, r.stdout[-2000:] + r.stderr[-2000:]
+
+
+def test_auto_carries_the_tuned_schedule_knobs(gg):
+    """AUTO resolution takes the table entry's passes of local expansion,
+    long-row threshold and bucket width with its schedule (and an explicit
+    schedule keeps the caller's), and the traversal it resolves to is exact."""
+    hg = gen.workload("rmat12")
+    s = int(gen.pick_sources(hg, 1, stream=gen.STREAM["sources"])[0])
+    g = gg.Graph.from_host(hg, symmetrize=True)
+    saved = gg.tune_get()
+    try:
+        sc, kc, dc = g.graph_class()
+        gg.tune_set([dict(algo=0, size_class=sc, skew_class=kc, depth_class=-1, mode=gg.VERTEX,
+                          sched=gg.NEARFAR, mapping=3, delta_eighths=3, hops=4, far_degree=40),
+                     dict(algo=1, size_class=sc, skew_class=kc, depth_class=-1, mode=gg.VERTEX,
+                          sched=gg.ASYNC, mapping=3, hops=6)])
+        o = g.resolve(gg.ALGO_SSSP)
+        avg_w = float(hg.w.mean())
+        assert (o.mode, o.sched, o.mapping, o.hops, o.far_degree) == (gg.VERTEX, gg.NEARFAR, 3,
+                                                                     4, 40)
+        assert o.delta == max(1, int(3 * avg_w / 8))
+        assert (g.resolve(gg.ALGO_BFS).sched, g.resolve(gg.ALGO_BFS).hops) == (gg.ASYNC, 6)
+        # an explicit schedule keeps the caller's knobs
+        e = g.resolve(gg.ALGO_SSSP, gg.make_opts(gg.VERTEX, gg.ASYNC, 3, hops=2))
+        assert (e.sched, e.hops, e.far_degree) == (gg.ASYNC, 2, 0)
+        say(f"[gpu] auto knobs {hg.name} class={(sc, kc, dc)}")
+        np.testing.assert_array_equal(g.sssp(s).cpu().numpy(),
+                                      oracle.sssp(hg.n, hg.row_ptr, hg.col, hg.w, s))
+        np.testing.assert_array_equal(g.bfs(s).cpu().numpy(),
+                                      oracle.bfs(hg.n, hg.row_ptr, hg.col, s))
+    finally:
+        gg.tune_set(saved)
+        g.free()
