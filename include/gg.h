@@ -65,9 +65,10 @@ typedef enum { GG_VERTEX = 0, GG_EDGE = 1, GG_MODE_AUTO = 2 } gg_mode;
  * GG_NEARFAR (SSSP, vertex-based, balanced mapping only) orders the worklist
  * by distance in buckets of width delta -- the Delta-stepping idea the paper
  * credits for the CPU worklist's win on road networks (Sec. 4.2-4.3): a round
- * serves only frontier vertices below the current bound and keeps the rest;
- * the bound grows by delta once a round pushes nothing below it.  The result
- * is the same as every other schedule.
+ * serves only frontier vertices below the current bound and keeps the rest
+ * (with gg_opts.far_degree, only rows longer than it are kept); the bound
+ * grows by delta once a round pushes nothing below it.  The result is the
+ * same as every other schedule.
  * GG_DIROPT picks the dense or the sparse form of each round on the device,
  * from the size of the frontier the previous round left; it needs the
  * both-directions CSR that GG_SYMMETRIZE or GG_SYMMETRIC provide.
