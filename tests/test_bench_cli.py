@@ -49,3 +49,21 @@ def test_traffic_summary_is_keyed_to_the_kernel_code():
     both = "".join(open(bench.os.path.join(csrc, f)).read() + "\n"
                    for f in ("gg_internal.h", "gg_kernels.hip"))
     assert bench.kernel_code_hash() == bench.kernel_code_hash(both)
+
+
+def test_tuned_rmat22_kernels_are_in_the_traffic_summary():
+    """The kernels the tuned variants of rmat22's class launch carry the
+    symbols under which the committed HBM traffic summary lists them, so the
+    bench's roofline finds its traffic figure."""
+    import json
+    import bench
+    from paper_1903_01665_amd import gg
+    summary = json.load(open(bench.os.path.join(bench.ROOT, "profiles",
+                                                "hbm_traffic_rmat22.json")))
+    keys = set(summary["bytes_per_dispatch"])
+    for ai, algo in enumerate(bench.ALGOS):
+        # rmat22: m = 2^26, hub degree 159873, 7 levels
+        e = gg.tune_lookup(ai, *gg.class_of(1 << 26, 1 << 22, 159873, 7), full=True)
+        for kind in ("round", "heavy"):
+            sym = bench.kernel_symbol(algo, kind, e["mode"], e["sched"], e["mapping"], e["hops"])
+            assert sym in keys, (algo, kind, e, sym)
