@@ -122,3 +122,29 @@ def test_calibration_ties_go_to_fewer_knobs():
     entries, _ = tune.choose([("bfs", cls, {plain: 1.0, nf: 0.5}),
                               ("bfs", cls, {plain: 1.0, nf: 3.0})])
     assert (entries[0]["sched"], entries[0]["hops"]) == (A, 0)
+
+
+def test_table_rederived_from_recorded_measurements(tmp_path):
+    """tune.py --from-measurements rebuilds the entries from a table's
+    recorded timings (no GPU): the best variant per class, ties to fewer
+    knobs, every field of the chosen variant carried into the entry."""
+    import json
+    from paper_1903_01665_amd import tune
+    ms = {"0/1/3/0/0/0": 2.00, "0/3/3/2/4/96": 1.50, "0/3/3/3/4/32": 1.52,
+          "1/0/0/0/0/0": 4.0, "0/0/1/0/0/0": None}
+    raw = {"measurements": [{"algo": "sssp", "class": [13, 2, 0], "ms": ms},
+                            {"algo": "bfs", "class": [8, 0, 1],
+                             "ms": {"0/1/3/0/0/0": 1.0, "0/1/3/0/8/0": 0.99}}]}
+    src = tmp_path / "recorded.json"
+    src.write_text(json.dumps(raw))
+    out = tmp_path / "table.json"
+    tune.main(["--from-measurements", str(src), "--out", str(out)])
+    t = json.loads(out.read_text())
+    by = {(e["algo"], e["size_class"]): e for e in t["entries"]}
+    sssp = by[(0, 13)]
+    # 1.50 beats 1.52 by less than the tie margin, and both have 3 knobs: the score decides
+    assert (sssp["sched"], sssp["delta_eighths"], sssp["hops"], sssp["far_degree"]) == (3, 2, 4, 96)
+    # a 1% win of local expansion is a tie: the plain worklist stays
+    assert (by[(1, 8)]["sched"], by[(1, 8)]["hops"]) == (A, 0)
+    # the measurements are kept (a failed run as null)
+    assert t["measurements"][0]["ms"]["0/0/1/0/0/0"] is None
