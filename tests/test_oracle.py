@@ -113,6 +113,45 @@ def test_sssp_clamps_at_inf():
                                   [0, big, 2 * big - 1, INF])
 
 
+def test_sssp_clamp_against_brute_force_with_huge_weights():
+    # weights near 2^30 and 2^31: many shortest paths pass INF.  Floyd-
+    # Warshall and Bellman-Ford in int64 (clamped only when written out)
+    # and scipy's float Dijkstra (exact below 2^53) agree with the heap
+    # Dijkstra on which vertices stay finite and on every finite value
+    rng = np.random.default_rng(2**31 - 1)
+    for i in range(40):
+        n = int(rng.integers(2, 60))
+        m = int(rng.integers(0, 5 * n + 1))
+        lo = [1, 2**29, INF - 50][i % 3]
+        g = random_graph(rng, n, m, lo, INF, name=f"huge{i}")
+        s = int(rng.integers(0, n))
+        d = oracle.sssp(g.n, g.row_ptr, g.col, g.w, s)
+        np.testing.assert_array_equal(d, oracle.sssp_floyd_warshall(g.n, g.row_ptr, g.col, g.w, s))
+        np.testing.assert_array_equal(d, oracle.sssp_bellman_ford(g.n, g.row_ptr, g.col, g.w, s))
+        ref = csgraph.dijkstra(_scipy_min_matrix(g), directed=True, indices=s)
+        ref = np.where(np.isinf(ref) | (ref >= INF), INF, ref).astype(np.int64)
+        np.testing.assert_array_equal(d.astype(np.int64), ref)
+        clamped = (oracle.bfs(g.n, g.row_ptr, g.col, s) != INF) & (d == INF)
+        if not clamped.any():
+            assert oracle.check_sssp(g.n, g.row_ptr, g.col, g.w, s, d) == 0
+
+
+def _scipy_min_matrix(g):
+    # parallel edges keep their smallest weight (csr_matrix would sum them)
+    src = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    best = {}
+    for u, v, w in zip(src.tolist(), g.col.tolist(), g.w.tolist()):
+        if (u, v) not in best or w < best[(u, v)]:
+            best[(u, v)] = w
+    if not best:
+        return csr_matrix((g.n, g.n))
+    keys = list(best)
+    # a stored zero weight would read as "no edge": add a tiny offset and
+    # round it away (all other weights are integers >= 1)
+    vals = [best[k] if best[k] > 0 else 1e-9 for k in keys]
+    return csr_matrix((vals, ([k[0] for k in keys], [k[1] for k in keys])), shape=(g.n, g.n))
+
+
 def test_sssp_rejects_bad_input():
     g = gen.from_edges(3, [0, 1], [1, 2], [1, 1])
     with pytest.raises(ValueError):
