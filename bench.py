@@ -83,6 +83,16 @@ def algorithmic_bytes(algo, mode, sched, kind, n, prof_kind, launches):
     U = prof_kind["updates"]
     P = prof_kind["pushes"]
     per_edge = 12 if algo == "sssp" else 8
+    if sched == 4 and (algo == "sssp" or (algo == "cc" and mode == 0)):
+        # per-round push/pull (SSSP; CC in vertex mode): an edge is 12 B
+        # (SSSP) or 8 B (CC) either way -- pushed: column, weight, head
+        # value; pulled: column and tail flag, plus weight and tail value
+        # for a frontier tail -- 16 B per vertex, 10 B per push (flags and
+        # the pushed vertex's row length)
+        if kind == "round":
+            return per_edge * E + 16 * V + ((n + 63) // 64) * launches + 4 * U + 10 * P
+        if kind == "heavy":
+            return per_edge * E + 10 * P
     if algo == "cc" and sched == 4:
         D = prof_kind.get("swept_edges", 0)
         if kind == "round":
@@ -156,69 +166,79 @@ def traversed_edges(deg, dist):
     return int(deg[dist < INF].sum())
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rmat22")
-    ap.add_argument("--no-variants", action="store_true", help="skip the per-variant table")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
-    ap.add_argument("--reps", type=int, default=3, help="repeats per variant in the table")
-    ap.add_argument("--calib-copy-mib", type=int, default=0,
-                    help="first run a plain device copy of this many MiB (counter calibration)")
-    ap.add_argument("--config", default="single",
-                    choices=["single", "batched", "serve", "concurrent", "msf"])
-    ap.add_argument("--workloads", default="er16k,rmat16,rmat22",
-                    help="concurrent: workloads to run")
-    ap.add_argument("--instances", type=int, default=512, help="batched: instance count")
-    ap.add_argument("--duration", type=float, default=12.0, help="serve: trace seconds")
-    ap.add_argument("--rate", type=float, default=2000.0, help="serve: queries per second")
-    ap.add_argument("--slots", type=int, default=8, help="serve: queries in flight at most")
-    ap.add_argument("--no-plain", action="store_true", help="serve: skip the plain run")
-    ap.add_argument("--sequential", action="store_true",
-                    help="single: run a step's SSSP, BFS and CC one after the other on one "
-                         "stream (default: at the same time on three streams)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported",
-              file=sys.stderr)
-        sys.exit(2)
-    if args.config == "batched":
-        return bench_batched(args)
-    if args.config == "serve":
-        return bench_serve(args)
-    if args.config == "concurrent":
-        return bench_concurrent(args)
-    if args.config == "msf":
-        return bench_msf(args)
+SCHED_NAMES = ["sync", "async", "auto", "nearfar", "diropt"]
 
+
+def host_info():
+    """Host facts recorded with every CPU baseline."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = None
+    return {"nproc": os.cpu_count(), "cpus_allowed": allowed, "cpu_model": model}
+
+
+def copy_ceiling(torch, mib=1024, reps=20):
+    """Achievable HBM bandwidth on this device: a plain device-to-device
+    copy of 1 GiB (read + write), timed with HIP events on its stream."""
+    n = (mib << 20) // 4
+    a = torch.ones(n, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    gbps = 2 * n * 4 / (ms * 1e-3) / 1e9
+    del a, b
+    return {"GBps": round(gbps, 1), "frac_of_peak": round(gbps / HBM_PEAK_GBS, 4),
+            "bytes_per_copy": 2 * n * 4,
+            "kind": "device-to-device copy of 1 GiB (torch copy_, read + write), "
+                    f"{reps} copies timed with HIP events"}
+
+
+def variant_name(c):
+    name = ["vertex", "edge"][c.mode] + "-" + SCHED_NAMES[c.sched]
+    if c.hops:
+        name += f"-h{c.hops}"
+    if c.sched == 3 and c.far_degree:
+        name += f"-long{c.far_degree}"
+    return name
+
+
+def run_workload(name, args, *, sources_kind="random8", variants=False, cpu=True, named=None):
+    """One workload: upload, AUTO step timed (SSSP, BFS and CC in flight
+    together from this host thread), roofline of the dominant kernel from a
+    profiled repeat, optional per-variant table and named-variant latency,
+    the oracle on the host and a bit-exact check.  Returns a dict."""
     import torch
 
     from paper_1903_01665_amd import gen, gg
 
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU", file=sys.stderr)
-        sys.exit(2)
-    gg.lib()
-
-    if args.calib_copy_mib:
-        # a plain copy of known size: reading its FETCH_SIZE / WRITE_SIZE
-        # counters scales the counters of the traversal kernels
-        nbytes = args.calib_copy_mib << 20
-        a = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        log(f"[bench] calibration copy of {args.calib_copy_mib} MiB done (3 dispatches)")
-        del a, b
-
     t = time.time()
-    hg = gen.workload(args.workload)
+    hg = gen.workload(name)
     deg = hg.degrees()
-    log(f"[bench] {args.workload}: n={hg.n} m={hg.m} generated in {time.time() - t:.1f}s")
-    sources = [int(s) for s in gen.pick_sources(hg, 8, stream=gen.STREAM["sources"])]
+    log(f"[bench] {name}: n={hg.n} m={hg.m} generated in {time.time() - t:.1f}s")
+    if sources_kind == "zero":
+        sources = [0]
+    elif sources_kind == "zero+4":
+        sources = [0] + [int(x) for x in gen.pick_sources(hg, 4, stream=gen.STREAM["sources"])]
+    else:
+        sources = [int(x) for x in gen.pick_sources(hg, 8, stream=gen.STREAM["sources"])]
     t = time.time()
     g = gg.Graph.from_host(hg, symmetrize=True)
     torch.cuda.synchronize()
@@ -226,11 +246,13 @@ def main():
     # depth class for the AUTO choice (one BFS, outside the timed region)
     gclass = g.probe()
     m_sym = hg.m if hg.symmetric else 2 * hg.m
-    log(f"[bench] uploaded in {upload_s:.2f}s; class {gclass}; sources {sources}")
+    log(f"[bench] {name}: uploaded in {upload_s:.2f}s; class {gclass}; sources {sources}")
 
     outs = {a: torch.empty(hg.n, dtype=torch.int32, device="cuda") for a in ALGOS}
     auto = gg.make_opts()
     chosen = {a: g.resolve(i, auto) for i, a in enumerate(ALGOS)}
+    wss = {a: gg.Workspace(g) for a in ALGOS}
+    cur = torch.cuda.current_stream()
 
     def step_sequential(i, opts=None):
         s = sources[i % len(sources)]
@@ -238,66 +260,58 @@ def main():
         g.bfs(s, out=outs["bfs"], opts=opts)
         g.cc(out=outs["cc"], opts=opts)
 
-    # the three traversals of a step are independent: by default they run at
-    # the same time, each on its own stream with its own workspace and no
-    # barrier between them (the paper's barrier-free independent kernels,
-    # Sec. 3.2), issued from a pool of three host threads (each call blocks
-    # until its traversal ends; the calls release the interpreter lock)
-    from concurrent.futures import ThreadPoolExecutor
-    pool = ThreadPoolExecutor(max_workers=3)
-    wss = {a: gg.Workspace(g) for a in ALGOS}
-    streams = {a: torch.cuda.Stream() for a in ALGOS}
-
-    def step_concurrent(i, opts=None):
+    # the three traversals of a step are independent: they are issued from
+    # this thread with the host-asynchronous calls, each on a workspace (and
+    # so a stream) of its own, with no barrier between them (the paper's
+    # barrier-free independent kernels, Sec. 3.2); the current stream then
+    # waits for all three on the device
+    def step_async(i, opts=None):
         s = sources[i % len(sources)]
-        futs = [pool.submit(g.sssp, s, out=outs["sssp"], opts=opts, ws=wss["sssp"],
-                            stream=streams["sssp"]),
-                pool.submit(g.bfs, s, out=outs["bfs"], opts=opts, ws=wss["bfs"],
-                            stream=streams["bfs"]),
-                pool.submit(g.cc, out=outs["cc"], opts=opts, ws=wss["cc"], stream=streams["cc"])]
-        for f in futs:
-            f.result()
-        for st in streams.values():
-            torch.cuda.current_stream().wait_stream(st)
+        ts = [g.sssp_async(s, out=outs["sssp"], ws=wss["sssp"], opts=opts),
+              g.bfs_async(s, out=outs["bfs"], ws=wss["bfs"], opts=opts),
+              g.cc_async(out=outs["cc"], ws=wss["cc"], opts=opts)]
+        for tk in ts:
+            tk.stream_wait(cur)
+            tk.free()
 
-    step = step_sequential if args.sequential else step_concurrent
+    step = step_sequential if args.sequential else step_async
 
-    # traversed edges per source (from the GPU results of a warm-up pass)
+    # traversed edges per source (from the GPU results of a first pass)
     m_trav, n_reach = {}, {}
     for i, s in enumerate(sources):
         step_sequential(i)
         torch.cuda.synchronize()
-        m_trav[s] = (traversed_edges(deg, outs["sssp"].cpu().numpy()),
-                     traversed_edges(deg, outs["bfs"].cpu().numpy()))
-        n_reach[s] = int((outs["sssp"].cpu().numpy() < INF).sum())
+        d = outs["sssp"].cpu().numpy()
+        m_trav[s] = (traversed_edges(deg, d), traversed_edges(deg, outs["bfs"].cpu().numpy()))
+        n_reach[s] = int((d < INF).sum())
+    steps = args.steps
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
 
     # ------------------------------------------------------------ timed --
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(steps):
         step(i)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    edges = sum(m_trav[sources[i % len(sources)]][0] + m_trav[sources[i % len(sources)]][1]
-                + m_sym for i in range(args.steps))
+    srcs = [sources[i % len(sources)] for i in range(steps)]
+    edges = sum(m_trav[s][0] + m_trav[s][1] + m_sym for s in srcs)
     gteps = edges / elapsed / 1e9
-    log(f"[bench] {args.steps} steps in {elapsed * 1e3:.1f} ms -> {gteps:.2f} GTEPS")
+    log(f"[bench] {name}: {steps} steps in {elapsed * 1e3:.1f} ms -> {gteps:.2f} GTEPS")
     # work-efficient bytes: what one pass over the reached part needs --
     # SSSP 12 B per traversed edge + 8 B per reached vertex, BFS and CC 8 B
     # per edge + 8 B per vertex (n for CC) -- over the step time; redundant
     # relaxations and extra sweeps lower it
-    we_bytes = sum(12 * m_trav[sources[i % len(sources)]][0] + 8 * n_reach[sources[i % len(sources)]]
-                   + 8 * m_trav[sources[i % len(sources)]][1] + 8 * n_reach[sources[i % len(sources)]]
-                   + 8 * m_sym + 8 * hg.n for i in range(args.steps))
+    we_bytes = sum(12 * m_trav[s][0] + 8 * n_reach[s] + 8 * m_trav[s][1] + 8 * n_reach[s]
+                   + 8 * m_sym + 8 * hg.n for s in srcs)
     work_efficient = round(we_bytes / elapsed / 1e9 / HBM_PEAK_GBS, 4)
 
     # ----------------------------------------- profiled repeat: roofline --
     per_kernel = []
-    for i in range(args.steps):
+    for i in range(steps):
         s = sources[i % len(sources)]
-        for ai, a in enumerate(ALGOS):
+        for a in ALGOS:
             o = gg.make_opts(flags=gg.OPT_PROFILE)
             if a == "cc":
                 g.cc(out=outs[a], opts=o)
@@ -319,30 +333,28 @@ def main():
         x[2] += b
     (da, dk), (dl, dms, db) = max(agg.items(), key=lambda kv: kv[1][1])
     c = chosen[da]
-    mname = ["vertex", "edge"][c.mode] + "-" + ["sync", "async", "auto", "nearfar", "diropt"][c.sched]
-    if c.hops:
-        mname += f"-h{c.hops}"
-    if c.sched == 3 and c.far_degree:
-        mname += f"-long{c.far_degree}"
+    mname = variant_name(c)
     achieved = db / (dms * 1e-3) / 1e9
     sym = kernel_symbol(da, dk, c.mode, c.sched, c.mapping, c.hops)
-    traffic = measured_traffic(sym, args.workload)
+    traffic = measured_traffic(sym, name)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else int(traffic),
-                "traffic_unit": "bytes/launch",
+                "traffic_unit": "bytes/launch (L2-miss: FETCH_SIZE + WRITE_SIZE, copy-scaled)",
                 "kernel": f"{da} {mname} {dk} kernel", "symbol": sym, "launches": dl,
                 "avg_launch_us": round(dms * 1e3 / dl, 2),
-                "algorithmic_bytes_per_launch": int(db / dl)}
+                "algorithmic_bytes_per_launch": int(db / dl),
+                "algorithmic_bytes_total": int(db)}
     kernel_table = {f"{a}/{k}": {"launches": L, "ms": round(ms, 3),
-                                 "GBps": round(b / (ms * 1e-3) / 1e9, 1) if ms > 0 else None}
+                                 "GBps": round(b / (ms * 1e-3) / 1e9, 1) if ms > 0 else None,
+                                 "algorithmic_bytes": int(b)}
                     for (a, k), (L, ms, b) in agg.items()}
-    log(f"[bench] dominant: {roofline['kernel']} {achieved:.0f} GB/s over {dl} launches")
+    log(f"[bench] {name}: dominant {roofline['kernel']} {achieved:.0f} GB/s over {dl} launches")
 
     # ------------------------------------------------ per-variant table --
-    variants = {}
+    table = {}
     avg_w = float(hg.w.mean()) if hg.w is not None and hg.m else 1.0
-    if not args.no_variants:
+    if variants:
         s = sources[0]
         for a in ALGOS:
             for vname, (mode, sched, mp, hops, far, de) in VARIANTS.items():
@@ -367,19 +379,45 @@ def main():
                 st = g.stats()
                 tm = float(np.median(times))
                 me = m_sym if a == "cc" else m_trav[s][0 if a == "sssp" else 1]
-                variants[f"{a}/{vname}"] = {"ms": round(tm * 1e3, 3),
-                                            "p99_ms": round(float(np.percentile(times, 99)) * 1e3, 3),
-                                            "reps": len(times),
-                                            "GTEPS": round(me / tm / 1e9, 3),
-                                            "iterations": st["iterations"],
-                                            "edges_processed": st["edges_processed"]}
+                table[f"{a}/{vname}"] = {"ms": round(tm * 1e3, 3),
+                                         "p99_ms": round(float(np.percentile(times, 99)) * 1e3, 3),
+                                         "reps": len(times),
+                                         "GTEPS": round(me / tm / 1e9, 3),
+                                         "iterations": st["iterations"],
+                                         "edges_processed": st["edges_processed"]}
                 log(f"[bench] {a:4s} {vname:13s} {tm * 1e3:9.3f} ms "
                     f"{me / tm / 1e9:7.2f} GTEPS it={st['iterations']}")
 
+    # ------------------------------- named variant: per-query latency --
+    named_res = None
+    if named is not None:
+        a, mode, sched, warm, reps = named
+        o = gg.make_opts(mode, sched)
+        s = sources[0]
+        for _ in range(warm):
+            getattr(g, a)(s, out=outs[a], opts=o)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(reps):
+            t1 = time.perf_counter()
+            getattr(g, a)(s, out=outs[a], opts=o)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t1)
+        st = g.stats()
+        me = m_trav[s][0 if a == "sssp" else 1]
+        tm = float(np.median(times))
+        named_res = {"algo": a, "variant": variant_name(g.resolve(ALGOS.index(a), o)),
+                     "warmup": warm, "reps": reps, "median_ms": round(tm * 1e3, 4),
+                     "p99_ms": round(float(np.percentile(times, 99)) * 1e3, 4),
+                     "GTEPS": round(me / tm / 1e9, 4), "iterations": st["iterations"],
+                     "timing": "host clock around the call and a device synchronize"}
+        log(f"[bench] {name}: {a} {named_res['variant']} median {tm * 1e3:.4f} ms, "
+            f"p99 {named_res['p99_ms']} ms over {reps} reps")
+
     # ------------------------------------------------- CPU oracle leg --
-    cpu = None
+    cpu_res = None
     verified = None
-    if not args.no_cpu:
+    if cpu:
         import oracle
 
         s = sources[0]
@@ -391,48 +429,151 @@ def main():
         lab = oracle.cc(hg.n, hg.row_ptr, hg.col)
         t4 = time.perf_counter()
         ce = m_trav[s][0] + m_trav[s][1] + m_sym
-        cpu = {"value": round(ce / (t4 - t1) / 1e9, 4), "unit": "GTEPS", "cores": 1,
-               "kind": "oracle",
-               "sample": f"full {args.workload} graph, source {s}: Dijkstra + FIFO BFS + "
-                         f"union-find CC, one thread",
-               "seconds": {"sssp": round(t2 - t1, 3), "bfs": round(t3 - t2, 3),
-                           "cc": round(t4 - t3, 3)}}
+        cpu_res = {"value": round(ce / (t4 - t1) / 1e9, 4), "unit": "GTEPS", "cores": 1,
+                   "threads": 1, "kind": "oracle",
+                   "sample": f"full {name} graph, source {s}: Dijkstra + FIFO BFS + "
+                             f"union-find CC, one thread",
+                   "seconds": {"sssp": round(t2 - t1, 3), "bfs": round(t3 - t2, 3),
+                               "cc": round(t4 - t3, 3)},
+                   "host": host_info()}
         step(0)
         torch.cuda.synchronize()
         verified = bool(np.array_equal(outs["sssp"].cpu().numpy(), d) and
                         np.array_equal(outs["bfs"].cpu().numpy(), b) and
                         np.array_equal(outs["cc"].cpu().numpy(), lab))
-        log(f"[bench] oracle {t4 - t1:.2f}s ({cpu['value']} GTEPS); GPU results match: {verified}")
+        log(f"[bench] {name}: oracle {t4 - t1:.2f}s ({cpu_res['value']} GTEPS); "
+            f"GPU results match: {verified}")
 
-    line = {
-        "metric": "GTEPS (SSSP+BFS+CC)", "value": round(gteps, 3), "unit": "GTEPS",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(elapsed * 1e3 / args.steps, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-        "config": {"workload": args.workload, "n": hg.n, "m": hg.m, "m_sym": m_sym,
-                   "step": "sssp+bfs+cc, AUTO variants, " + (
-                       "one after the other on one stream" if args.sequential
-                       else "at the same time on three streams"),
-                   "variant": {a: {"mode": ["vertex", "edge"][chosen[a].mode],
-                                   "sched": ["sync", "async", "auto", "nearfar", "diropt"][chosen[a].sched],
-                                   "mapping": chosen[a].mapping,
-                                   "hops": chosen[a].hops,
-                                   "delta": chosen[a].delta if chosen[a].sched == 3 else 0,
-                                   "far_degree": chosen[a].far_degree} for a in ALGOS},
-                   "sources": sources, "upload_s": round(upload_s, 2),
-                   "graph_class": list(gclass),
-                   "verified_vs_oracle": verified},
-        "roofline": roofline,
-        "work_efficient_frac": work_efficient,
-        "cpu_baseline": cpu,
-        "kernels": kernel_table,
-        "variants": variants,
-    }
-    print(json.dumps(line), flush=True)
-    pool.shutdown()
     for w in wss.values():
         w.free()
     g.free()
+    res = {"workload": name, "n": hg.n, "m": hg.m, "m_sym": m_sym,
+           "GTEPS": round(gteps, 3), "steps": steps, "ms_per_step": round(elapsed * 1e3 / steps, 3),
+           "step": "sssp+bfs+cc, AUTO variants, " + (
+               "one after the other on one stream" if args.sequential
+               else "in flight together (host-asynchronous calls from one thread)"),
+           "variant": {a: {"mode": ["vertex", "edge"][chosen[a].mode],
+                           "sched": SCHED_NAMES[chosen[a].sched],
+                           "mapping": chosen[a].mapping, "hops": chosen[a].hops,
+                           "delta": chosen[a].delta if chosen[a].sched == 3 else 0,
+                           "far_degree": chosen[a].far_degree} for a in ALGOS},
+           "sources": sources, "upload_s": round(upload_s, 2), "graph_class": list(gclass),
+           "verified_vs_oracle": verified, "roofline": roofline,
+           "work_efficient_frac": work_efficient, "cpu_baseline": cpu_res,
+           "kernels": kernel_table}
+    if table:
+        res["variants"] = table
+    if named_res:
+        res["named_variant"] = named_res
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="rmat22")
+    ap.add_argument("--no-variants", action="store_true", help="skip the per-variant table")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="skip the other workloads (er16k, grid4096, er23) and the copy ceiling")
+    ap.add_argument("--reps", type=int, default=3, help="repeats per variant in the table")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--config", default="single",
+                    choices=["single", "batched", "serve", "concurrent", "msf"])
+    ap.add_argument("--workloads", default="er16k,rmat16,rmat22",
+                    help="concurrent: workloads to run")
+    ap.add_argument("--instances", type=int, default=512, help="batched: instance count")
+    ap.add_argument("--duration", type=float, default=12.0, help="serve: trace seconds")
+    ap.add_argument("--serve-warmup", type=float, default=0.0,
+                    help="serve: seconds of trace before the measured part")
+    ap.add_argument("--rate", type=float, default=2000.0, help="serve: queries per second")
+    ap.add_argument("--slots", type=int, default=8, help="serve: queries in flight at most")
+    ap.add_argument("--no-plain", action="store_true", help="serve: skip the plain run")
+    ap.add_argument("--sequential", action="store_true",
+                    help="single: run a step's SSSP, BFS and CC one after the other on one "
+                         "stream (default: in flight together)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.config == "batched":
+        return bench_batched(args)
+    if args.config == "serve":
+        return bench_serve(args)
+    if args.config == "concurrent":
+        return bench_concurrent(args)
+    if args.config == "msf":
+        return bench_msf(args)
+
+    import torch
+
+    from paper_1903_01665_amd import gg
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    gg.lib()
+
+    if args.calib_copy_mib:
+        # a plain copy of known size: reading its FETCH_SIZE / WRITE_SIZE
+        # counters scales the counters of the traversal kernels
+        nbytes = args.calib_copy_mib << 20
+        a = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {args.calib_copy_mib} MiB done (3 dispatches)")
+        del a, b
+
+    ceiling = None if args.headline_only else copy_ceiling(torch)
+    if ceiling:
+        log(f"[bench] device copy ceiling {ceiling['GBps']} GB/s")
+    head = run_workload(args.workload, args, variants=not args.no_variants,
+                        cpu=not args.no_cpu,
+                        sources_kind={"er16k": "zero", "grid4096": "zero+4",
+                                      "er23": "zero+4"}.get(args.workload, "random8"),
+                        named=("sssp", 0, 0, 5, 100) if args.workload == "er16k" else None)
+    others = {}
+    if not args.headline_only:
+        # the other configurations: C1 (its named variant, vertex-synchronous
+        # SSSP from vertex 0, 5 warm-up + 100 timed calls, beside the AUTO
+        # step), the road-like grid and the large uniform graph (source 0 and
+        # four random sources)
+        plan = [("er16k", "zero", ("sssp", 0, 0, 5, 100)), ("grid4096", "zero+4", None),
+                ("er23", "zero+4", None)]
+        for w, sk, named in plan:
+            if w == args.workload:
+                continue
+            others[w] = run_workload(w, args, sources_kind=sk, variants=False,
+                                     cpu=not args.no_cpu, named=named)
+            torch.cuda.empty_cache()
+
+    line = {
+        "metric": "GTEPS (SSSP+BFS+CC)", "value": head["GTEPS"], "unit": "GTEPS",
+        "n_gpus": 1, "steps": head["steps"], "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {k: head[k] for k in ("workload", "n", "m", "m_sym", "step", "variant",
+                                        "sources", "upload_s", "graph_class",
+                                        "verified_vs_oracle")},
+        "roofline": head["roofline"],
+        "work_efficient_frac": head["work_efficient_frac"],
+        "cpu_baseline": head["cpu_baseline"],
+        "copy_ceiling": ceiling,
+        "kernels": head["kernels"],
+    }
+    if "variants" in head:
+        line["variants"] = head["variants"]
+    if "named_variant" in head:
+        line["named_variant"] = head["named_variant"]
+    if others:
+        line["configs"] = others
+    print(json.dumps(line), flush=True)
 
 
 def common_line(args, metric, value, unit, ms_per_step, config, **extra):
@@ -450,17 +591,8 @@ def bench_batched(args):
 
     from paper_1903_01665_amd import gen, gg
 
-    rng = np.random.default_rng(gen.STREAM["batch"])
-    inst = []
     t = time.time()
-    for i in range(args.instances):
-        scale = int(rng.integers(10, 19))
-        ef = int(rng.integers(8, 33))
-        hg = gen.rmat(scale, ef << scale, stream=gen.STREAM["batch"] * 100000 + i,
-                      name=f"i{i}-rmat{scale}x{ef}")
-        algo = int(rng.integers(0, 2))
-        src = int(gen.pick_sources(hg, 1, stream=gen.STREAM["batch"] * 100000 + 50000 + i)[0])
-        inst.append((algo, hg, src))
+    inst = gen.batch_instances(args.instances)
     total_m = sum(hg.m for _, hg, _ in inst)
     log(f"[bench] {len(inst)} instances, {total_m} edges, generated in {time.time() - t:.1f}s")
 
@@ -634,7 +766,7 @@ def bench_serve(args):
     from paper_1903_01665_amd import gen, gg, serve
 
     n_pool, upload_every = 32, 5.0
-    n_up = int(args.duration // upload_every)
+    n_up = int((args.serve_warmup + args.duration) // upload_every)
     scales = serve.pool_scales(n_pool + n_up, 12, 22, gen.STREAM["serve"])
     t = time.time()
     hosts = [serve.make_graph(i, sc) for i, sc in enumerate(scales)]
@@ -647,7 +779,11 @@ def bench_serve(args):
         k = int(ti // upload_every)  # uploads done by time ti
         return list(range(min(k, n_up), n_pool + min(k, n_up)))
 
-    trace = serve.make_trace(args.rate, args.duration, graphs_at, sources, gen.STREAM["serve"])
+    # the trace covers the warm-up and the measured part; latencies count
+    # the queries that arrive after the warm-up
+    total_s = args.serve_warmup + args.duration
+    trace = serve.make_trace(args.rate, total_s, graphs_at, sources, gen.STREAM["serve"])
+    measured = trace.t >= args.serve_warmup
     # traversed edges per (graph, source)
     trav = {}
     for i, h in enumerate(hosts):
@@ -655,13 +791,14 @@ def bench_serve(args):
         trav[i] = serve.traversed_edges(g, h, sources[i])
         g.free()
     edges = sum(trav[int(gi)][int(s)] for gi, s in zip(trace.graph, trace.source))
-    log(f"[bench] trace: {len(trace.t)} queries over {args.duration}s, {edges} traversed edges")
+    log(f"[bench] trace: {len(trace.t)} queries over {total_s}s ({int(measured.sum())} after "
+        f"the {args.serve_warmup}s warm-up), {edges} traversed edges")
     svc_s = np.full(len(trace.t), np.nan)
     lat_s, st, wall_s = serve.run_served(hosts, trace, slots=args.slots,
                                          upload_every=upload_every, n_pool=n_pool, service=svc_s)
     ok = int((st == 0).sum())
-    log(f"[bench] served: wall {wall_s:.2f}s p50 {serve.percentile(lat_s, 50) * 1e3:.2f} ms "
-        f"p99 {serve.percentile(lat_s, 99) * 1e3:.2f} ms ({ok}/{len(st)} ok), "
+    log(f"[bench] served: wall {wall_s:.2f}s p50 {serve.percentile(lat_s[measured], 50) * 1e3:.2f} ms "
+        f"p99 {serve.percentile(lat_s[measured], 99) * 1e3:.2f} ms ({ok}/{len(st)} ok), "
         f"service mean {np.nanmean(svc_s) * 1e3:.3f} ms")
     svc_p = np.full(len(trace.t), np.nan)
     if args.no_plain:
@@ -669,17 +806,20 @@ def bench_serve(args):
     else:
         lat_p, wall_p = serve.run_plain(hosts, trace, n_pool=n_pool, upload_every=upload_every,
                                         service=svc_p)
-        log(f"[bench] plain: wall {wall_p:.2f}s p50 {serve.percentile(lat_p, 50) * 1e3:.2f} ms "
-            f"p99 {serve.percentile(lat_p, 99) * 1e3:.2f} ms, "
+        log(f"[bench] plain: wall {wall_p:.2f}s p50 {serve.percentile(lat_p[measured], 50) * 1e3:.2f} ms "
+            f"p99 {serve.percentile(lat_p[measured], 99) * 1e3:.2f} ms, "
             f"service mean {np.nanmean(svc_p) * 1e3:.3f} ms")
-    q = lambda x, p: round(serve.percentile(x, p) * 1e3, 3)
+    q = lambda x, p: round(serve.percentile(x[measured] if len(x) == len(measured) else x, p)
+                           * 1e3, 3)
     sv = lambda x: {"mean": round(float(np.nanmean(x)) * 1e3, 4),
                     "p50": round(float(np.nanpercentile(x, 50)) * 1e3, 4)} \
         if np.isfinite(x).any() else None
     common_line(args, "GTEPS served (Poisson SSSP/BFS queries)", edges / wall_s / 1e9, "GTEPS",
                 wall_s * 1e3 / max(1, len(trace.t)),
                 {"workload": "serve-rmat-12..22", "graphs": n_pool, "uploads": n_up,
-                 "rate_qps": args.rate, "duration_s": args.duration, "queries": len(trace.t),
+                 "rate_qps": args.rate, "duration_s": args.duration,
+                 "warmup_s": args.serve_warmup, "queries": len(trace.t),
+                 "measured_queries": int(measured.sum()),
                  "traversed_edges": edges, "slots": args.slots},
                 latency_ms={"served": {"p50": q(lat_s, 50), "p99": q(lat_s, 99)},
                             "plain": {"p50": q(lat_p, 50), "p99": q(lat_p, 99)}},

@@ -29,8 +29,16 @@
  *   - Pointers named *_dev are device pointers (hipMalloc'd memory or a torch
  *     tensor's data_ptr); every other pointer is host memory.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
- *     Traversal calls are stream-ordered and return before the work ends;
- *     the caller synchronises (stream or event) before reading results.
+ *     Traversal kernels run after the work the caller enqueued earlier on
+ *     `stream`.  A traversal takes a data-dependent number of rounds and
+ *     only the device can tell when it has ended, so the plain calls
+ *     (gg_sssp, gg_bfs, gg_cc and their _ex forms) keep the calling host
+ *     thread until the device has reported the end: the output values are
+ *     then final, while up to one batch of rounds past the end (which
+ *     return at their first instruction) may still be queued on `stream`;
+ *     work enqueued on `stream` afterwards runs after them.  The _async
+ *     forms (gg_sssp_async and below) return at once with a ticket; one host
+ *     thread can so keep several traversals in flight together.
  *   - A HIP failure is reported as GG_EHIP and recorded on the graph handle;
  *     gg_graph_error() returns the first recorded failure.
  */
@@ -76,15 +84,22 @@ typedef enum { GG_VERTEX = 0, GG_EDGE = 1, GG_MODE_AUTO = 2 } gg_mode;
  *   does; a frontier of more than n/12 vertices is pulled -- every unvisited
  *   vertex scans its in-neighbours (the DSL's innbrs iterator, Sec. 2) and
  *   stops at the first one on the level.
- *   CC (edge-based): round 0 takes one synchronous step from the ids
- *   (label = min(id, smallest neighbour id), read from the both-directions
- *   rows without atomics); later rounds sweep every stored edge (GG_SYNC's
- *   edge form) while the rows of the vertices lowered by the previous round
- *   hold more than 1/8 of the both-directions edges, then serve those
- *   vertices as a worklist (GG_ASYNC's vertex form) -- the paper's
- *   synchronous and asynchronous schedules (Sec. 3.3) chosen per round
- *   instead of per run.
- * With GG_MODE_AUTO an explicit GG_DIROPT takes the mode it runs in. */
+ *   CC: round 0 takes one synchronous step from the ids (label = min(id,
+ *   smallest neighbour id), read from the both-directions rows without
+ *   atomics); later rounds are dense while the rows of the vertices lowered
+ *   by the previous round hold more than 1/8 of the both-directions edges,
+ *   then serve those vertices as a worklist (GG_ASYNC's vertex form) -- the
+ *   paper's synchronous and asynchronous schedules (Sec. 3.3) chosen per
+ *   round instead of per run.  A dense round sweeps every stored edge with
+ *   atomics (GG_EDGE: GG_SYNC's edge form) or, vertex-based (GG_VERTEX),
+ *   lets every vertex pull the labels of its neighbours that are on the
+ *   frontier, with no atomics on rows up to the heavy threshold.
+ *   SSSP (vertex-based; needs the in-edge CSR of GG_TRANSPOSE): rounds push
+ *   the frontier as GG_ASYNC does; a round whose frontier's out-edges exceed
+ *   1/4 of the stored edges is pulled instead -- every vertex takes the
+ *   least dist[u] + w over its in-edges whose tail u is on the frontier.
+ * With GG_MODE_AUTO an explicit GG_DIROPT takes the mode it runs in (edge
+ * for CC, vertex otherwise). */
 typedef enum {
     GG_SYNC = 0,
     GG_ASYNC = 1,
@@ -106,6 +121,8 @@ typedef enum { GG_ALGO_SSSP = 0, GG_ALGO_BFS = 1, GG_ALGO_CC = 2, GG_ALGO_MSF = 
 #define GG_SYMMETRIZE 1u      /* also build the both-directions CSR needed by vertex-based CC */
 #define GG_INPUT_ON_DEVICE 2u /* row_ptr/col/w are device pointers */
 #define GG_SYMMETRIC 4u       /* the input already holds v->u for every u->v */
+#define GG_TRANSPOSE 8u       /* also build the weighted in-edge CSR that the pull rounds of
+                                 SSSP's per-round schedule read (8 bytes per edge) */
 
 typedef struct gg_graph_s* gg_graph;
 typedef struct gg_ws_s* gg_ws;
@@ -181,6 +198,11 @@ typedef struct {
     int32_t profiled; /* 0 when the last run was not profiled */
     int32_t rounds;   /* round kernels launched (including those past the end) */
     gg_kind_profile kind[GG_KINDS];
+    /* device time of the begin of the first launch and of the end of the
+     * last, in ms from one reference point per process (an event recorded
+     * by the first profiled call), so that traversals run on different
+     * streams or host threads can be placed on one time line */
+    double begin_ms, end_ms;
 } gg_profile;
 
 /* Upload a graph given in CSR: row_ptr[n+1] (row_ptr[0] == 0,
@@ -198,8 +220,9 @@ int gg_graph_upload(int32_t n, int64_t m, const int32_t* row_ptr, const int32_t*
                     const int32_t* w, uint32_t flags, void* stream, gg_graph* out);
 
 /* Free a graph and its default workspace.  Workspaces made with
- * gg_ws_create must be freed first (GG_EBUSY otherwise).  Synchronises the
- * device work of the handle before freeing. */
+ * gg_ws_create must be freed first, and no host-asynchronous traversal of
+ * the graph may be in flight (GG_EBUSY otherwise).  Synchronises the device
+ * before freeing. */
 int gg_graph_free(gg_graph g);
 
 /* Sizes and degree facts.  Any pointer may be NULL. */
@@ -229,9 +252,11 @@ int gg_cc(gg_graph g, int32_t mode, int32_t sched, int32_t* label_out_dev, void*
 /* Workspaces: per-query scratch (worklists, stamps, counters) so that
  * several traversals of one graph can be in flight on different streams.
  * A workspace serves one traversal at a time: a call on a workspace that
- * another host thread is using at that moment returns GG_EBUSY (the graph's
- * default workspace included), and a call on a workspace whose previous
- * traversal ran on another stream waits for it on the device. */
+ * another host thread is using at that moment, or that a host-asynchronous
+ * traversal holds, returns GG_EBUSY (the graph's default workspace included),
+ * and a call on a workspace whose previous traversal ran on another stream
+ * waits for it on the device.  gg_ws_free: GG_EBUSY while a traversal holds
+ * the workspace; else waits for its last traversal, then frees it. */
 int gg_ws_create(gg_graph g, gg_ws* out);
 int gg_ws_free(gg_ws ws);
 
@@ -242,6 +267,54 @@ int gg_sssp_ex(gg_graph g, gg_ws ws, int32_t source, const gg_opts* opts, int32_
 int gg_bfs_ex(gg_graph g, gg_ws ws, int32_t source, const gg_opts* opts, int32_t* dist_out_dev,
               void* stream);
 int gg_cc_ex(gg_graph g, gg_ws ws, const gg_opts* opts, int32_t* label_out_dev, void* stream);
+
+/* ---- Host-asynchronous traversals: the paper's asynchronous execution
+ * (Sec. 3.2, Algorithms 5-6) lets independent kernels -- BFS and SSSP of one
+ * graph -- run with no host barrier between them.  These forms validate the
+ * call, enqueue the init kernel and the first rounds, hand the traversal to
+ * a driver thread of the library and return at once with a ticket.  The
+ * rounds run on one of eight streams of the library (taken in turn; the
+ * first call makes them), after the work the caller enqueued on `stream`
+ * before the call and after the workspace's previous traversal; the driver
+ * thread launches the next
+ * batch of rounds of every traversal in flight as soon as the previous one
+ * completes.  Same arguments, results and errors as the _ex forms, plus:
+ *   ticket  (host, out) the handle of the traversal, freed by gg_ticket_free.
+ * The workspace (ws NULL = the graph's default one) stays taken until the
+ * traversal ends: any call on it meanwhile, gg_last_stats and gg_ws_free
+ * included, returns GG_EBUSY, and gg_graph_free returns GG_EBUSY while any
+ * traversal of the graph is in flight.  The output must not be read, and
+ * the graph not freed, before the ticket reports the end. */
+typedef struct gg_ticket_s* gg_ticket;
+
+int gg_sssp_async(gg_graph g, gg_ws ws, int32_t source, const gg_opts* opts,
+                  int32_t* dist_out_dev, void* stream, gg_ticket* ticket);
+int gg_bfs_async(gg_graph g, gg_ws ws, int32_t source, const gg_opts* opts, int32_t* dist_out_dev,
+                 void* stream, gg_ticket* ticket);
+int gg_cc_async(gg_graph g, gg_ws ws, const gg_opts* opts, int32_t* label_out_dev, void* stream,
+                gg_ticket* ticket);
+
+/* GG_EBUSY while the traversal runs; once every kernel of it has completed,
+ * its status (GG_OK, GG_ETIMEOUT, GG_EITER or a HIP failure).  Never blocks. */
+int gg_ticket_query(gg_ticket t);
+
+/* Block the host until every kernel of the traversal has completed; returns
+ * its status as gg_ticket_query does. */
+int gg_ticket_wait(gg_ticket t);
+
+/* Make `stream` wait on the device for the traversal's last kernel.  The
+ * host blocks only until the driver has seen the end (the device work past
+ * it is waited for by `stream`, not by the host).  Returns the status. */
+int gg_ticket_stream_wait(gg_ticket t, void* stream);
+
+/* Device times of the traversal in milliseconds, measured from the begin of
+ * traversal `ref` (NULL = t itself): begin (before its init kernel) and end
+ * (after its last round); rounds launched.  Waits for both traversals.  Any
+ * output pointer may be NULL. */
+int gg_ticket_times(gg_ticket t, gg_ticket ref, float* begin_ms, float* end_ms, int32_t* rounds);
+
+/* Release a ticket (waits for the traversal first if it still runs). */
+int gg_ticket_free(gg_ticket t);
 
 /* Minimum spanning forest (MST is the fourth algorithm of Sec. 4.1, Table 3;
  * the DSL's Set type is a union-find structure, Sec. 2).  Every stored edge e
@@ -262,11 +335,13 @@ int gg_msf(gg_graph g, gg_ws ws, uint8_t* in_msf_dev, int64_t* total_weight, int
 
 /* Statistics of the last traversal on a workspace (NULL = default).  Waits
  * for that traversal to finish.  Returns the traversal's device-side status
- * (GG_ETIMEOUT, GG_EITER) if it failed, GG_OK otherwise. */
+ * (GG_ETIMEOUT, GG_EITER) if it failed, GG_OK otherwise; GG_EBUSY while a
+ * traversal holds the workspace. */
 int gg_last_stats(gg_graph g, gg_ws ws, gg_stats* out);
 
 /* Timing of the last traversal on a workspace (NULL = default) run with
- * GG_OPT_PROFILE.  Waits for the traversal to finish. */
+ * GG_OPT_PROFILE.  Waits for the traversal to finish; GG_EBUSY while a
+ * traversal holds the workspace. */
 int gg_last_profile(gg_graph g, gg_ws ws, gg_profile* out);
 
 /* Resolve AUTO fields of opts for an algorithm on this graph, as a call
@@ -411,15 +486,22 @@ int gg_server_create(int32_t slots, int64_t mem_budget_bytes, gg_server* out);
 int gg_server_add_graph(gg_server s, gg_graph g, int32_t* graph_id);
 
 /* Retire a graph: later submissions to it fail; queries already queued or
- * in flight finish.  Its memory is released by gg_server_free (releasing
- * device memory while other queries run would synchronise the device). */
+ * in flight finish.  Its memory (graph and pooled workspaces) is released
+ * by the driver thread once none of its queries is left and the server has
+ * no query in flight (releasing device memory waits for the whole device),
+ * or by gg_server_free. */
 int gg_server_remove_graph(gg_server s, int32_t graph_id);
 
 /* Queue a query.  out_dev: caller-owned device int32[n] of that graph,
- * written by the traversal (readable once the query is reported done).
- * GG_EINVAL for an unknown or retiring graph, a bad algorithm or source. */
+ * written by the traversal (readable once the query is reported done; the
+ * caller keeps it allocated until then).  stream: the query's kernels run
+ * after the work enqueued on it before this call (an event recorded there),
+ * so the caller may prepare out_dev on its stream.  GG_EINVAL for an
+ * unknown or retiring graph, a bad algorithm or source.  With a memory
+ * budget, the workspaces kept for reuse count against it too: idle ones of
+ * other graphs are freed when a new one would not fit. */
 int gg_server_submit(gg_server s, int32_t graph_id, int32_t algo, int32_t source,
-                     int32_t* out_dev, int64_t* query_id);
+                     int32_t* out_dev, void* stream, int64_t* query_id);
 
 /* Copies up to `cap` newly finished queries to results and their count to
  * *n_done.  Never blocks on the device. */

@@ -30,7 +30,7 @@ using namespace gg;
 
 namespace {
 
-// Heavy-row chunks of a CSR held on the host.
+// Heavy-row chunks of a CSR held on the host, in row order.
 std::vector<int2> build_chunks(const std::vector<int>& row, int n, int heavy, int chunk) {
     std::vector<int2> out;
     for (int v = 0; v < n; ++v) {
@@ -111,62 +111,137 @@ int make_ws(gg_graph g, gg_ws_s** out) {
     return GG_OK;
 }
 
+// Upload checks of host edge arrays, split over host threads: every column
+// in [0, n), every weight >= 0; the largest weight and the weight sum.
+struct HostCheck {
+    bool ok = true;
+    int max_w = 0;
+    long long wsum = 0;
+};
+
+HostCheck check_host(const int* col, const int* w, long long m, int n) {
+    const int nt = (int)std::max(1LL, std::min<long long>(
+                            std::min<long long>(16, std::thread::hardware_concurrency()),
+                            m / (1 << 20) + 1));
+    std::vector<HostCheck> part((size_t)nt);
+    auto work = [&](int t) {
+        HostCheck& r = part[(size_t)t];
+        const long long e0 = m * t / nt, e1 = m * (t + 1) / nt;
+        for (long long e = e0; e < e1; ++e)
+            if ((unsigned)col[e] >= (unsigned)n) r.ok = false;
+        if (w)
+            for (long long e = e0; e < e1; ++e) {
+                const int x = w[e];
+                if (x < 0) r.ok = false;
+                r.max_w = std::max(r.max_w, x);
+                r.wsum += x;
+            }
+    };
+    std::vector<std::thread> th;
+    for (int t = 1; t < nt; ++t) {
+        try {
+            th.emplace_back(work, t);
+        } catch (...) {
+            work(t);  // no thread: check the part here
+        }
+    }
+    work(0);
+    for (auto& x : th) x.join();
+    HostCheck r;
+    for (const HostCheck& x : part) {
+        r.ok = r.ok && x.ok;
+        r.max_w = std::max(r.max_w, x.max_w);
+        r.wsum += x.wsum;
+    }
+    return r;
+}
+
 // Graphs with fewer edges keep the single edge list for the edge sweep.
 constexpr long long kPartMinEdges = 1LL << 20;
 
 // The edge list again, cut into kXcd parts by head vertex with equal edge
 // counts (part boundaries at the in-degree quantiles), CSR order kept inside
 // a part, each part padded to a multiple of 4 edges with the self-loop 0->0
-// of weight 0 (it never changes a value).
-int build_parts(gg_graph g, const std::vector<int>& hrow, const int* col, const int* w,
-                hipStream_t s) {
+// of weight 0 (it never changes a value).  The split runs on the device
+// (per-block counts per part, bases from their prefix sums on the host, then
+// a stable placement); hin holds the in-degrees.
+int build_parts(gg_graph g, const std::vector<int>& hin, hipStream_t s) {
     const int n = g->n;
     const long long m = g->m;
-    std::vector<long long> cum((size_t)n + 1, 0);
-    for (long long e = 0; e < m; ++e) cum[(size_t)col[e] + 1]++;
-    for (int v = 0; v < n; ++v) cum[v + 1] += cum[v];
     std::vector<unsigned char> part((size_t)n);
+    long long cum = 0;
     int p = 0;
     for (int v = 0; v < n; ++v) {
-        while (p < kXcd - 1 && cum[v] >= (long long)(p + 1) * m / kXcd) ++p;
+        while (p < kXcd - 1 && cum >= (long long)(p + 1) * m / kXcd) ++p;
         part[v] = (unsigned char)p;
+        cum += hin[v];
     }
+    const int nb = split_blocks(m);
+    unsigned char* dpart = nullptr;
+    int* dcounts = nullptr;
+    long long* dbase = nullptr;
+    std::vector<int> counts((size_t)nb * kXcd);
+    auto done = [&](int rc) {
+        dfree(dpart);
+        dfree(dcounts);
+        dfree(dbase);
+        return rc;
+    };
+    hipError_t e = dalloc(&dpart, (size_t)n);
+    if (e == hipSuccess) e = dalloc(&dcounts, counts.size());
+    if (e == hipSuccess) e = hipMemcpyAsync(dpart, part.data(), (size_t)n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_split_count(g->col, (int)m, dpart, dcounts, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(counts.data(), dcounts, sizeof(int) * counts.size(),
+                           hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return done(e == hipErrorOutOfMemory ? GG_ENOMEM : GG_EHIP);
     long long cnt[kXcd] = {};
-    for (long long e = 0; e < m; ++e) cnt[part[col[e]]]++;
+    for (int b = 0; b < nb; ++b)
+        for (int k = 0; k < kXcd; ++k) cnt[k] += counts[(size_t)b * kXcd + k];
     long long off[kXcd + 1];
     off[0] = 0;
     for (int k = 0; k < kXcd; ++k) off[k + 1] = off[k] + ((cnt[k] + 3) & ~3LL);
     const long long mp = off[kXcd];
-    if (mp >= (1LL << 31)) return GG_OK;  // keep the single list
-    std::vector<int> ps((size_t)mp, 0), pc((size_t)mp, 0), pwv(w ? (size_t)mp : 0, 0);
-    long long cur[kXcd];
-    for (int k = 0; k < kXcd; ++k) cur[k] = off[k];
-    for (int u = 0; u < n; ++u)
-        for (int e = hrow[u]; e < hrow[u + 1]; ++e) {
-            const long long at = cur[part[col[e]]]++;
-            ps[at] = u;
-            pc[at] = col[e];
-            if (w) pwv[at] = w[e];
+    if (mp >= (1LL << 31)) return done(GG_OK);  // keep the single list
+    std::vector<long long> base((size_t)nb * kXcd);
+    long long run[kXcd];
+    for (int k = 0; k < kXcd; ++k) run[k] = off[k];
+    for (int b = 0; b < nb; ++b)
+        for (int k = 0; k < kXcd; ++k) {
+            base[(size_t)b * kXcd + k] = run[k];
+            run[k] += counts[(size_t)b * kXcd + k];
         }
-    hipError_t e = dalloc(&g->psrc, (size_t)mp);
+    e = dalloc(&dbase, base.size());
+    if (e == hipSuccess) e = dalloc(&g->psrc, (size_t)mp);
     if (e == hipSuccess) e = dalloc(&g->pcol, (size_t)mp);
-    if (e == hipSuccess && w) e = dalloc(&g->pw, (size_t)mp);
-    if (e == hipSuccess) e = hipMemcpyAsync(g->psrc, ps.data(), sizeof(int) * mp, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(g->pcol, pc.data(), sizeof(int) * mp, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess && w)
-        e = hipMemcpyAsync(g->pw, pwv.data(), sizeof(int) * mp, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && g->w) e = dalloc(&g->pw, (size_t)mp);
+    // the padding edges are the zero self-loop 0->0
+    if (e == hipSuccess) e = hipMemsetAsync(g->psrc, 0, sizeof(int) * mp, s);
+    if (e == hipSuccess) e = hipMemsetAsync(g->pcol, 0, sizeof(int) * mp, s);
+    if (e == hipSuccess && g->w) e = hipMemsetAsync(g->pw, 0, sizeof(int) * mp, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dbase, base.data(), sizeof(long long) * base.size(),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = launch_split_place(g->src, g->col, g->w, (int)m, dpart, dbase, g->psrc, g->pcol,
+                               g->pw, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         dfree(g->psrc);
         dfree(g->pcol);
         dfree(g->pw);
-        return e == hipErrorOutOfMemory ? GG_ENOMEM : GG_EHIP;
+        return done(e == hipErrorOutOfMemory ? GG_ENOMEM : GG_EHIP);
     }
     for (int k = 0; k <= kXcd; ++k) g->poff[k] = (int)off[k];
-    return GG_OK;
+    return done(GG_OK);
 }
 
 void free_graph_arrays(gg_graph g) {
+    dfree(g->trow);
+    dfree(g->tcol);
+    dfree(g->tw);
+    dfree(g->tchunks);
     dfree(g->psrc);
     dfree(g->pcol);
     dfree(g->pw);
@@ -205,15 +280,24 @@ DevGraph dev_graph(gg_graph g) {
     d.pcol = g->pcol;
     d.pw = g->pw;
     for (int k = 0; k <= kXcd; ++k) d.poff[k] = g->poff[k];
+    d.trow = g->trow;
+    d.tcol = g->tcol;
+    d.tw = g->tw;
+    d.tchunks = g->tchunks;
+    d.n_tchunks = g->n_tchunks;
     return d;
 }
 
 // The per-round dense/sparse schedule: BFS vertex-based (pull over
-// in-neighbours), CC edge-based (sweeps, then the worklist); both read the
-// both-directions CSR.
+// in-neighbours), CC edge-based (dense rounds sweep the stored edges) or
+// vertex-based (dense rounds pull over the both-directions rows) -- these
+// read the both-directions CSR -- and SSSP vertex-based (dense rounds pull
+// over the weighted in-edge CSR).
 bool diropt_ok(gg_graph g, int algo, int mode) {
+    if (algo == GG_ALGO_SSSP) return mode == GG_VERTEX && g->trow != nullptr;
     if (!g->has_sym) return false;
-    return (algo == GG_ALGO_BFS && mode == GG_VERTEX) || (algo == GG_ALGO_CC && mode == GG_EDGE);
+    return (algo == GG_ALGO_BFS && mode == GG_VERTEX) ||
+           (algo == GG_ALGO_CC && (mode == GG_EDGE || mode == GG_VERTEX));
 }
 
 // AUTO fields resolve through the tuning table (else built-in rules) for
@@ -250,8 +334,13 @@ void resolve(gg_graph g, int algo, const gg_opts* in, gg_opts* out) {
     if (auto_map) o.mapping = tp;
     // bucket width of the near-far schedule: explicit, else the table's
     // eighths of the mean weight, else 4 mean weights
-    if (o.sched == GG_NEARFAR && o.delta <= 0)
-        o.delta = std::max(1, (int)((te > 0 ? te : 32) * g->avg_w / 8));
+    // (computed in double and capped at 2^30 before the conversion: with
+    // weights near 2^31 the product passes the int range, and the bound
+    // saturates at INF long before a width of 2^30 matters)
+    if (o.sched == GG_NEARFAR && o.delta <= 0) {
+        const double d = (te > 0 ? te : 32) * g->avg_w / 8.0;
+        o.delta = d >= (double)(1 << 30) ? (1 << 30) : std::max(1, (int)d);
+    }
     // a choice taken from the table must be one this graph can run
     if (auto_sched && o.sched == GG_DIROPT && !diropt_ok(g, algo, o.mode)) {
         o.sched = algo == GG_ALGO_CC ? GG_SYNC : GG_ASYNC;
@@ -322,7 +411,8 @@ int plan_make(gg_graph g, gg_ws ws, int algo, int source, const int* sources_dev
     // default bucket width: a few mean weights (one bucket then spans paths
     // of several light edges)
     R.delta = nearfar ? std::max(1, o.delta) : 0;
-    R.fedges = p.cc && diropt;
+    R.fedges = diropt && (p.cc || algo == GG_ALGO_SSSP);
+    R.pullmode = diropt && (algo == GG_ALGO_SSSP || (p.cc && o.mode == GG_VERTEX));
     R.hops = p.async && !p.edge && !diropt && o.mapping == GG_MAP_BALANCED ? o.hops : 0;
     R.far_degree = nearfar ? o.far_degree : 0;
 
@@ -341,17 +431,30 @@ int plan_make(gg_graph g, gg_ws ws, int algo, int source, const int* sources_dev
         p.g_round = grid((g->m / 4 + kBlock - 1) / kBlock);
     } else if (diropt && p.cc) {
         p.g_round = grid(std::max(ngroups * kParts / wpb + 1, (g->m / 4 + kBlock - 1) / kBlock));
+    } else if (diropt && algo == GG_ALGO_SSSP) {
+        p.g_round = grid(std::max(ngroups * kParts, ntiles + g->n_tchunks) / wpb + 1);
     } else if (diropt) {
         p.g_round = grid(std::max(ngroups * kParts, ntiles) / wpb + 1);
     } else {
         p.g_round = grid((ngroups * kParts + wpb - 1) / wpb);
     }
     p.need_heavy = p.async && (p.edge || diropt || o.mapping == GG_MAP_BALANCED) && nh > 0;
+    // the heavy kernel of an SSSP pull round clears the frontier it read
+    if (diropt && algo == GG_ALGO_SSSP) p.need_heavy = true;
     p.g_heavy = grid((nh + 64LL * wpb - 1) / (64LL * wpb));
+    if (diropt && algo == GG_ALGO_SSSP)  // enough blocks to clear the flags quickly
+        p.g_heavy = std::max(p.g_heavy, grid((ngroups * 256 + kBlock - 1) / kBlock));
     p.need_jump = p.cc && p.edge && (!p.async || diropt) && R.jump;
+    // ... and the shortcut kernel of a CC pull round
+    if (diropt && p.cc && R.pullmode) p.need_jump = true;
     p.g_jump = grid((n + kBlock - 1) / kBlock);
     return GG_OK;
 }
+
+// Reference point of the profiled time line: an event recorded on the
+// stream of the first profiled call of the process.
+hipEvent_t g_time_ref = nullptr;
+std::once_flag g_time_ref_once;
 
 // Every launch goes through here so that profiling can bracket it.
 template <class F>
@@ -359,6 +462,13 @@ hipError_t plan_launch(Plan& p, int kind, F&& fn) {
     gg_ws ws = p.ws;
     if (!p.prof) return fn();
     hipError_t e = hipSuccess;
+    std::call_once(g_time_ref_once, [&] {
+        if (hipEventCreate(&g_time_ref) == hipSuccess &&
+            hipEventRecord(g_time_ref, p.s) != hipSuccess) {
+            (void)hipEventDestroy(g_time_ref);
+            g_time_ref = nullptr;
+        }
+    });
     const int i = ws->nlaunch;
     while ((int)ws->pev.size() < 2 * (i + 1)) {
         hipEvent_t ev;
@@ -394,6 +504,7 @@ hipError_t plan_round(Plan& p, int r, int stamp) {
     R.stamp = stamp;
     hipError_t e = plan_launch(p, KIND_ROUND, [&] {
         if (p.diropt && p.cc) return launch_cc_diropt(R, p.g_round, kBlock, p.s);
+        if (p.diropt && p.algo == GG_ALGO_SSSP) return launch_sssp_diropt(R, p.g_round, kBlock, p.s);
         if (p.diropt) return launch_bfs_diropt(R, p.g_round, kBlock, p.s);
         if (!p.async && !p.edge) return launch_vsync(R, p.algo, p.g_round, kBlock, p.s);
         if (!p.async) return launch_esync(R, p.algo, p.g_round, kBlock, p.s);
@@ -448,6 +559,7 @@ int drive_start(Drive& d, long long r0, int stamp_base, int tag) {
     d.t0 = std::chrono::steady_clock::now();
     d.status = GG_OK;
     d.finished = false;
+    d.stopping = false;
     // two batches in flight from the start
     for (int i = 0; i < 2; ++i) {
         int rc = drive_enqueue(d);
@@ -486,6 +598,14 @@ int drive_step(Drive& d, bool block) {
             d.finished = true;
             return 1;
         }
+        if (d.stopping) {
+            // out of rounds or time: the newer batch must complete before the
+            // status is final (checked on later steps, never waited for here)
+            if (!completed((d.k + 1) & 1)) return 0;
+            if (!reported()) d.status = d.stop_status;
+            d.finished = true;
+            return 1;
+        }
         if (!completed(d.k & 1)) return 0;
     } else if (block) {
         HIPCHK(p.g, hipEventSynchronize(ws->ev[d.k & 1]));
@@ -501,12 +621,15 @@ int drive_step(Drive& d, bool block) {
     const long long ms = std::chrono::duration_cast<std::chrono::milliseconds>(
                              std::chrono::steady_clock::now() - d.t0).count();
     if (d.r >= d.max_rounds || ms > p.o.time_limit_ms) {
+        const int st = d.r >= d.max_rounds ? GG_EITER : GG_ETIMEOUT;
         if (d.poll) {
-            while (!completed((d.k + 1) & 1)) std::this_thread::yield();
+            d.stopping = true;
+            d.stop_status = st;
+            if (!completed((d.k + 1) & 1)) return 0;
         } else {
             HIPCHK(p.g, hipEventSynchronize(ws->ev[(d.k + 1) & 1]));
         }
-        if (!reported()) d.status = d.r >= d.max_rounds ? GG_EITER : GG_ETIMEOUT;
+        if (!reported()) d.status = st;
         d.finished = true;
         return 1;
     }
@@ -618,8 +741,7 @@ int gg_graph_upload(int32_t n, int64_t m, const int32_t* row_ptr, const int32_t*
         std::memcpy(hrow.data(), row_ptr, sizeof(int) * ((size_t)n + 1));
     }
     if (hrow[0] != 0 || hrow[n] != m) return GG_EINVAL;
-    int max_deg = 0, argmax_deg = 0, max_w = 0;
-    double avg_w = 0;
+    int max_deg = 0, argmax_deg = 0;
     for (int v = 0; v < n; ++v) {
         if (hrow[v + 1] < hrow[v]) return GG_EINVAL;
         if (hrow[v + 1] - hrow[v] > max_deg) {
@@ -627,18 +749,11 @@ int gg_graph_upload(int32_t n, int64_t m, const int32_t* row_ptr, const int32_t*
             argmax_deg = v;
         }
     }
-    if (!on_dev) {
-        for (long long e = 0; e < m; ++e)
-            if (col[e] < 0 || col[e] >= n) return GG_EINVAL;
-        if (w) {
-            double sum = 0;
-            for (long long e = 0; e < m; ++e) {
-                if (w[e] < 0) return GG_EINVAL;
-                sum += w[e];
-                max_w = std::max(max_w, (int)w[e]);
-            }
-            avg_w = m ? sum / (double)m : 0.0;
-        }
+    // host input: checked on the host (before any device work), in parallel
+    HostCheck hc;
+    if (!on_dev && m > 0) {
+        hc = check_host(col, w, m, n);
+        if (!hc.ok) return GG_EINVAL;
     }
     gg_graph g = new (std::nothrow) gg_graph_s();
     if (!g) return GG_ENOMEM;
@@ -648,55 +763,72 @@ int gg_graph_upload(int32_t n, int64_t m, const int32_t* row_ptr, const int32_t*
     g->argmax_deg = argmax_deg;
     g->heavy = (double)max_deg >= 128.0 * ((double)m / (double)n) && m > 0 ? kHeavySkewed
                                                                             : kHeavyUniform;
-    g->avg_w = avg_w;
-    g->max_w = max_w;
     g->weighted = w != nullptr;
+    if (!on_dev && w && m > 0) {
+        g->max_w = hc.max_w;
+        g->avg_w = (double)hc.wsum / (double)m;
+    }
     const hipMemcpyKind kind = on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    int* tmp = nullptr;  // in-degrees / fill cursors, and the check's statistics
     auto bail = [&](int code) {
         (void)hipStreamSynchronize(s);
+        dfree(tmp);
         free_graph_arrays(g);
         delete g;
         return code;
+    };
+    auto grid = [&](long long units) {
+        return (int)std::max(1LL, std::min<long long>(units, device().max_blocks));
     };
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = dalloc(&g->row, (size_t)n + 1);
     if (e == hipSuccess) e = dalloc(&g->col, (size_t)m);
     if (e == hipSuccess && w) e = dalloc(&g->w, (size_t)m);
     if (e == hipSuccess) e = dalloc(&g->src, (size_t)m);
+    if (e == hipSuccess) e = dalloc(&tmp, (size_t)n + 8);
     if (e == hipSuccess) e = hipMemcpyAsync(g->row, hrow.data(), sizeof(int) * ((size_t)n + 1),
                                             hipMemcpyHostToDevice, s);
     if (e == hipSuccess && m) e = hipMemcpyAsync(g->col, col, sizeof(int) * m, kind, s);
     if (e == hipSuccess && m && w) e = hipMemcpyAsync(g->w, w, sizeof(int) * m, kind, s);
-    auto grid = [&](long long units) {
-        return (int)std::max(1LL, std::min<long long>(units, device().max_blocks));
-    };
-    if (e == hipSuccess)
-        e = launch_fill_src(g->row, n, (int)m, g->src, grid((m + 4095) / 4096), kBlock, s);
     if (e != hipSuccess) return bail(e == hipErrorOutOfMemory ? GG_ENOMEM : GG_EHIP);
-    if (on_dev) {
-        // validate device input on the host after copying it back
-        std::vector<int> hc((size_t)m), hw(w ? (size_t)m : 0);
-        if (m && hipMemcpy(hc.data(), g->col, sizeof(int) * m, hipMemcpyDeviceToHost) != hipSuccess)
-            return bail(GG_EHIP);
-        for (long long i = 0; i < m; ++i)
-            if (hc[i] < 0 || hc[i] >= n) return bail(GG_EINVAL);
+    // device input: column range, weight sign, largest weight and weight
+    // sum, checked on the device
+    if (on_dev && m > 0) {
+        int st[8] = {INT32_MAX, INT32_MIN, INT32_MAX, INT32_MIN, 0, 0, 0, 0};
+        unsigned long long* dsum = reinterpret_cast<unsigned long long*>(tmp + 4);
+        e = hipMemcpyAsync(tmp, st, sizeof(st), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = launch_check(g->col, g->w, (int)m, tmp, dsum, grid((m + 4095) / 4096), s);
+        if (e == hipSuccess) e = hipMemcpyAsync(st, tmp, sizeof(st), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return bail(GG_EHIP);
+        if (st[0] < 0 || st[1] >= n) return bail(GG_EINVAL);
         if (w) {
-            if (m && hipMemcpy(hw.data(), g->w, sizeof(int) * m, hipMemcpyDeviceToHost) != hipSuccess)
-                return bail(GG_EHIP);
-            double sum = 0;
-            for (long long i = 0; i < m; ++i) {
-                if (hw[i] < 0) return bail(GG_EINVAL);
-                sum += hw[i];
-                g->max_w = std::max(g->max_w, (int)hw[i]);
-            }
-            g->avg_w = m ? sum / (double)m : 0.0;
+            if (st[2] < 0) return bail(GG_EINVAL);
+            unsigned long long sum = 0;
+            std::memcpy(&sum, st + 4, sizeof(sum));
+            g->max_w = st[3];
+            g->avg_w = (double)sum / (double)m;
         }
-        if (m >= kPartMinEdges) {
-            const int rc = build_parts(g, hrow, hc.data(), w ? hw.data() : nullptr, s);
-            if (rc != GG_OK) return bail(rc);
-        }
-    } else if (m >= kPartMinEdges) {
-        const int rc = build_parts(g, hrow, col, w, s);
+    }
+    e = launch_fill_src(g->row, n, (int)m, g->src, grid((m + 4095) / 4096), kBlock, s);
+    if (e != hipSuccess) return bail(GG_EHIP);
+    // in-degrees, counted once for the head-partitioned edge list, the
+    // both-directions CSR and the in-edge CSR
+    const bool sym_build = (flags & GG_SYMMETRIZE) && !(flags & GG_SYMMETRIC);
+    std::vector<int> hin;
+    if (m > 0 && (m >= kPartMinEdges || sym_build || (flags & GG_TRANSPOSE))) {
+        hin.resize((size_t)n);
+        e = hipMemsetAsync(tmp, 0, sizeof(int) * n, s);
+        if (e == hipSuccess)
+            e = launch_count_in(g->col, (int)m, tmp, grid((m + kBlock - 1) / kBlock), kBlock, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(hin.data(), tmp, sizeof(int) * n, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return bail(GG_EHIP);
+    }
+    if (m >= kPartMinEdges) {
+        const int rc = build_parts(g, hin, s);
         if (rc != GG_OK) return bail(rc);
     }
     std::vector<int2> hch = build_chunks(hrow, n, g->heavy, g->chunk);
@@ -727,35 +859,23 @@ int gg_graph_upload(int32_t n, int64_t m, const int32_t* row_ptr, const int32_t*
     } else if (flags & GG_SYMMETRIZE) {
         const long long ms = 2 * m;
         if (ms >= (1LL << 31)) return bail(GG_EINVAL);
-        int* indeg = nullptr;
-        e = dalloc(&indeg, (size_t)n);
-        if (e == hipSuccess) e = hipMemsetAsync(indeg, 0, sizeof(int) * n, s);
-        if (e == hipSuccess && m)
-            e = launch_count_in(g->col, (int)m, indeg, grid((m + kBlock - 1) / kBlock), kBlock, s);
-        std::vector<int> hin((size_t)n), hsrow((size_t)n + 1);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(hin.data(), indeg, sizeof(int) * n, hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) {
-            dfree(indeg);
-            return bail(GG_EHIP);
-        }
+        std::vector<int> hsrow((size_t)n + 1);
         hsrow[0] = 0;
-        for (int v = 0; v < n; ++v) hsrow[v + 1] = hsrow[v] + (hrow[v + 1] - hrow[v]) + hin[v];
+        for (int v = 0; v < n; ++v)
+            hsrow[v + 1] = hsrow[v] + (hrow[v + 1] - hrow[v]) + (m > 0 ? hin[v] : 0);
         if (e == hipSuccess) e = dalloc(&g->srow, (size_t)n + 1);
         if (e == hipSuccess) e = dalloc(&g->scol, (size_t)ms);
         if (e == hipSuccess) e = dalloc(&g->ssrc, (size_t)ms);
         if (e == hipSuccess)
             e = hipMemcpyAsync(g->srow, hsrow.data(), sizeof(int) * ((size_t)n + 1),
                                hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = hipMemsetAsync(indeg, 0, sizeof(int) * n, s);
+        if (e == hipSuccess) e = hipMemsetAsync(tmp, 0, sizeof(int) * n, s);
         if (e == hipSuccess && m)
-            e = launch_sym_fill(g->row, g->col, g->src, n, (int)m, g->srow, indeg, g->scol,
+            e = launch_sym_fill(g->row, g->col, g->src, n, (int)m, g->srow, tmp, g->scol,
                                 grid((m + kBlock - 1) / kBlock), kBlock, s);
         if (e == hipSuccess)
             e = launch_fill_src(g->srow, n, (int)ms, g->ssrc, grid((ms + 4095) / 4096), kBlock, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
-        dfree(indeg);
         if (e != hipSuccess) return bail(e == hipErrorOutOfMemory ? GG_ENOMEM : GG_EHIP);
         g->has_sym = true;
         g->ms = ms;
@@ -769,8 +889,37 @@ int gg_graph_upload(int32_t n, int64_t m, const int32_t* row_ptr, const int32_t*
             if (e != hipSuccess) return bail(GG_EHIP);
         }
     }
+    if ((flags & GG_TRANSPOSE) && m > 0) {
+        // weighted in-edge CSR: prefix sums of the in-degrees on the host,
+        // then every edge placed in its head's row
+        std::vector<int> htrow((size_t)n + 1);
+        htrow[0] = 0;
+        for (int v = 0; v < n; ++v) htrow[v + 1] = htrow[v] + hin[v];
+        if (e == hipSuccess) e = dalloc(&g->trow, (size_t)n + 1);
+        if (e == hipSuccess) e = dalloc(&g->tcol, (size_t)m);
+        if (e == hipSuccess) e = dalloc(&g->tw, (size_t)m);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(g->trow, htrow.data(), sizeof(int) * ((size_t)n + 1),
+                               hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemsetAsync(tmp, 0, sizeof(int) * n, s);
+        if (e == hipSuccess)
+            e = launch_t_fill(g->col, g->w, g->src, (int)m, g->trow, tmp, g->tcol, g->tw,
+                              grid((m + kBlock - 1) / kBlock), kBlock, s);
+        std::vector<int2> tch;
+        if (e == hipSuccess) tch = build_chunks(htrow, n, g->heavy, g->chunk);
+        g->n_tchunks = (int)tch.size();
+        if (e == hipSuccess && !tch.empty()) {
+            e = dalloc(&g->tchunks, tch.size());
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(g->tchunks, tch.data(), sizeof(int2) * tch.size(),
+                                   hipMemcpyHostToDevice, s);
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return bail(e == hipErrorOutOfMemory ? GG_ENOMEM : GG_EHIP);
+    }
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return bail(GG_EHIP);
+    dfree(tmp);
     int rc = make_ws(g, &g->ws0);
     if (rc != GG_OK) return bail(rc);
     g->ws0->is_default = true;
@@ -780,7 +929,7 @@ int gg_graph_upload(int32_t n, int64_t m, const int32_t* row_ptr, const int32_t*
 
 int gg_graph_free(gg_graph g) {
     if (!g) return GG_EINVAL;
-    if (g->n_ws > 0) return GG_EBUSY;
+    if (g->n_ws > 0 || g->n_async.load() > 0) return GG_EBUSY;
     (void)hipDeviceSynchronize();
     free_ws_arrays(g->ws0);
     delete g->ws0;
@@ -814,6 +963,7 @@ int gg_ws_create(gg_graph g, gg_ws* out) {
 
 int gg_ws_free(gg_ws ws) {
     if (!ws || ws->is_default) return GG_EINVAL;
+    if (ws->busy.load()) return GG_EBUSY;
     if (ws->used) (void)hipEventSynchronize(ws->finished);
     ws->owner->n_ws--;
     free_ws_arrays(ws);
@@ -862,6 +1012,7 @@ int gg_last_stats(gg_graph g, gg_ws ws, gg_stats* out) {
     if (!g || !out) return GG_EINVAL;
     if (!ws) ws = g->ws0;
     if (ws->owner != g) return GG_EINVAL;
+    if (ws->busy.load()) return GG_EBUSY;
     if (!ws->used) {
         *out = gg_stats{};
         return GG_OK;
@@ -888,6 +1039,7 @@ int gg_last_profile(gg_graph g, gg_ws ws, gg_profile* out) {
     if (!g || !out) return GG_EINVAL;
     if (!ws) ws = g->ws0;
     if (ws->owner != g) return GG_EINVAL;
+    if (ws->busy.load()) return GG_EBUSY;
     *out = gg_profile{};
     if (!ws->used || !ws->profiled) return GG_OK;
     HIPCHK(g, hipEventSynchronize(ws->finished));
@@ -896,6 +1048,13 @@ int gg_last_profile(gg_graph g, gg_ws ws, gg_profile* out) {
                         hipMemcpyDeviceToHost));
     out->profiled = 1;
     out->rounds = ws->rounds;
+    if (g_time_ref && ws->nlaunch > 0) {
+        float b = 0.f, e = 0.f;
+        HIPCHK(g, hipEventElapsedTime(&b, g_time_ref, ws->pev[0]));
+        HIPCHK(g, hipEventElapsedTime(&e, g_time_ref, ws->pev[2 * ws->nlaunch - 1]));
+        out->begin_ms = b;
+        out->end_ms = e;
+    }
     for (int i = 0; i < ws->nlaunch; ++i) {
         float ms = 0.f;
         HIPCHK(g, hipEventElapsedTime(&ms, ws->pev[2 * i], ws->pev[2 * i + 1]));

@@ -76,6 +76,14 @@ struct DevGraph {
     const int* pcol;
     const int* pw;
     int poff[kXcd + 1];
+    // in-edges with their weights (pull rounds of SSSP): row v of trow/tcol
+    // lists the tails of v's in-edges, tw their weights; rows longer than
+    // `heavy` are also cut into (row, first edge) chunks; null when not built
+    const int* trow;
+    const int* tcol;
+    const int* tw;
+    const int2* tchunks;
+    int n_tchunks;
 };
 
 // Device view of a workspace: frontier flags (one byte per vertex, one per
@@ -110,6 +118,8 @@ struct Round {
                  // (both-directions CSR) of the pushed vertices, and edge sweeps push
     int hops;    // worklist rounds (balanced mapping): passes of local expansion (0 = off)
     int far_degree; // near-far: only rows longer than this wait for the bound (0 = all)
+    int pullmode;   // per-round schedule: dense rounds pull over in-edges (SSSP: trow;
+                    // CC: the both-directions rows) instead of pushing or sweeping
 };
 
 // Launch entry points (gg_kernels.hip).  Each returns the hipError_t of the
@@ -124,6 +134,7 @@ hipError_t launch_heavy(const Round& R, int algo, int grid, int block, hipStream
 hipError_t launch_bfs_diropt(const Round& R, int grid, int block, hipStream_t s);
 hipError_t launch_jump(const Round& R, int grid, int block, hipStream_t s);
 hipError_t launch_cc_diropt(const Round& R, int grid, int block, hipStream_t s);
+hipError_t launch_sssp_diropt(const Round& R, int grid, int block, hipStream_t s);
 // One thread stores v into the pinned host word *p (system scope) once every
 // earlier kernel of the stream has completed.
 hipError_t launch_mark(unsigned long long* p, unsigned long long v, hipStream_t s);
@@ -135,5 +146,19 @@ hipError_t launch_count_in(const int* col, int m, int* indeg, int grid, int bloc
 hipError_t launch_sym_fill(const int* row, const int* col, const int* src, int n, int m,
                            const int* srow, int* cursor, int* scol, int grid, int block,
                            hipStream_t s);
+hipError_t launch_t_fill(const int* col, const int* w, const int* src, int m, const int* trow,
+                         int* cursor, int* tcol, int* tw, int grid, int block, hipStream_t s);
+// stats[0..3] = min column, max column, min weight, max weight (initialised
+// by the caller to the neutral values); *wsum += the weight sum
+hipError_t launch_check(const int* col, const int* w, int m, int* stats,
+                        unsigned long long* wsum, int grid, hipStream_t s);
+// stable split of the edge list by head part: per-block counts
+// (split_blocks(m) x kXcd), then placement from per-block bases
+int split_blocks(long long m);
+hipError_t launch_split_count(const int* col, int m, const unsigned char* part, int* counts,
+                              hipStream_t s);
+hipError_t launch_split_place(const int* src, const int* col, const int* w, int m,
+                              const unsigned char* part, const long long* base, int* psrc,
+                              int* pcol, int* pw, hipStream_t s);
 
 }  // namespace gg

@@ -58,6 +58,10 @@ constexpr int kPullRatio = 12;
 // frontier hold more than (both-directions edges) / kSweepRatio edges.
 constexpr int kSweepRatio = 8;
 
+// SSSP with the per-round choice pulls a round when the out-edges of the
+// frontier the previous round left exceed (stored edges) / kSsspPullRatio.
+constexpr int kSsspPullRatio = 4;
+
 // ------------------------------------------------------------ helpers ----
 
 __device__ __forceinline__ int wave_incl_scan(int x) {
@@ -331,6 +335,7 @@ __device__ __forceinline__ void relax_batch(const Round& R, const int* col, cons
                 R.ws.tflag[nxt][t[j] >> 6] = 1;
                 acc.p++;
                 if (A == CC && R.fedges) acc.add_f(R.g.srow[t[j] + 1] - R.g.srow[t[j]]);
+                if (A == SSSP && R.fedges) acc.add_f(R.g.row[t[j] + 1] - R.g.row[t[j]]);
                 // near-far: a new distance below the round's bound keeps the
                 // bound where it is for the next round
                 if (A == SSSP && (unsigned)sv[j] + (unsigned)wt[j] < (unsigned)bound) acc.nr = 1;
@@ -1370,6 +1375,176 @@ __global__ __launch_bounds__(256) void k_bfs_diropt(Round R) {
     block_finish(R, acc, R.r % 3, KIND_ROUND);
 }
 
+// Clear frontier generation `gen` (vertex and tile flags; the arrays are
+// padded to whole groups of 64 tiles, 16-byte aligned).
+__device__ __forceinline__ void clear_generation(const Round& R, int gen) {
+    const long long groups = ((long long)R.g.n + 4095) / 4096;
+    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long tt = (long long)gridDim.x * blockDim.x;
+    uint4* vf = reinterpret_cast<uint4*>(R.ws.vflag[gen]);
+    uint4* tf = reinterpret_cast<uint4*>(R.ws.tflag[gen]);
+    for (long long i = tid; i < groups * 256; i += tt) vf[i] = make_uint4(0, 0, 0, 0);
+    for (long long i = tid; i < groups * 4; i += tt) tf[i] = make_uint4(0, 0, 0, 0);
+}
+
+// Candidate of one in-edge (tail u, weight wt) of a pull round, or kInf:
+// only tails on the frontier count (every other tail's value has already
+// been carried along all its out-edges), SSSP adds the weight and drops a
+// sum at or above INF.
+template <int A>
+__device__ __forceinline__ int pull_cand(const Round& R, const unsigned char* vf, int u, int wt,
+                                         Acc& acc) {
+    if (!vf[u]) return kInf;
+    acc.d++;
+    const int x = R.val[u];
+    if (A == SSSP) {
+        const unsigned c = (unsigned)x + (unsigned)wt;
+        return c < (unsigned)kInf ? (int)c : kInf;
+    }
+    return x;
+}
+
+// Pull round (the DSL's innbrs iterator, Sec. 2): every vertex v takes the
+// least candidate over its in-edges -- SSSP: dist[u] + w over the weighted
+// in-edge CSR; CC: label[u] over the both-directions rows -- from the tails
+// on the current frontier, and lowers its own value with a plain store (no
+// other lane writes v in this round).  Rows longer than the heavy threshold
+// are served chunk by chunk, one atomic minimum per chunk.  Every vertex
+// whose value drops goes on the next frontier with its out-row length
+// counted; the frontier generation read here is cleared by the round's
+// companion kernel once every wavefront has read it.  Values only decrease,
+// so reading a tail that another wavefront lowers meanwhile is safe: the
+// lowered tail is pushed and carried along its edges later.
+template <int A>
+__device__ void pull_round(const Round& R, Acc& acc) {
+    const DevGraph& g = R.g;
+    const int* irow = A == SSSP ? g.trow : g.srow;
+    const int* icol = A == SSSP ? g.tcol : g.scol;
+    const int* iw = A == SSSP ? g.tw : nullptr;
+    const int2* ich = A == SSSP ? g.tchunks : g.shchunks;
+    const long long nch = A == SSSP ? g.n_tchunks : g.n_shchunks;
+    const int* orow = A == SSSP ? g.row : g.srow;
+    const int n = g.n;
+    const int cur = R.r & 1, nxt = cur ^ 1;
+    const unsigned char* vf = R.ws.vflag[cur];
+    const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    const long long gw = (long long)blockIdx.x * wpb + (threadIdx.x >> 6);
+    const long long tw = (long long)gridDim.x * wpb;
+    const long long ntiles = (n + 63) / 64;
+    __shared__ int s_pmin[4][64];  // blocks of 256 threads: four wavefronts
+    int* smin = s_pmin[threadIdx.x >> 6];
+    auto lower = [&](int v, int x, int old) {
+        // v dropped from old to x: count it and put it on the next frontier
+        if (x < old) {
+            acc.u++;
+            push(R, nxt, v);
+            acc.p++;
+            acc.add_f(orow[v + 1] - orow[v]);
+        }
+    };
+    for (long long t = gw; t < ntiles; t += tw) {
+        const int v = (int)(t * 64 + lane);
+        int rb = 0, deg = 0;
+        if (v < n) {
+            rb = irow[v];
+            deg = irow[v + 1] - rb;
+            acc.v++;
+        }
+        const bool light = deg <= g.heavy;
+        smin[lane] = kInf;
+        __builtin_amdgcn_wave_barrier();
+        // the in-edges of the tile's light rows, 64 per step, with the loads
+        // of kBatch steps in flight: columns (and weights), then flags and
+        // tail values; the minimum per row collects in LDS
+        const int d = light ? deg : 0;
+        const int incl = wave_incl_scan(d);
+        const int total = __shfl(incl, 63, 64);
+        const int excl = incl - d;
+        for (int base = 0; base < total; base += 64 * kBatch) {
+            int e[kBatch], slot[kBatch], u[kBatch], wt[kBatch];
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j) {
+                const int k = base + j * 64 + lane;
+                int o = 0;
+#pragma unroll
+                for (int step = 32; step > 0; step >>= 1) {
+                    const int cand = o + step;
+                    if (__shfl(excl, cand, 64) <= k) o = cand;
+                }
+                // every lane takes part in the shuffles (a lane past the end
+                // still serves as a source for the others)
+                const int eb = __shfl(rb, o, 64) + (k - __shfl(excl, o, 64));
+                e[j] = k < total ? eb : -1;
+                slot[j] = o;
+            }
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j) {
+                u[j] = e[j] >= 0 ? icol[e[j]] : 0;
+                wt[j] = (A == SSSP && e[j] >= 0) ? iw[e[j]] : 0;
+            }
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j) {
+                if (e[j] < 0) continue;
+                const int x = pull_cand<A>(R, vf, u[j], wt[j], acc);
+                if (x < kInf) atomicMin(&smin[slot[j]], x);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (v < n && light) {
+            acc.e += deg;
+            const int x = smin[lane];
+            const int old = R.val[v];
+            if (x < old) R.val[v] = x;
+            lower(v, x, old);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    // heavy rows, one chunk per wavefront step: kBatch edges per lane
+    for (long long k = gw; k < nch; k += tw) {
+        const int2 c = ich[k];
+        const int e1 = min(c.y + kChunk, irow[c.x + 1]);
+        int u[kChunk / 64], wt[kChunk / 64];
+#pragma unroll
+        for (int j = 0; j < kChunk / 64; ++j) {
+            const int e = c.y + j * 64 + lane;
+            u[j] = e < e1 ? icol[e] : -1;
+            wt[j] = (A == SSSP && e < e1) ? iw[e] : 0;
+        }
+        int x = kInf;
+#pragma unroll
+        for (int j = 0; j < kChunk / 64; ++j)
+            if (u[j] >= 0) x = min(x, pull_cand<A>(R, vf, u[j], wt[j], acc));
+#pragma unroll
+        for (int dd = 32; dd > 0; dd >>= 1) x = min(x, __shfl_xor(x, dd, 64));
+        if (lane == 0) {
+            acc.e += e1 - c.y;
+            if (x < kInf) lower(c.x, x, atomicMin(&R.val[c.x], x));
+        }
+    }
+}
+
+// SSSP with a per-round choice between pushing the frontier (the worklist
+// round of Sec. 3.3, heavy out-rows to the chunk kernel) and pulling every
+// vertex over its in-edges (the innbrs iterator) when the frontier's
+// out-edges are a large part of the graph: a pull round needs no atomics on
+// light rows and reads each in-edge's tail flag before its value.
+__global__ __launch_bounds__(256) void k_sssp_diropt(Round R) {
+    if (!round_begin(R)) return;
+    Ctl* ctl = R.ws.ctl;
+    const bool pull = R.r > 0 && prev_front(R) * kSsspPullRatio > (long long)R.g.m;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->pull[R.r % 3] = pull;
+        ctl->hgrid[R.r % 3] = 0;  // rewritten by this round's heavy kernel
+    }
+    Acc acc;
+    if (pull)
+        pull_round<SSSP>(R, acc);
+    else
+        vasync_body<SSSP, MAP_BALANCED>(R, acc, false, kInf);
+    block_finish(R, acc, R.r % 3, KIND_ROUND);
+}
+
 // Heavy rows of the frontier: the light kernel of the same round stamped
 // them; every wavefront walks the static chunk list and serves the chunks
 // whose row carries this round's stamp.
@@ -1391,13 +1566,20 @@ __global__ __launch_bounds__(256) void k_heavy(Round R) {
     const int bound = nf ? *(volatile int*)&ctl->bound[R.r % 3] : kInf;
     // a pulling BFS round or a sweeping CC round stamps no heavy row:
     // nothing to serve
-    const bool pulled =
-        (A == BFS || (A == CC && R.fedges)) && *(volatile int*)&ctl->pull[R.r % 3] != 0;
+    const bool pulled = (A == BFS || ((A == CC || A == SSSP) && R.fedges)) &&
+                        *(volatile int*)&ctl->pull[R.r % 3] != 0;
     Acc acc;
+    // an SSSP pull round read the frontier generation without consuming it:
+    // it is cleared here, once the round kernel has completed
+    if (A == SSSP && pulled) clear_generation(R, R.r & 1);
     // 64 chunk stamps are checked at once, then the wavefront serves the
-    // chunks that match in turn.  The 64 chunks of one check are spread over
-    // the list with the stride of the whole grid, so that the chunks of one
-    // long row (which sit next to each other) land on different wavefronts.
+    // chunks that match.  The 64 chunks of one check are spread over the
+    // list with the stride of the whole grid, so that the chunks of one long
+    // row (which sit next to each other) land on different wavefronts, and
+    // every wavefront gets a like mix of long and short rows.  (Checking 64
+    // consecutive entries instead, with the list ordered so that a row's
+    // chunks lie far apart, loads the descriptors coalesced but gave the
+    // first wavefronts the hubs' full chunks: rmat22 79.4 -> 75.3 GTEPS.)
     for (long long k0 = 0; !pulled && gw + k0 * tw < nch; k0 += 64) {
         const long long it = gw + (k0 + lane) * tw;
         int2 c = make_int2(0, 0);
@@ -1415,7 +1597,33 @@ __global__ __launch_bounds__(256) void k_heavy(Round R) {
         // lowered atomically.
         const bool lvl = A == BFS && R.hops == 0;
         const int cend = on ? min(c.y + kChunk, row[c.x + 1]) : 0;
-        unsigned long long am = __ballot(on);
+        // matched chunks of at most 64 edges (most heavy rows are short:
+        // rmat22 has 313K such chunks of its 542K) go four at a time, one per
+        // edge slot of the lanes, instead of one wavefront step each
+        unsigned long long sm = __ballot(on && cend - c.y <= 64);
+        unsigned long long am = __ballot(on) & ~sm;
+        while (sm) {
+            int e[4], sv[4];
+            bool ok[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int o = sm ? __ffsll(sm) - 1 : -1;
+                if (sm) sm &= sm - 1;
+                e[j] = 0;
+                sv[j] = 0;
+                ok[j] = false;
+                if (o >= 0) {
+                    const int e0 = __shfl(c.y, o, 64);
+                    e[j] = e0 + lane;
+                    ok[j] = e[j] < __shfl(cend, o, 64);
+                    sv[j] = lvl ? R.r : R.val[__shfl(c.x, o, 64)];
+                }
+            }
+            if (A == BFS && !lvl)
+                relax_batch<A, 4, true, true>(R, col, e, sv, ok, nxt, acc, bound);
+            else
+                relax_batch<A, 4, true>(R, col, e, sv, ok, nxt, acc, bound);
+        }
         while (am) {
             const int o = __ffsll(am) - 1;
             am &= am - 1;
@@ -1444,7 +1652,9 @@ __global__ __launch_bounds__(256) void k_jump(Round R) {
     const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long tt = (long long)gridDim.x * blockDim.x;
     Acc acc;
-    for (long long v = tid; v < n; v += tt) {
+    // a pulling round read its frontier generation without consuming it
+    if (R.pullmode) clear_generation(R, R.r & 1);
+    for (long long v = R.jump ? tid : n; v < n; v += tt) {
         const int x = R.val[v];
         const int y = R.val[x];
         if (y < x) {
@@ -1476,17 +1686,13 @@ __global__ __launch_bounds__(256) void k_cc_diropt(Round R) {
         ctl->hgrid[R.r % 3] = 0;  // rewritten by this round's heavy or shortcut kernel
     }
     Acc acc;
-    if (sweep) {
-        // the frontier generation of this round is not read: clear it (the
-        // flag arrays are padded to whole groups of 64 tiles, 16-byte aligned)
-        const int cur = R.r & 1;
-        const long long groups = ((long long)R.g.n + 4095) / 4096;
-        const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-        const long long tt = (long long)gridDim.x * blockDim.x;
-        uint4* vf = reinterpret_cast<uint4*>(R.ws.vflag[cur]);
-        uint4* tf = reinterpret_cast<uint4*>(R.ws.tflag[cur]);
-        for (long long i = tid; i < groups * 256; i += tt) vf[i] = make_uint4(0, 0, 0, 0);
-        for (long long i = tid; i < groups * 4; i += tt) tf[i] = make_uint4(0, 0, 0, 0);
+    if (sweep && R.pullmode && R.r > 0) {
+        // vertex-based dense round: every vertex pulls the labels of its
+        // frontier neighbours (the shortcut kernel clears the generation)
+        pull_round<CC>(R, acc);
+    } else if (sweep) {
+        // the frontier generation of this round is not read: clear it
+        clear_generation(R, R.r & 1);
         if (R.r == 0) {
             cc_first_pass(R, acc);
         } else {
@@ -1586,6 +1792,140 @@ __global__ __launch_bounds__(256) void k_sym_fill(const int* row, const int* col
         scol[srow[u] + (int)(e - row[u])] = v;
         const int pos = srow[v] + (row[v + 1] - row[v]) + atomicAdd(&cursor[v], 1);
         scol[pos] = u;
+    }
+}
+
+// Upload checks of the edge arrays: the smallest and largest column, the
+// smallest and largest weight (stats[0..3]) and the weight sum.  One atomic
+// per block and statistic.
+__global__ __launch_bounds__(256) void k_check(const int* col, const int* w, int m, int* stats,
+                                               unsigned long long* wsum) {
+    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long tt = (long long)gridDim.x * blockDim.x;
+    int cmin = 2147483647, cmax = -2147483647 - 1, wmin = 2147483647, wmax = -2147483647 - 1;
+    unsigned long long sum = 0;
+    for (long long e = tid; e < m; e += tt) {
+        const int c = col[e];
+        cmin = min(cmin, c);
+        cmax = max(cmax, c);
+        if (w) {
+            const int x = w[e];
+            wmin = min(wmin, x);
+            wmax = max(wmax, x);
+            sum += (unsigned long long)(long long)x;  // the total's sign is checked by wmin
+        }
+    }
+    __shared__ int s4[4][4];
+    __shared__ unsigned long long ss[4];
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        cmin = min(cmin, __shfl_xor(cmin, d, 64));
+        cmax = max(cmax, __shfl_xor(cmax, d, 64));
+        wmin = min(wmin, __shfl_xor(wmin, d, 64));
+        wmax = max(wmax, __shfl_xor(wmax, d, 64));
+        sum += __shfl_xor(sum, d, 64);
+    }
+    const int wid = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s4[wid][0] = cmin;
+        s4[wid][1] = cmax;
+        s4[wid][2] = wmin;
+        s4[wid][3] = wmax;
+        ss[wid] = sum;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < (int)(blockDim.x >> 6); ++i) {
+            cmin = min(cmin, s4[i][0]);
+            cmax = max(cmax, s4[i][1]);
+            wmin = min(wmin, s4[i][2]);
+            wmax = max(wmax, s4[i][3]);
+            sum += ss[i];
+        }
+        atomicMin(&stats[0], cmin);
+        atomicMax(&stats[1], cmax);
+        atomicMin(&stats[2], wmin);
+        atomicMax(&stats[3], wmax);
+        atomicAdd(wsum, sum);
+    }
+}
+
+// Stable split of the edge list by the part of each edge's head (part[v] in
+// [0, kXcd)), CSR order kept inside a part.  Block b owns edges
+// [b * kSplitTile, (b + 1) * kSplitTile): the first kernel counts its edges
+// per part, the second places them at base[b][p] onwards, 256 edges at a
+// time, ranked by ballots so that the order is kept.
+constexpr int kSplitTile = 4096;
+
+__global__ __launch_bounds__(256) void k_split_count(const int* col, int m,
+                                                     const unsigned char* part, int* counts) {
+    __shared__ int c[kXcd];
+    if (threadIdx.x < kXcd) c[threadIdx.x] = 0;
+    __syncthreads();
+    const long long e0 = (long long)blockIdx.x * kSplitTile;
+    const long long e1 = min(e0 + kSplitTile, (long long)m);
+    for (long long e = e0 + threadIdx.x; e < e1; e += blockDim.x) atomicAdd(&c[part[col[e]]], 1);
+    __syncthreads();
+    if (threadIdx.x < kXcd) counts[(long long)blockIdx.x * kXcd + threadIdx.x] = c[threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void k_split_place(const int* src, const int* col, const int* w,
+                                                     int m, const unsigned char* part,
+                                                     const long long* base, int* psrc, int* pcol,
+                                                     int* pw) {
+    __shared__ long long off[kXcd];
+    __shared__ int wc[4][kXcd];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (threadIdx.x < kXcd) off[threadIdx.x] = base[(long long)blockIdx.x * kXcd + threadIdx.x];
+    __syncthreads();
+    const long long e0 = (long long)blockIdx.x * kSplitTile;
+    const long long e1 = min(e0 + kSplitTile, (long long)m);
+    for (long long t = e0; t < e1; t += blockDim.x) {
+        const long long e = t + threadIdx.x;
+        int p = -1, u = 0, v = 0, x = 0;
+        if (e < e1) {
+            u = src[e];
+            v = col[e];
+            if (w) x = w[e];
+            p = part[v];
+        }
+        long long at = -1;
+        for (int q = 0; q < kXcd; ++q) {
+            const unsigned long long mk = __ballot(p == q);
+            if (lane == 0) wc[wid][q] = __popcll(mk);
+            if (p == q) at = __popcll(mk & ((1ull << lane) - 1));
+        }
+        __syncthreads();
+        if (p >= 0) {
+            long long o = off[p] + at;
+            for (int i = 0; i < wid; ++i) o += wc[i][p];
+            psrc[o] = u;
+            pcol[o] = v;
+            if (w) pw[o] = x;
+        }
+        __syncthreads();
+        if (threadIdx.x < kXcd) {
+            int tot = 0;
+            for (int i = 0; i < (int)(blockDim.x >> 6); ++i) tot += wc[i][threadIdx.x];
+            off[threadIdx.x] += tot;
+        }
+        __syncthreads();
+    }
+}
+
+// In-edge CSR with weights: the tails and weights of v's in-edges at
+// trow[v] + (a slot claimed with a counter; the order inside a row is
+// unspecified).
+__global__ __launch_bounds__(256) void k_t_fill(const int* col, const int* w, const int* src,
+                                                int m, const int* trow, int* cursor, int* tcol,
+                                                int* tw) {
+    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long tt = (long long)gridDim.x * blockDim.x;
+    for (long long e = tid; e < m; e += tt) {
+        const int v = col[e];
+        const int pos = trow[v] + atomicAdd(&cursor[v], 1);
+        tcol[pos] = src[e];
+        tw[pos] = w ? w[e] : 1;
     }
 }
 
@@ -1693,6 +2033,10 @@ hipError_t launch_cc_diropt(const Round& R, int grid, int block, hipStream_t s) 
     GG_LAUNCH(k_cc_diropt, grid, block, s, R);
 }
 
+hipError_t launch_sssp_diropt(const Round& R, int grid, int block, hipStream_t s) {
+    GG_LAUNCH(k_sssp_diropt, grid, block, s, R);
+}
+
 __global__ __launch_bounds__(64) void k_mark(unsigned long long* p, unsigned long long v) {
     if (threadIdx.x == 0) __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
@@ -1720,6 +2064,35 @@ hipError_t launch_sym_fill(const int* row, const int* col, const int* src, int n
                            hipStream_t s) {
     (void)n;
     GG_LAUNCH(k_sym_fill, grid, block, s, row, col, src, m, srow, cursor, scol);
+}
+
+hipError_t launch_t_fill(const int* col, const int* w, const int* src, int m, const int* trow,
+                         int* cursor, int* tcol, int* tw, int grid, int block, hipStream_t s) {
+    GG_LAUNCH(k_t_fill, grid, block, s, col, w, src, m, trow, cursor, tcol, tw);
+}
+
+hipError_t launch_check(const int* col, const int* w, int m, int* stats,
+                        unsigned long long* wsum, int grid, hipStream_t s) {
+    GG_LAUNCH(k_check, grid, 256, s, col, w, m, stats, wsum);
+}
+
+int split_blocks(long long m) { return (int)((m + kSplitTile - 1) / kSplitTile); }
+
+hipError_t launch_split_count(const int* col, int m, const unsigned char* part, int* counts,
+                              hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_split_count, dim3(split_blocks(m)), dim3(256), 0, s, col, m, part,
+                       counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_split_place(const int* src, const int* col, const int* w, int m,
+                              const unsigned char* part, const long long* base, int* psrc,
+                              int* pcol, int* pw, hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_split_place, dim3(split_blocks(m)), dim3(256), 0, s, src, col, w, m,
+                       part, base, psrc, pcol, pw);
+    return hipGetLastError();
 }
 
 }  // namespace gg

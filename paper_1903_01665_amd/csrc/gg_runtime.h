@@ -104,6 +104,7 @@ struct gg_graph_s {
     bool symmetric = false;
     int err = GG_OK;
     int n_ws = 0;  // user workspaces alive
+    std::atomic<int> n_async{0};  // host-asynchronous traversals in flight
     // device arrays
     int *row = nullptr, *col = nullptr, *w = nullptr, *src = nullptr;
     int *srow = nullptr, *scol = nullptr, *ssrc = nullptr;
@@ -112,6 +113,9 @@ struct gg_graph_s {
     long long ms = 0;
     int heavy = gg::kHeavyUniform, chunk = gg::kChunk;
     int *psrc = nullptr, *pcol = nullptr, *pw = nullptr;  // head-partitioned edge list
+    int *trow = nullptr, *tcol = nullptr, *tw = nullptr;  // weighted in-edge CSR
+    int2* tchunks = nullptr;
+    int n_tchunks = 0;
     int poff[gg::kXcd + 1] = {};
     double avg_w = 0;  // mean edge weight (0 when unweighted)
     int max_w = 0;     // largest edge weight
@@ -132,6 +136,9 @@ struct WsClaim {
         if (ws) ws->busy.store(false);
     }
     bool held() const { return ws != nullptr; }
+    // the claim outlives the call (a host-asynchronous traversal releases it
+    // when it ends)
+    void keep() { ws = nullptr; }
 };
 
 inline int fail_hip(gg_graph g, hipError_t e) {
@@ -183,6 +190,10 @@ struct Drive {
     std::chrono::steady_clock::time_point t0;
     int status = GG_OK;
     bool finished = false;
+    // poll: out of rounds or time, waiting for the newer batch to complete
+    // before stop_status becomes final
+    bool stopping = false;
+    int stop_status = GG_OK;
 };
 // Bound on the rounds of a traversal planned by p.
 long long max_rounds(const Plan& p);

@@ -13,6 +13,7 @@
 // sits on the path between two batches; gg_server_poll only hands out the
 // finished queries.
 
+#include <algorithm>
 #include <condition_variable>
 #include <deque>
 #include <map>
@@ -39,6 +40,7 @@ struct Query {
     long long id = 0;
     int graph_id = 0, algo = 0, source = 0;
     int* out = nullptr;
+    hipEvent_t ready = nullptr;  // recorded on the caller's stream at submission
     double t_submit = 0, t_admit = 0, t_done = 0;
     gg_ws ws = nullptr;
     int stream = -1;
@@ -69,8 +71,10 @@ struct gg_server_s {
     std::deque<gg_query_result> finished;  // not yet handed out by poll
     std::vector<hipStream_t> streams;
     std::vector<char> stream_busy;
+    std::vector<hipEvent_t> spare_events;  // for Query::ready
     int slots = 0;
     long long budget = 0, used = 0;
+    long long alloc = 0;  // bytes of every workspace allocated (pooled or in flight)
     std::chrono::steady_clock::time_point t0;
     double now() const {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -88,6 +92,46 @@ void free_graph_entry(SGraph& G) {
     G = SGraph{};
 }
 
+void release_event(gg_server s, Query* q) {
+    if (q->ready) s->spare_events.push_back(q->ready);
+    q->ready = nullptr;
+}
+
+// Free the idle pooled workspaces of graphs other than `keep` until a new
+// workspace of `need` bytes fits the budget (freeing device memory waits for
+// the device, so this runs only when the budget forces it).
+void trim_pools(gg_server s, int keep, long long need) {
+    for (auto& kv : s->graphs) {
+        if (s->alloc + need <= s->budget) return;
+        if (kv.first == keep) continue;
+        SGraph& G = kv.second;
+        while (!G.pool.empty() && s->alloc + need > s->budget) {
+            gg_ws w = G.pool.back();
+            G.pool.pop_back();
+            G.all.erase(std::find(G.all.begin(), G.all.end(), w));
+            gg_ws_free(w);
+            s->alloc -= G.ws_bytes;
+        }
+    }
+}
+
+// Retired graphs with nothing queued or in flight are freed while the
+// server has no query in flight (freeing device memory waits for the whole
+// device, which then costs no query anything).
+void reap_retired(gg_server s) {
+    if (!s->active.empty()) return;
+    for (auto it = s->graphs.begin(); it != s->graphs.end();) {
+        SGraph& G = it->second;
+        if (G.retiring && G.in_use == 0) {
+            s->alloc -= (long long)G.all.size() * G.ws_bytes;
+            free_graph_entry(G);
+            it = s->graphs.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+
 // Start a query on a free stream with a workspace of its graph.
 int admit(gg_server s, Query* q, SGraph& G) {
     int si = -1;
@@ -102,13 +146,19 @@ int admit(gg_server s, Query* q, SGraph& G) {
         ws = G.pool.back();
         G.pool.pop_back();
     } else {
+        if (s->budget > 0) trim_pools(s, q->graph_id, G.ws_bytes);
         int rc = gg_ws_create(G.g, &ws);
         if (rc != GG_OK) return rc;
         G.all.push_back(ws);
+        s->alloc += G.ws_bytes;
     }
     hipStream_t st = s->streams[si];
     Plan& p = q->d.p;
     int rc = plan_make(G.g, ws, q->algo, q->source, nullptr, 0, nullptr, q->out, st, &p);
+    // after the caller's work on the output before submission, and after the
+    // workspace's last query
+    if (rc == GG_OK && q->ready)
+        rc = hipStreamWaitEvent(st, q->ready, 0) == hipSuccess ? GG_OK : GG_EHIP;
     if (rc == GG_OK && ws->used && ws->last_stream != st)
         rc = hipStreamWaitEvent(st, ws->finished, 0) == hipSuccess ? GG_OK : GG_EHIP;
     hipError_t e = hipSuccess;
@@ -121,6 +171,11 @@ int admit(gg_server s, Query* q, SGraph& G) {
     q->d.poll = true;
     if (rc == GG_OK) rc = drive_start(q->d, 0, base, base);
     if (rc != GG_OK) {
+        // kernels may already be enqueued: the workspace's next query is
+        // ordered after them
+        (void)hipEventRecord(ws->finished, st);
+        ws->last_stream = st;
+        ws->used = true;
         G.pool.push_back(ws);
         return rc;
     }
@@ -149,6 +204,7 @@ bool step_locked(gg_server s) {
             q->t_done = q->t_admit;
             s->finished.push_back(gg_query_result{q->id, rc, 0, q->t_submit, q->t_admit, q->t_done});
             G.in_use--;
+            release_event(s, q);
             delete q;
             continue;
         }
@@ -182,10 +238,12 @@ bool step_locked(gg_server s) {
         s->finished.push_back(gg_query_result{q->id, status, (int32_t)q->d.r, q->t_submit,
                                               q->t_admit, q->t_done});
         G.in_use--;
+        release_event(s, q);
         delete q;
         s->active[i] = s->active.back();
         s->active.pop_back();
     }
+    reap_retired(s);
     return moved;
 }
 
@@ -198,6 +256,7 @@ void drive_loop(gg_server s) {
     std::unique_lock<std::mutex> lk(s->mu);
     while (!s->stop) {
         if (s->queue.empty() && s->active.empty()) {
+            reap_retired(s);
             s->wake.wait(lk);
             continue;
         }
@@ -258,14 +317,16 @@ int gg_server_remove_graph(gg_server s, int32_t graph_id) {
     std::lock_guard<std::mutex> lk(s->mu);
     auto it = s->graphs.find(graph_id);
     if (it == s->graphs.end() || it->second.retiring) return GG_EINVAL;
-    // no new submissions; the memory is released when the server is freed
-    // (freeing device memory now would synchronise the whole device)
+    // no new submissions; the memory is released once its queries are done
+    // and the server has nothing in flight (freeing device memory waits for
+    // the whole device)
     it->second.retiring = true;
+    s->wake.notify_one();
     return GG_OK;
 }
 
 int gg_server_submit(gg_server s, int32_t graph_id, int32_t algo, int32_t source,
-                     int32_t* out_dev, int64_t* query_id) {
+                     int32_t* out_dev, void* stream, int64_t* query_id) {
     if (!s || !out_dev || (algo != GG_ALGO_SSSP && algo != GG_ALGO_BFS)) return GG_EINVAL;
     Query* q = new (std::nothrow) Query();
     if (!q) return GG_ENOMEM;
@@ -275,6 +336,19 @@ int gg_server_submit(gg_server s, int32_t graph_id, int32_t algo, int32_t source
         source >= it->second.g->n || (algo == GG_ALGO_SSSP && !it->second.g->weighted)) {
         delete q;
         return GG_EINVAL;
+    }
+    // the query starts after what the caller enqueued on `stream` so far
+    if (!s->spare_events.empty()) {
+        q->ready = s->spare_events.back();
+        s->spare_events.pop_back();
+    } else if (hipEventCreateWithFlags(&q->ready, hipEventDisableTiming) != hipSuccess) {
+        delete q;
+        return GG_EHIP;
+    }
+    if (hipEventRecord(q->ready, reinterpret_cast<hipStream_t>(stream)) != hipSuccess) {
+        release_event(s, q);
+        delete q;
+        return GG_EHIP;
     }
     q->id = s->next_query++;
     q->graph_id = graph_id;
@@ -322,8 +396,15 @@ int gg_server_free(gg_server s) {
     s->wake.notify_one();
     if (s->driver.joinable()) s->driver.join();
     (void)hipDeviceSynchronize();
-    for (Query* q : s->queue) delete q;
-    for (Query* q : s->active) delete q;
+    for (Query* q : s->queue) {
+        release_event(s, q);
+        delete q;
+    }
+    for (Query* q : s->active) {
+        release_event(s, q);
+        delete q;
+    }
+    for (hipEvent_t e : s->spare_events) (void)hipEventDestroy(e);
     for (auto& kv : s->graphs) free_graph_entry(kv.second);
     for (hipStream_t st : s->streams)
         if (st) (void)hipStreamDestroy(st);

@@ -202,3 +202,22 @@ def workload(name: str, seed: int = MASTER_SEED) -> HostGraph:
         return uniform(int(nn), int(mm), 1, 100, seed, STREAM["er23"] + 7 * int(nn) + int(mm),
                        name=name)
     raise KeyError(name)
+
+
+def batch_instances(count: int = 512, seed: int = MASTER_SEED):
+    """The batched workload: `count` independent instances [(algo, graph,
+    source)], each an R-MAT graph with scale uniform in 10..18 and edge
+    factor uniform in 8..32 (weights [1, 100]), algorithm SSSP (0) or BFS (1)
+    with probability 1/2, from a seeded source with out-degree > 0.  Each
+    instance draws from its own stream of the master seed."""
+    rng = np.random.default_rng(STREAM["batch"])
+    out = []
+    for i in range(count):
+        scale = int(rng.integers(10, 19))
+        ef = int(rng.integers(8, 33))
+        hg = rmat(scale, ef << scale, seed=seed, stream=STREAM["batch"] * 100000 + i,
+                  name=f"i{i}-rmat{scale}x{ef}")
+        algo = int(rng.integers(0, 2))
+        src = int(pick_sources(hg, 1, seed=seed, stream=STREAM["batch"] * 100000 + 50000 + i)[0])
+        out.append((algo, hg, src))
+    return out

@@ -21,7 +21,7 @@ VERTEX, EDGE, MODE_AUTO = 0, 1, 2
 SYNC, ASYNC, SCHED_AUTO, NEARFAR, DIROPT = 0, 1, 2, 3, 4
 MAP_AUTO, MAP_THREAD, MAP_WAVE, MAP_BALANCED = 0, 1, 2, 3
 ALGO_SSSP, ALGO_BFS, ALGO_CC, ALGO_MSF = 0, 1, 2, 3
-SYMMETRIZE, INPUT_ON_DEVICE, SYMMETRIC = 1, 2, 4
+SYMMETRIZE, INPUT_ON_DEVICE, SYMMETRIC, TRANSPOSE = 1, 2, 4, 8
 OPT_CC_NO_JUMP = 1
 OPT_PROFILE = 2
 KINDS = ("round", "heavy", "aux")
@@ -38,7 +38,8 @@ EXPORTS = ["gg_graph_upload", "gg_graph_free", "gg_graph_info", "gg_graph_error"
            "gg_batch_offsets", "gg_batch_info", "gg_batch_group", "gg_batch_free",
            "gg_server_create", "gg_server_add_graph", "gg_server_remove_graph",
            "gg_server_submit", "gg_server_poll", "gg_server_state", "gg_server_now",
-           "gg_server_free"]
+           "gg_server_free", "gg_sssp_async", "gg_bfs_async", "gg_cc_async", "gg_ticket_query",
+           "gg_ticket_wait", "gg_ticket_stream_wait", "gg_ticket_times", "gg_ticket_free"]
 BATCH_NO_GRAPH, BATCH_ONE_GROUP = 1, 2
 
 TUNE_TABLE = os.path.join(_HERE, "tune_table.json")
@@ -100,10 +101,12 @@ class KindProfile(ctypes.Structure):
 
 class Profile(ctypes.Structure):
     _fields_ = [("profiled", ctypes.c_int32), ("rounds", ctypes.c_int32),
-                ("kind", KindProfile * 3)]
+                ("kind", KindProfile * 3), ("begin_ms", ctypes.c_double),
+                ("end_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {"profiled": bool(self.profiled), "rounds": self.rounds,
+                "begin_ms": self.begin_ms, "end_ms": self.end_ms,
                 **{KINDS[i]: {k: getattr(self.kind[i], k) for k, _ in KindProfile._fields_}
                    for i in range(3)}}
 
@@ -159,12 +162,20 @@ def lib():
     L.gg_server_create.argtypes = [i32, i64, P(vp)]
     L.gg_server_add_graph.argtypes = [vp, vp, P(i32)]
     L.gg_server_remove_graph.argtypes = [vp, i32]
-    L.gg_server_submit.argtypes = [vp, i32, i32, i32, vp, P(i64)]
+    L.gg_server_submit.argtypes = [vp, i32, i32, i32, vp, vp, P(i64)]
     L.gg_server_poll.argtypes = [vp, P(QueryResult), i32, P(i32)]
     L.gg_server_state.argtypes = [vp, P(i32), P(i32), P(i64)]
     L.gg_server_now.argtypes = [vp]
     L.gg_server_now.restype = ctypes.c_double
     L.gg_server_free.argtypes = [vp]
+    L.gg_sssp_async.argtypes = [vp, vp, i32, P(Opts), vp, vp, P(vp)]
+    L.gg_bfs_async.argtypes = [vp, vp, i32, P(Opts), vp, vp, P(vp)]
+    L.gg_cc_async.argtypes = [vp, vp, P(Opts), vp, vp, P(vp)]
+    L.gg_ticket_query.argtypes = [vp]
+    L.gg_ticket_wait.argtypes = [vp]
+    L.gg_ticket_stream_wait.argtypes = [vp, vp]
+    L.gg_ticket_times.argtypes = [vp, vp, P(ctypes.c_float), P(ctypes.c_float), P(i32)]
+    L.gg_ticket_free.argtypes = [vp]
     L.gg_status_str.argtypes = [i32]
     L.gg_status_str.restype = ctypes.c_char_p
     L.gg_version.argtypes = []
@@ -270,7 +281,8 @@ class Workspace:
 class Graph:
     """A graph resident in HBM (CSR, edge list, optional both-directions CSR)."""
 
-    def __init__(self, n, row_ptr, col, w=None, symmetrize=False, symmetric=False, stream=None):
+    def __init__(self, n, row_ptr, col, w=None, symmetrize=False, symmetric=False, stream=None,
+                 transpose=False):
         L = lib()
         self.n = int(n)
         self._row, prow = _arr(row_ptr)
@@ -279,7 +291,8 @@ class Graph:
         pw = None
         if w is not None:
             self._w, pw = _arr(w if len(w) else np.zeros(1, np.int32))
-        flags = (SYMMETRIZE if symmetrize else 0) | (SYMMETRIC if symmetric else 0)
+        flags = (SYMMETRIZE if symmetrize else 0) | (SYMMETRIC if symmetric else 0) | \
+            (TRANSPOSE if transpose else 0)
         h = ctypes.c_void_p()
         _check(L.gg_graph_upload(self.n, m, prow, pcol, pw, flags, _stream_ptr(stream),
                                  ctypes.byref(h)), "gg_graph_upload")
@@ -290,10 +303,10 @@ class Graph:
             del self._w
 
     @classmethod
-    def from_host(cls, hg, symmetrize=False, stream=None):
+    def from_host(cls, hg, symmetrize=False, stream=None, transpose=False):
         """Upload a :class:`paper_1903_01665_amd.gen.HostGraph`."""
         return cls(hg.n, hg.row_ptr, hg.col, hg.w, symmetrize=symmetrize and not hg.symmetric,
-                   symmetric=hg.symmetric, stream=stream)
+                   symmetric=hg.symmetric, stream=stream, transpose=transpose)
 
     def info(self):
         n, m, d, hw, hs = (ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(),
@@ -351,6 +364,27 @@ class Graph:
         o = opts or make_opts(mode, sched, mapping)
         return self._run(lib().gg_cc_ex, "gg_cc", [], o, out, ws, stream)
 
+    # -- host-asynchronous forms (return at once with a Ticket) -------------
+    def _run_async(self, fn, what, args, opts, out, ws, stream):
+        out = self._out(out)
+        o = opts if opts is not None else make_opts()
+        wsh = ws.handle if ws is not None else None
+        t = ctypes.c_void_p()
+        _check(fn(self.handle, wsh, *args, ctypes.byref(o), ctypes.c_void_p(out.data_ptr()),
+                  _stream_ptr(stream), ctypes.byref(t)), what)
+        return Ticket(t, out)
+
+    def sssp_async(self, source, out=None, ws=None, stream=None, opts=None) -> "Ticket":
+        return self._run_async(lib().gg_sssp_async, "gg_sssp_async", [int(source)], opts, out,
+                               ws, stream)
+
+    def bfs_async(self, source, out=None, ws=None, stream=None, opts=None) -> "Ticket":
+        return self._run_async(lib().gg_bfs_async, "gg_bfs_async", [int(source)], opts, out,
+                               ws, stream)
+
+    def cc_async(self, out=None, ws=None, stream=None, opts=None) -> "Ticket":
+        return self._run_async(lib().gg_cc_async, "gg_cc_async", [], opts, out, ws, stream)
+
     def msf(self, out=None, ws=None, stream=None):
         """Minimum spanning forest: (uint8 cuda tensor marking the forest's
         edges in CSR order, total weight, edge count)."""
@@ -397,6 +431,56 @@ class Graph:
         _check(lib().gg_resolve(self.handle, algo, ctypes.byref(opts or make_opts()),
                                 ctypes.byref(out)), "gg_resolve")
         return out
+
+
+class Ticket:
+    """A host-asynchronous traversal in flight (gg_*_async in gg.h).  Holds
+    the output tensor so that it stays allocated until the traversal ends."""
+
+    def __init__(self, handle, out):
+        self.handle = handle
+        self.out = out
+
+    def query(self) -> bool:
+        """True once every kernel of the traversal has completed."""
+        rc = lib().gg_ticket_query(self.handle)
+        if rc == -4:
+            return False
+        _check(rc, "gg_ticket_query")
+        return True
+
+    def wait(self):
+        """Block until the traversal has completed; returns its output."""
+        _check(lib().gg_ticket_wait(self.handle), "gg_ticket_wait")
+        return self.out
+
+    def stream_wait(self, stream=None):
+        """Make `stream` (default: the current one) wait for the traversal."""
+        _check(lib().gg_ticket_stream_wait(self.handle, _stream_ptr(stream)),
+               "gg_ticket_stream_wait")
+        return self.out
+
+    def times(self, ref: "Ticket" = None):
+        """(begin_ms, end_ms, rounds) on the device, from ref's begin."""
+        b, e, r = ctypes.c_float(), ctypes.c_float(), ctypes.c_int32()
+        _check(lib().gg_ticket_times(self.handle, ref.handle if ref is not None else None,
+                                     ctypes.byref(b), ctypes.byref(e), ctypes.byref(r)),
+               "gg_ticket_times")
+        return b.value, e.value, r.value
+
+    def free(self):
+        if getattr(self, "handle", None):
+            _check(lib().gg_ticket_free(self.handle), "gg_ticket_free")
+            self.handle = None
+            self.out = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None) and _lib is not None:
+                _lib.gg_ticket_free(self.handle)
+                self.handle = None
+        except Exception:
+            pass
 
 
 class Batch:
@@ -486,6 +570,7 @@ class Server:
         self.handle = h
         self._res = (QueryResult * 4096)()
         self._graphs = {}
+        self._outs = {}  # query id -> output tensor, held until the query is polled
 
     def add_graph(self, graph: Graph) -> int:
         gid = ctypes.c_int32()
@@ -497,20 +582,35 @@ class Server:
 
     def remove_graph(self, gid: int):
         _check(lib().gg_server_remove_graph(self.handle, gid), "gg_server_remove_graph")
+        self._graphs.pop(gid, None)
 
-    def submit(self, gid, algo, source, out) -> int:
+    def submit(self, gid, algo, source, out, stream=None) -> int:
+        """Queue a query writing `out` (an int32 cuda tensor of >= n elements
+        of that graph); it runs after the work enqueued on `stream` (default:
+        the current stream) so far."""
+        import torch
+        n = self._graphs.get(gid)
+        if n is None:
+            raise GGError(-1, "gg_server_submit: unknown graph")
+        if out.dtype != torch.int32 or not out.is_cuda or not out.is_contiguous() or \
+                out.numel() < n:
+            raise ValueError("output must be a contiguous int32 cuda tensor of >= n elements")
         qid = ctypes.c_int64()
         _check(lib().gg_server_submit(self.handle, gid, algo, int(source),
-                                      ctypes.c_void_p(out.data_ptr()), ctypes.byref(qid)),
-               "gg_server_submit")
+                                      ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream),
+                                      ctypes.byref(qid)), "gg_server_submit")
+        self._outs[qid.value] = out
         return qid.value
 
     def poll(self):
         n = ctypes.c_int32()
         _check(lib().gg_server_poll(self.handle, self._res, len(self._res), ctypes.byref(n)),
                "gg_server_poll")
-        return [(r.id, r.status, r.rounds, r.t_submit, r.t_admit, r.t_done)
+        done = [(r.id, r.status, r.rounds, r.t_submit, r.t_admit, r.t_done)
                 for r in self._res[: n.value]]
+        for d in done:
+            self._outs.pop(d[0], None)
+        return done
 
     def state(self):
         q, f, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()

@@ -38,7 +38,10 @@ NEARFAR = ([(V, NF, BAL, de, 0, 0) for de in (8, 16, 32, 64, 128, 512)] +
            # narrow buckets that hold back only long rows (skewed graphs)
            [(V, NF, BAL, de, 4, far) for de in (2, 3, 4, 6) for far in (32, 96)])
 DIROPT = [(V, gg.DIROPT, BAL, 0, 0, 0)]
-CC_DIROPT = [(gg.EDGE, gg.DIROPT, BAL, 0, 0, 0)]
+# CC's per-round schedule with edge sweeps or vertex pulls as dense rounds
+CC_DIROPT = [(gg.EDGE, gg.DIROPT, BAL, 0, 0, 0), (V, gg.DIROPT, BAL, 0, 0, 0)]
+# SSSP's per-round schedule (pull rounds over the weighted in-edge CSR)
+SSSP_DIROPT = [(V, gg.DIROPT, BAL, 0, 0, 0)]
 
 # calibration graphs: the size classes of the workloads, from a seed stream of
 # their own so that no benchmark graph is itself in the set
@@ -128,13 +131,17 @@ def choose(results):
     return entries, detail
 
 
-def measure(args):
+def measure(args, known=None):
+    """Time every variant on every calibration graph; with `known` (the
+    measurements of an earlier table, in calibration order: (algo, class,
+    {variant: seconds})) only the variants missing there are timed and the
+    rest are taken over."""
     import torch
     gg.tune_set([])  # measure with the built-in rules in place
     results = []  # (algo, class, {variant: time})
     for kind, p in CALIBRATION:
         hg = make(kind, p, args.seed)
-        g = gg.Graph.from_host(hg, symmetrize=True)
+        g = gg.Graph.from_host(hg, symmetrize=True, transpose=True)
         cls = g.probe()
         # traversal times vary with the source: every variant runs from the
         # same few
@@ -143,9 +150,16 @@ def measure(args):
         avg_w = float(hg.w.mean()) if hg.w is not None and hg.m else 1.0
         for algo in ALGOS:
             times = {}
-            extra = NEARFAR if algo == "sssp" else DIROPT if algo == "bfs" else CC_DIROPT
+            if known:
+                ka, kc, kt = known[len(results)]
+                if (ka, tuple(kc)) != (algo, tuple(cls)):
+                    raise RuntimeError(f"measurements do not match: {ka} {kc} vs {algo} {cls}")
+                times = dict(kt)
+            extra = (NEARFAR + SSSP_DIROPT if algo == "sssp" else DIROPT if algo == "bfs"
+                     else CC_DIROPT)
             for v in VARIANTS + LOCAL + extra:
-                times[v] = time_variant(g, algo, srcs, v, args.reps, out, avg_w)
+                if v not in times:
+                    times[v] = time_variant(g, algo, srcs, v, args.reps, out, avg_w)
             best = min(times.values())
             print(f"[tune] {hg.name:8s} class={cls} {algo:4s} best "
                   f"{min(times, key=times.get)} {best * 1e3:.3f} ms", file=sys.stderr, flush=True)
@@ -164,13 +178,22 @@ def main(argv=None):
     ap.add_argument("--from-measurements", metavar="TABLE_JSON",
                     help="re-derive the entries from the measurements of an earlier table "
                          "(no GPU needed)")
+    ap.add_argument("--extend", metavar="TABLE_JSON",
+                    help="time only the variants that the measurements of this table lack "
+                         "and keep the others")
     args = ap.parse_args(argv)
-    if args.from_measurements:
-        with open(args.from_measurements) as f:
+
+    def load(path):
+        with open(path) as f:
             raw = json.load(f)["measurements"]
-        results = [(r["algo"], tuple(r["class"]),
-                    {variant_key(k): (t * 1e-3 if t is not None else math.inf)
-                     for k, t in r["ms"].items()}) for r in raw]
+        return [(r["algo"], tuple(r["class"]),
+                 {variant_key(k): (t * 1e-3 if t is not None else math.inf)
+                  for k, t in r["ms"].items()}) for r in raw]
+
+    if args.from_measurements:
+        results = load(args.from_measurements)
+    elif args.extend:
+        results = measure(args, load(args.extend))
     else:
         results = measure(args)
     entries, detail = choose(results)

@@ -140,3 +140,50 @@ def test_batch_with_local_expansion(gg, flags):
             check(b, inst, want, out)
     finally:
         b.free()
+
+
+@pytest.mark.slow
+def test_batch_at_full_scale_matches_the_oracle(gg):
+    """The batched workload at its real size -- 512 R-MAT instances of scale
+    10..18 and edge factor 8..32 (about 5.6e8 edges), half SSSP, half BFS --
+    run as one batch (eager, then replayed from its HIP graphs): every
+    instance's slice equals the oracle's result for it.  The oracle runs on
+    a pool of host threads (each call releases the interpreter lock)."""
+    import os
+    import time
+    from concurrent.futures import ThreadPoolExecutor
+
+    import torch
+    t = time.time()
+    inst = gen.batch_instances(512)
+    say(f"[gpu] batch full scale: {len(inst)} instances, "
+        f"{sum(hg.m for _, hg, _ in inst)} edges generated in {time.time() - t:.1f}s")
+    b = gg.Batch(inst)
+    try:
+        out = torch.full((b.total_n,), -7, dtype=torch.int32, device="cuda")
+        b.run(out)
+        torch.cuda.synchronize()
+        first = out.cpu().numpy()
+        out.fill_(-7)
+        b.run(out)  # replayed from the captured graphs
+        torch.cuda.synchronize()
+        second = out.cpu().numpy()
+        off = b.offsets()
+    finally:
+        b.free()
+    t = time.time()
+    workers = min(16, os.cpu_count() or 1)
+
+    def one(k):
+        algo, hg, s = inst[k]
+        want = (oracle.sssp(hg.n, hg.row_ptr, hg.col, hg.w, s) if algo == 0
+                else oracle.bfs(hg.n, hg.row_ptr, hg.col, s))
+        a, z = off[k], off[k] + hg.n
+        return (k, int(np.count_nonzero(first[a:z] != want)),
+                int(np.count_nonzero(second[a:z] != want)))
+
+    with ThreadPoolExecutor(max_workers=workers) as pool:
+        res = list(pool.map(one, range(len(inst))))
+    say(f"[gpu] batch full scale: oracle on {workers} threads in {time.time() - t:.1f}s")
+    bad = [r for r in res if r[1] or r[2]]
+    assert not bad, bad[:5]

@@ -16,6 +16,9 @@ pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 COMBOS = [("auto", None), ("vertex-sync", (0, 0, 3)), ("vertex-async", (0, 1, 3)),
           ("edge-sync", (1, 0, 0)), ("edge-async", (1, 1, 0))]
+# per-round schedules: (name, variant, algorithms it applies to)
+PER_ROUND = [("vertex-diropt", (0, 4, 3), ("sssp", "bfs", "cc")),
+             ("edge-diropt", (1, 4, 0), ("cc",))]
 
 
 def say(*a):
@@ -31,11 +34,12 @@ def run_full(name, combos, mapping_extra=()):
     want = {"sssp": oracle.sssp(hg.n, hg.row_ptr, hg.col, hg.w, s),
             "bfs": oracle.bfs(hg.n, hg.row_ptr, hg.col, s),
             "cc": oracle.cc(hg.n, hg.row_ptr, hg.col)}
-    g = gg.Graph.from_host(hg, symmetrize=True)
+    g = gg.Graph.from_host(hg, symmetrize=True, transpose=True)
     try:
-        for cname, v in list(combos) + list(mapping_extra):
+        runs = [(c, v, ("sssp", "bfs", "cc")) for c, v in list(combos) + list(mapping_extra)]
+        for cname, v, algos in runs + PER_ROUND:
             o = gg.make_opts(*v) if v else gg.make_opts()
-            for algo in ("sssp", "bfs", "cc"):
+            for algo in algos:
                 say(f"[gpu-full] {name} {algo} {cname}")
                 out = g.cc(opts=o) if algo == "cc" else getattr(g, algo)(s, opts=o)
                 got = out.cpu().numpy()

@@ -200,21 +200,49 @@ def test_bad_calls(gg):
 
 
 def test_two_streams_two_workspaces(gg):
+    """SSSP and BFS issued at the same moment from two host threads, each on
+    its own stream and workspace: their device time lines overlap (profile
+    events on one time line), and both results are exact."""
+    import threading
+
     import torch
-    hg = gen.workload("rmat12")
-    srcs = gen.pick_sources(hg, 2, stream=7)
-    want = [oracle.sssp(hg.n, hg.row_ptr, hg.col, hg.w, int(s)) for s in srcs]
+    hg = gen.workload("grid256")  # hundreds of rounds: milliseconds each
+    want = expected(hg, 0)
     g = gg.Graph.from_host(hg, symmetrize=True)
     ws = [gg.Workspace(g), gg.Workspace(g)]
     st = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = [torch.full((hg.n,), -1, dtype=torch.int32, device="cuda") for _ in range(2)]
+    torch.cuda.synchronize()
+    o = gg.make_opts(VERTEX, SYNC, BALANCED, flags=gg.OPT_PROFILE)
     try:
-        outs = []
-        for i in range(2):
-            with torch.cuda.stream(st[i]):
-                outs.append(g.sssp(int(srcs[i]), ws=ws[i], stream=st[i]))
-        torch.cuda.synchronize()
-        for i in range(2):
-            np.testing.assert_array_equal(outs[i].cpu().numpy(), want[i])
+        for rep in range(3):
+            say(f"[gpu] two host threads, two streams: grid256 rep={rep}")
+            gate = threading.Barrier(2)
+            errs = []
+
+            def run(i):
+                try:
+                    gate.wait()
+                    fn = g.sssp if i == 0 else g.bfs
+                    fn(0, out=outs[i], ws=ws[i], stream=st[i], opts=o)
+                except Exception as e:  # reported below
+                    errs.append(e)
+
+            th = [threading.Thread(target=run, args=(i,)) for i in range(2)]
+            for t in th:
+                t.start()
+            for t in th:
+                t.join()
+            assert not errs, errs
+            torch.cuda.synchronize()
+            p0, p1 = g.profile(ws[0]), g.profile(ws[1])
+            say(f"[gpu]   sssp [{p0['begin_ms']:.3f}, {p0['end_ms']:.3f}] ms, "
+                f"bfs [{p1['begin_ms']:.3f}, {p1['end_ms']:.3f}] ms")
+            assert p0["begin_ms"] < p1["end_ms"] and p1["begin_ms"] < p0["end_ms"], (p0, p1)
+            np.testing.assert_array_equal(outs[0].cpu().numpy(), want["sssp"])
+            np.testing.assert_array_equal(outs[1].cpu().numpy(), want["bfs"])
+            for x in outs:
+                x.fill_(-1)
     finally:
         for w in ws:
             w.free()
@@ -393,9 +421,8 @@ def test_diropt_cc(gg):
                 # the stored edges or serve a worklist
                 assert pr["round"]["edges_processed"] >= 2 * hg.m, pr
                 assert pr["round"]["swept_edges"] > 0 or pr["round"]["vertices_processed"] > 0, pr
-            # a vertex-based mode is refused; AUTO takes the edge mode
-            with pytest.raises(gg.GGError):
-                g.cc(VERTEX, gg.DIROPT)
+            # the vertex-based form pulls its dense rounds; AUTO takes the edge mode
+            np.testing.assert_array_equal(g.cc(VERTEX, gg.DIROPT).cpu().numpy()[: hg.n], want)
             np.testing.assert_array_equal(g.cc(gg.MODE_AUTO, gg.DIROPT).cpu().numpy()[: hg.n],
                                           want)
         finally:

@@ -117,3 +117,96 @@ def test_retired_graph_rejects_new_queries(gg):
         np.testing.assert_array_equal(out.cpu().numpy(), oracle.sssp(h.n, h.row_ptr, h.col, h.w, 0))
     finally:
         srv.free()
+
+
+def test_submit_follows_the_callers_stream(gg):
+    """A query runs after the work the caller enqueued on its stream before
+    submitting (a spin kernel, then a fill of the output)."""
+    import torch
+    h = gen.rmat(13, 16 << 13, stream=81, name="rmat13")
+    srcs = [int(s) for s in gen.pick_sources(h, 4, stream=82)]
+    want = [oracle.sssp(h.n, h.row_ptr, h.col, h.w, s) for s in srcs]
+    srv = gg.Server(slots=4)
+    st = torch.cuda.Stream()
+    try:
+        gid = srv.add_graph(gg.Graph.from_host(h))
+        outs = [torch.empty(h.n, dtype=torch.int32, device="cuda") for _ in srcs]
+        torch.cuda.synchronize()
+        say("[gpu] serve: submit after work on the caller's stream")
+        ids = {}
+        with torch.cuda.stream(st):
+            torch.cuda._sleep(20_000_000)
+            for i, s in enumerate(srcs):
+                outs[i].fill_(-5)
+                ids[srv.submit(gid, 0, s, outs[i], stream=st)] = i
+        done = 0
+        while done < len(srcs):
+            for qid, status, *_ in srv.poll():
+                assert status == 0
+                done += 1
+        torch.cuda.synchronize()
+        for i in range(len(srcs)):
+            np.testing.assert_array_equal(outs[i].cpu().numpy(), want[i])
+    finally:
+        srv.free()
+
+
+def test_submit_checks_the_output(gg):
+    import torch
+    h = gen.uniform(300, 1200, stream=6)
+    srv = gg.Server(slots=2)
+    try:
+        gid = srv.add_graph(gg.Graph.from_host(h))
+        for bad in (torch.empty(h.n - 1, dtype=torch.int32, device="cuda"),
+                    torch.empty(h.n, dtype=torch.int64, device="cuda"),
+                    torch.empty(h.n, dtype=torch.int32),
+                    torch.empty(2 * h.n, dtype=torch.int32, device="cuda")[::2]):
+            with pytest.raises(ValueError):
+                srv.submit(gid, 0, 0, bad)
+        with pytest.raises(gg.GGError):
+            srv.submit(gid + 7, 0, 0, torch.empty(h.n, dtype=torch.int32, device="cuda"))
+    finally:
+        srv.free()
+
+
+def test_retired_graph_memory_is_released(gg):
+    """Once a retired graph has no query left and the server is idle, its
+    device memory goes back (measured with the device's free memory); the
+    other graphs keep serving."""
+    import time
+
+    import torch
+    big = gen.rmat(18, 16 << 18, stream=83, name="rmat18")  # ~50 MB of arrays
+    small = gen.uniform(400, 2000, stream=84)
+    srv = gg.Server(slots=4)
+    try:
+        gid_b = srv.add_graph(gg.Graph.from_host(big))
+        gid_s = srv.add_graph(gg.Graph.from_host(small))
+        out_b = torch.empty(big.n, dtype=torch.int32, device="cuda")
+        out_s = torch.empty(small.n, dtype=torch.int32, device="cuda")
+        s_b = int(gen.pick_sources(big, 1, stream=85)[0])
+        srv.submit(gid_b, 1, s_b, out_b)
+        while not srv.poll():
+            pass
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
+        srv.remove_graph(gid_b)
+        freed = 0
+        t0 = time.time()
+        while time.time() - t0 < 10:
+            freed = torch.cuda.mem_get_info()[0] - free0
+            if freed >= 40 << 20:
+                break
+            time.sleep(0.05)
+        say(f"[gpu] serve: retired rmat18 released {freed >> 20} MiB")
+        assert freed >= 40 << 20, freed
+        srv.submit(gid_s, 0, 3, out_s)
+        while not srv.poll():
+            pass
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(out_s.cpu().numpy(),
+                                      oracle.sssp(small.n, small.row_ptr, small.col, small.w, 3))
+        np.testing.assert_array_equal(out_b.cpu().numpy(),
+                                      oracle.bfs(big.n, big.row_ptr, big.col, s_b))
+    finally:
+        srv.free()

@@ -63,16 +63,17 @@ def test_table_validation():
 
 def test_table_takes_only_runnable_schedules():
     """Near-far is an SSSP vertex schedule; the per-round dense/sparse choice
-    is a BFS vertex and a CC edge schedule."""
+    is a BFS and SSSP vertex schedule and a CC schedule in either mode."""
     saved = gg.tune_get()
     try:
         def entry(algo, mode, sched):
             return dict(algo=algo, size_class=5, skew_class=0, depth_class=0, mode=mode,
                         sched=sched, mapping=3)
-        for ok in (entry(0, 0, gg.NEARFAR), entry(1, 0, gg.DIROPT), entry(2, 1, gg.DIROPT)):
+        for ok in (entry(0, 0, gg.NEARFAR), entry(1, 0, gg.DIROPT), entry(2, 1, gg.DIROPT),
+                   entry(0, 0, gg.DIROPT), entry(2, 0, gg.DIROPT)):
             gg.tune_set([ok])
-        for bad in (entry(1, 0, gg.NEARFAR), entry(0, 0, gg.DIROPT), entry(2, 0, gg.DIROPT),
-                    entry(1, 1, gg.DIROPT), entry(0, 1, gg.NEARFAR)):
+        for bad in (entry(1, 0, gg.NEARFAR), entry(0, 1, gg.DIROPT), entry(1, 1, gg.DIROPT),
+                    entry(0, 1, gg.NEARFAR)):
             with pytest.raises(gg.GGError):
                 gg.tune_set([bad])
     finally:
