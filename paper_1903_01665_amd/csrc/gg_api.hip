@@ -96,6 +96,11 @@ int make_ws(gg_graph g, gg_ws_s** out) {
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ws->finished, hipEventDisableTiming);
     if (e == hipSuccess) e = hipMemset(ws->vflag_mem, 0, (size_t)(2 * (vbytes + tbytes)));
     if (e == hipSuccess) e = hipMemset(ws->dev.ctl, 0, sizeof(Ctl));
+    // the fills above are queued on the null stream and may still be in
+    // flight when hipMemset returns; traversals use the workspace on other
+    // (non-blocking) streams, which do not wait for the null stream: wait
+    // here, so that a fill can never land in the middle of a traversal
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     if (e != hipSuccess) {
         free_ws_arrays(ws);
         delete ws;

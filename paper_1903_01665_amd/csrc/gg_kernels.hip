@@ -1597,33 +1597,7 @@ __global__ __launch_bounds__(256) void k_heavy(Round R) {
         // lowered atomically.
         const bool lvl = A == BFS && R.hops == 0;
         const int cend = on ? min(c.y + kChunk, row[c.x + 1]) : 0;
-        // matched chunks of at most 64 edges (most heavy rows are short:
-        // rmat22 has 313K such chunks of its 542K) go four at a time, one per
-        // edge slot of the lanes, instead of one wavefront step each
-        unsigned long long sm = __ballot(on && cend - c.y <= 64);
-        unsigned long long am = __ballot(on) & ~sm;
-        while (sm) {
-            int e[4], sv[4];
-            bool ok[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int o = sm ? __ffsll(sm) - 1 : -1;
-                if (sm) sm &= sm - 1;
-                e[j] = 0;
-                sv[j] = 0;
-                ok[j] = false;
-                if (o >= 0) {
-                    const int e0 = __shfl(c.y, o, 64);
-                    e[j] = e0 + lane;
-                    ok[j] = e[j] < __shfl(cend, o, 64);
-                    sv[j] = lvl ? R.r : R.val[__shfl(c.x, o, 64)];
-                }
-            }
-            if (A == BFS && !lvl)
-                relax_batch<A, 4, true, true>(R, col, e, sv, ok, nxt, acc, bound);
-            else
-                relax_batch<A, 4, true>(R, col, e, sv, ok, nxt, acc, bound);
-        }
+        unsigned long long am = __ballot(on);
         while (am) {
             const int o = __ffsll(am) - 1;
             am &= am - 1;
