@@ -316,6 +316,22 @@ int gg_ticket_times(gg_ticket t, gg_ticket ref, float* begin_ms, float* end_ms, 
 /* Release a ticket (waits for the traversal first if it still runs). */
 int gg_ticket_free(gg_ticket t);
 
+/* BFS for callers that cannot allocate memory (code that must not call
+ * hipMalloc, such as tight serving loops or hosts that forbid it): the same
+ * traversal as gg_bfs_ex on the graph's arrays, with the scratch memory that
+ * a workspace holds (frontier flags, round stamps, control and counters)
+ * taken from one fixed device array of the library, about 26 MB, that each
+ * GPU holds from the first call on it until the process ends.  The call
+ * allocates nothing: no device or host memory, no events.  Arguments as
+ * gg_bfs_ex without a workspace; GG_OPT_PROFILE is ignored and gg_last_stats
+ * does not report these calls.  GG_EINVAL for a graph of more than 4,194,304
+ * vertices (the array's limit) and for the errors of gg_bfs_ex.  Calls on one
+ * GPU share the array: they are serialised by a lock inside the library, and
+ * each returns only once every kernel it enqueued on `stream` has completed
+ * (the host waits for `stream`), so a call never sees another's kernels. */
+int gg_bfs_noalloc(gg_graph g, int32_t source, const gg_opts* opts, int32_t* dist_out_dev,
+                   void* stream);
+
 /* Minimum spanning forest (MST is the fourth algorithm of Sec. 4.1, Table 3;
  * the DSL's Set type is a union-find structure, Sec. 2).  Every stored edge e
  * is taken as an undirected edge with key (w[e], e) -- weight first, then

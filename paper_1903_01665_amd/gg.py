@@ -39,7 +39,8 @@ EXPORTS = ["gg_graph_upload", "gg_graph_free", "gg_graph_info", "gg_graph_error"
            "gg_server_create", "gg_server_add_graph", "gg_server_remove_graph",
            "gg_server_submit", "gg_server_poll", "gg_server_state", "gg_server_now",
            "gg_server_free", "gg_sssp_async", "gg_bfs_async", "gg_cc_async", "gg_ticket_query",
-           "gg_ticket_wait", "gg_ticket_stream_wait", "gg_ticket_times", "gg_ticket_free"]
+           "gg_ticket_wait", "gg_ticket_stream_wait", "gg_ticket_times", "gg_ticket_free",
+           "gg_bfs_noalloc"]
 BATCH_NO_GRAPH, BATCH_ONE_GROUP = 1, 2
 
 TUNE_TABLE = os.path.join(_HERE, "tune_table.json")
@@ -176,6 +177,7 @@ def lib():
     L.gg_ticket_stream_wait.argtypes = [vp, vp]
     L.gg_ticket_times.argtypes = [vp, vp, P(ctypes.c_float), P(ctypes.c_float), P(i32)]
     L.gg_ticket_free.argtypes = [vp]
+    L.gg_bfs_noalloc.argtypes = [vp, i32, P(Opts), vp, vp]
     L.gg_status_str.argtypes = [i32]
     L.gg_status_str.restype = ctypes.c_char_p
     L.gg_version.argtypes = []
