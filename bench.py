@@ -605,9 +605,17 @@ def bench_batched(args):
     log(f"[bench] batch built and captured in {time.time() - t:.1f}s: {info}")
     res = out.cpu().numpy()
     off = b.offsets()
-    m_trav = 0
+    m_trav = v_reach = min_bytes = 0
     for i, (algo, hg, s) in enumerate(inst):
-        m_trav += int(hg.degrees()[res[off[i]: off[i] + hg.n] != INF].sum())
+        reached = res[off[i]: off[i] + hg.n] != INF
+        e = int(hg.degrees()[reached].sum())
+        v = int(reached.sum())
+        m_trav += e
+        v_reach += v
+        # work-efficient minimum: every reached vertex's row offsets and value
+        # (read and written) once, every edge of it once (column, weight for
+        # SSSP, head value)
+        min_bytes += (12 if algo == 0 else 8) * e + 16 * v
     for _ in range(args.warmup):
         b.run(out)
     torch.cuda.synchronize()
@@ -641,10 +649,53 @@ def bench_batched(args):
     for g in graphs:
         g.free()
     b.free()
+
+    # the whole run is the unit here: the groups' kernels run inside HIP-graph
+    # replays on streams of their own, overlapped, so no single kernel's
+    # launch time stands for the run
+    roof = {"bound": "hbm", "achieved": round(min_bytes / tb / 1e9, 1), "peak": 8000.0,
+            "unit": "GB/s", "frac": round(min_bytes / tb / 1e9 / 8000.0, 4), "traffic": None,
+            "kernel": "whole batched run (every group's round kernels, HIP-graph replays)",
+            "launches": len(groups), "avg_launch_us": round(tb * 1e6, 2),
+            "algorithmic_bytes_per_launch": int(min_bytes / max(1, len(groups))),
+            "algorithmic_bytes_total": int(min_bytes),
+            "algorithmic_bytes_rule": "12 B (SSSP) / 8 B (BFS) per traversed edge + 16 B per "
+                                      "reached vertex, once each"}
+
+    cpu = verified = None
+    if not args.no_cpu:
+        import concurrent.futures
+
+        import oracle
+        threads = min(16, host_info()["cpus_allowed"] or os.cpu_count() or 1)
+
+        def one(i):
+            algo, hg, s = inst[i]
+            if algo == 0:
+                return oracle.sssp(hg.n, hg.row_ptr, hg.col, hg.w, s)
+            return oracle.bfs(hg.n, hg.row_ptr, hg.col, s)
+
+        # ctypes releases the GIL inside the C oracle: the instances run in
+        # parallel, one per thread at a time
+        t0 = time.perf_counter()
+        with concurrent.futures.ThreadPoolExecutor(threads) as ex:
+            want = list(ex.map(one, range(len(inst))))
+        tc = time.perf_counter() - t0
+        verified = all(np.array_equal(want[i], res[off[i]: off[i] + hg.n])
+                       for i, (_, hg, _) in enumerate(inst))
+        cpu = {"value": round(m_trav / tc / 1e9, 4), "unit": "GTEPS", "cores": threads,
+               "threads": threads, "kind": "oracle", "seconds": round(tc, 3),
+               "sample": f"all {len(inst)} instances: Dijkstra / FIFO BFS per instance, "
+                         f"instances spread over {threads} threads",
+               "host": host_info()}
+        log(f"[bench] oracle on {threads} threads: {tc:.2f}s ({cpu['value']} GTEPS); "
+            f"GPU results match: {verified}")
     common_line(args, "GTEPS batched (512 SSSP/BFS instances)", m_trav / tb / 1e9, "GTEPS",
                 tb * 1e3,
                 {"workload": "batched-rmat-10..18", "instances": len(inst), "edges": total_m,
-                 "traversed_edges": m_trav, "groups": groups},
+                 "traversed_edges": m_trav, "reached_vertices": v_reach, "groups": groups,
+                 "verified_vs_oracle": verified},
+                roofline=roof, cpu_baseline=cpu,
                 plain={"GTEPS": round(m_trav / tp / 1e9, 4), "ms_per_pass": round(tp * 1e3, 3)},
                 speedup_vs_plain=round(tp / tb, 3), results_identical_to_plain=same)
 
@@ -795,7 +846,8 @@ def bench_serve(args):
         f"the {args.serve_warmup}s warm-up), {edges} traversed edges")
     svc_s = np.full(len(trace.t), np.nan)
     lat_s, st, wall_s = serve.run_served(hosts, trace, slots=args.slots,
-                                         upload_every=upload_every, n_pool=n_pool, service=svc_s)
+                                         upload_every=upload_every, n_pool=n_pool, service=svc_s,
+                                         log=log)
     ok = int((st == 0).sum())
     log(f"[bench] served: wall {wall_s:.2f}s p50 {serve.percentile(lat_s[measured], 50) * 1e3:.2f} ms "
         f"p99 {serve.percentile(lat_s[measured], 99) * 1e3:.2f} ms ({ok}/{len(st)} ok), "
@@ -805,7 +857,7 @@ def bench_serve(args):
         lat_p, wall_p = np.array([np.nan]), float("nan")
     else:
         lat_p, wall_p = serve.run_plain(hosts, trace, n_pool=n_pool, upload_every=upload_every,
-                                        service=svc_p)
+                                        service=svc_p, log=log)
         log(f"[bench] plain: wall {wall_p:.2f}s p50 {serve.percentile(lat_p[measured], 50) * 1e3:.2f} ms "
             f"p99 {serve.percentile(lat_p[measured], 99) * 1e3:.2f} ms, "
             f"service mean {np.nanmean(svc_p) * 1e3:.3f} ms")

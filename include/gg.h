@@ -147,7 +147,7 @@ typedef struct {
                               vertex-based, BALANCED mapping), 0..64; 0 = off.  A wavefront
                               serves the vertices it has just lowered (those below the
                               near-far bound) again in the same round, up to `hops` times,
-                              from a 256-entry list of its own; what does not fit, and the
+                              from a 128-entry list of its own; what does not fit, and the
                               list left after the last pass, goes to the next round's
                               frontier.  Fewer rounds on high-diameter graphs; the result
                               is the same.  Ignored by other variants; with
@@ -319,8 +319,8 @@ int gg_ticket_free(gg_ticket t);
 /* BFS for callers that cannot allocate memory (code that must not call
  * hipMalloc, such as tight serving loops or hosts that forbid it): the same
  * traversal as gg_bfs_ex on the graph's arrays, with the scratch memory that
- * a workspace holds (frontier flags, round stamps, control and counters)
- * taken from one fixed device array of the library, about 26 MB, that each
+ * a workspace holds (frontier flags, heavy-row bits, control and counters)
+ * taken from one fixed device array of the library, about 10 MB, that each
  * GPU holds from the first call on it until the process ends.  The call
  * allocates nothing: no device or host memory, no events.  Arguments as
  * gg_bfs_ex without a workspace; GG_OPT_PROFILE is ignored and gg_last_stats
@@ -479,7 +479,7 @@ int gg_batch_free(gg_batch b);
  * the server owns them from then on), a FIFO of submitted queries and a set
  * of slots.  A driver thread of the server admits queued queries while a
  * slot is free and the per-query state of all admitted queries (a
- * workspace: frontier flags and round stamps, ~6 bytes per vertex) fits the
+ * workspace: frontier flags and heavy-row bits, ~2.3 bytes per vertex) fits the
  * memory budget, enqueues each admitted query's rounds on the slot's own
  * stream, and launches a query's next batch of rounds as soon as its
  * previous one completes, so the kernels of different queries overlap on

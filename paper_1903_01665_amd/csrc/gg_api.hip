@@ -53,7 +53,7 @@ int grid_for(long long items_per_block_unit, long long units) {
 void free_ws_arrays(gg_ws_s* ws) {
     if (!ws) return;
     if (ws->vflag_mem) (void)hipFree(ws->vflag_mem);
-    if (ws->dev.hstamp) (void)hipFree(ws->dev.hstamp);
+    if (ws->dev.hbits[0]) (void)hipFree(ws->dev.hbits[0]);
     if (ws->dev.ctl) (void)hipFree(ws->dev.ctl);
     if (ws->dev.stat) (void)hipFree(ws->dev.stat);
     if (ws->dev.pcount) (void)hipFree(ws->dev.pcount);
@@ -69,7 +69,7 @@ void free_ws_arrays(gg_ws_s* ws) {
     ws->pev.clear();
     if (ws->finished) (void)hipEventDestroy(ws->finished);
     ws->vflag_mem = nullptr;
-    ws->dev.hstamp = nullptr;
+    ws->dev.hbits[0] = ws->dev.hbits[1] = nullptr;
     ws->dev.ctl = nullptr;
     ws->dev.stat = nullptr;
     ws->h_done = nullptr;
@@ -85,8 +85,9 @@ int make_ws(gg_graph g, gg_ws_s** out) {
     const long long tbytes = ((ntiles + 63) / 64) * 64;
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = dalloc(&ws->vflag_mem, (size_t)(2 * (vbytes + tbytes)));
-    if (e == hipSuccess) e = dalloc(&ws->dev.hstamp, (size_t)g->n);
-    if (e == hipSuccess) e = hipMemset(ws->dev.hstamp, 0xff, sizeof(int) * (size_t)g->n);
+    const long long hwords = ((long long)g->n + 31) / 32;
+    if (e == hipSuccess) e = dalloc(&ws->dev.hbits[0], (size_t)(2 * hwords));
+    if (e == hipSuccess) e = hipMemset(ws->dev.hbits[0], 0, sizeof(unsigned) * (size_t)(2 * hwords));
     if (e == hipSuccess) e = dalloc(&ws->dev.ctl, 1);
     if (e == hipSuccess) e = dalloc(&ws->dev.stat, (size_t)kKinds * kMaxStatBlocks);
     if (e == hipSuccess) e = dalloc(&ws->dev.pcount, (size_t)3 * 2 * kMaxStatBlocks);
@@ -106,6 +107,7 @@ int make_ws(gg_graph g, gg_ws_s** out) {
         delete ws;
         return fail_hip(g, e);
     }
+    ws->dev.hbits[1] = ws->dev.hbits[0] + hwords;
     ws->dev.vflag[0] = ws->vflag_mem;
     ws->dev.vflag[1] = ws->vflag_mem + vbytes;
     ws->dev.tflag[0] = ws->vflag_mem + 2 * vbytes;
@@ -502,11 +504,10 @@ hipError_t plan_init(Plan& p) {
     return e;
 }
 
-// Round r with heavy-row stamp `stamp`.
-hipError_t plan_round(Plan& p, int r, int stamp) {
+// Round r of the plan's traversal.
+hipError_t plan_round(Plan& p, int r) {
     Round& R = p.R;
     R.r = r;
-    R.stamp = stamp;
     hipError_t e = plan_launch(p, KIND_ROUND, [&] {
         if (p.diropt && p.cc) return launch_cc_diropt(R, p.g_round, kBlock, p.s);
         if (p.diropt && p.algo == GG_ALGO_SSSP) return launch_sssp_diropt(R, p.g_round, kBlock, p.s);
@@ -523,16 +524,15 @@ hipError_t plan_round(Plan& p, int r, int stamp) {
     return e;
 }
 
-// Reserve `span` round stamps on the workspace; returns the first.  Stamps
-// never repeat across traversals of a workspace (the heavy kernel serves a
-// chunk only when its row carries the current round's stamp); they restart,
-// with the stamp array cleared, long before the 32-bit range ends.
+// Reserve `span` round stamps on the workspace; returns the first.  The
+// first stamp of a traversal is its tag: the round kernel that finds the end
+// stores it into the workspace's pinned word, so a late kernel of an earlier
+// traversal (an older, smaller tag) cannot end this one.  Stamps restart
+// long before the 32-bit range ends (the previous tag is then large).
 int reserve_stamps(gg_ws ws, hipStream_t s, long long span, hipError_t* err) {
+    (void)s;
     *err = hipSuccess;
-    if ((long long)ws->epoch + span > (1LL << 30)) {
-        *err = hipMemsetAsync(ws->dev.hstamp, 0xff, sizeof(int) * (size_t)ws->owner->n, s);
-        ws->epoch = 0;
-    }
+    if ((long long)ws->epoch + span > (1LL << 30)) ws->epoch = 0;
     const int base = ws->epoch;
     ws->epoch = (int)std::min<long long>((long long)base + span, 1LL << 30);
     return base;
@@ -576,7 +576,7 @@ int drive_start(Drive& d, long long r0, int stamp_base, int tag) {
 int drive_enqueue(Drive& d) {
     Plan& p = d.p;
     const long long stop = std::min(d.r + d.batch, d.max_rounds);
-    for (; d.r < stop; ++d.r) HIPCHK(p.g, plan_round(p, (int)d.r, d.stamp_base + (int)d.r));
+    for (; d.r < stop; ++d.r) HIPCHK(p.g, plan_round(p, (int)d.r));
     if (d.poll) {
         const unsigned long long v = ++p.ws->prog_seq;
         HIPCHK(p.g, launch_mark(prog_word(p.ws), v, p.s));
@@ -689,7 +689,6 @@ int run_multi(gg_graph g, gg_ws ws, int algo, int source, const int* sources_dev
     const int base = reserve_stamps(ws, s, (long long)g->n + 3, &e);
     HIPCHK(g, e);
     p.R.epoch = base;
-    p.R.stamp = base;
     HIPCHK(g, plan_init(p));
     long long r_end = 0;
     const int status = plan_drive(p, 0, base, base, &r_end);

@@ -224,7 +224,6 @@ int run_async(gg_graph g, gg_ws ws, int algo, int source, const gg_opts* opts, i
     if (e == hipSuccess) base = reserve_stamps(ws, p.s, (long long)g->n + 3, &e);
     if (e == hipSuccess) {
         p.R.epoch = base;
-        p.R.stamp = base;
         e = plan_init(p);
     }
     if (e != hipSuccess) {

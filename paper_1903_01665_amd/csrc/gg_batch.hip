@@ -92,15 +92,14 @@ int capture(Group& G, int* out) {
     int rc = plan_make(G.g, nullptr, G.algo, 0, G.sources, G.nsrc, &G.opts, out, G.stream, &p);
     if (rc != GG_OK) return rc;
     hipError_t e;
-    // stamps reserved (and, if needed, cleared) before the capture begins;
-    // every replay uses the same ones, which marks the same frontier rows
+    // the tag is reserved before the capture begins; every replay uses it
     const int base = reserve_stamps(p.ws, G.stream, (long long)G.r_cap + 1, &e);
     if (e != hipSuccess) return GG_EHIP;
     p.R.epoch = base;
     if (hipStreamBeginCapture(G.stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return GG_EHIP;
     e = plan_init(p);
-    for (int r = 0; r < G.r_cap && e == hipSuccess; ++r) e = plan_round(p, r, base + r);
+    for (int r = 0; r < G.r_cap && e == hipSuccess; ++r) e = plan_round(p, r);
     hipGraph_t graph = nullptr;
     const hipError_t e2 = hipStreamEndCapture(G.stream, &graph);
     if (e != hipSuccess || e2 != hipSuccess || !graph) {

@@ -87,12 +87,12 @@ struct DevGraph {
 };
 
 // Device view of a workspace: frontier flags (one byte per vertex, one per
-// 64-vertex tile), two generations; the round stamp of heavy frontier rows;
-// control; stats.
+// 64-vertex tile), two generations; the heavy frontier rows of a round as a
+// bit per vertex, two generations; control; stats.
 struct DevWs {
     unsigned char* vflag[2];
     unsigned char* tflag[2];
-    int* hstamp;  // [n]: stamp of the last round that had the row on its frontier
+    unsigned* hbits[2];  // [(n + 31) / 32] each: round r marks its heavy rows in hbits[r & 1]
     Ctl* ctl;
     Stat* stat;
     int* pcount;  // [3][2][kMaxStatBlocks]: frontier size pushed per block of round r % 3
@@ -108,8 +108,7 @@ struct Round {
     const int* sources;  // device list of sources of a multi-source traversal
     int nsrc;
     int r;       // round (sweep, level) index
-    int stamp;   // r + a per-workspace epoch that grows across traversals
-    int epoch;   // stamp of round 0 of this traversal
+    int epoch;   // tag of this traversal: grows across the traversals of a workspace
     int* host_done; // pinned host word: set to `epoch` by the kernel that finds the end
     int mapping; // Map
     int jump;    // CC: apply the label[label[v]] shortcut

@@ -430,6 +430,29 @@ __device__ __forceinline__ void push(const Round& R, int nxt, int t) {
     R.ws.tflag[nxt][t >> 6] = 1;
 }
 
+// Heavy frontier rows: round r sets row u's bit in hbits[r & 1] (an atomic
+// OR that returns nothing) and the chunk kernel of the same round serves the
+// chunks of the rows whose bit is set.  The bits fit in the dies' L2 (512 KB
+// for 4M vertices), so the chunk kernel's check of every chunk is a cached
+// load; the round kernel of round r clears the bits of round r-1 (its chunk
+// kernel has completed) so that round r+1 finds them clear.
+__device__ __forceinline__ void mark_heavy(const Round& R, int u) {
+    atomicOr(&R.ws.hbits[R.r & 1][u >> 5], 1u << (u & 31));
+}
+
+__device__ __forceinline__ bool heavy_marked(const Round& R, int u) {
+    return (R.ws.hbits[R.r & 1][u >> 5] >> (u & 31)) & 1u;
+}
+
+__device__ __forceinline__ void clear_prev_heavy(const Round& R) {
+    if (R.g.n_hchunks == 0 && R.g.n_shchunks == 0) return;  // no heavy row to mark
+    const long long words = ((long long)R.g.n + 31) / 32;
+    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long tt = (long long)gridDim.x * blockDim.x;
+    unsigned* b = R.ws.hbits[(R.r + 1) & 1];
+    for (long long i = tid; i < words; i += tt) b[i] = 0;
+}
+
 // ------------------------------------------------------ local expansion ----
 // A worklist round with local expansion (Round::hops > 0) lets a wavefront
 // serve again, within the same round, the vertices it has just lowered: a
@@ -441,25 +464,33 @@ __device__ __forceinline__ void push(const Round& R, int nxt, int t) {
 // wrote is safe: if another lane lowered it further since, that lane put it
 // on a list or the frontier itself.  On a high-diameter graph this advances
 // the frontier several steps per launch; the fixpoint is the same.
-// 256 entries, served 64 (one per lane) at a time: on a grid a served vertex
-// lowers one or two new heads, so a list of 64 overflowed to the next round
-// at once (grid4096 SSSP: 586 rounds with 64 entries, 437 with 128 or 256;
-// er23 SSSP 3.47 / 3.40 / 3.29 ms)
-constexpr int kLocalCap = 256;
+// The list holds (vertex, value, row begin, row end): the row offsets of a
+// head that may be lowered below the bound are loaded together with its
+// atomic, so that serving the
+// entry in the next pass starts at the column loads -- one dependent load
+// fewer per pass.  128 entries per list, served 64 (one per lane) at a time:
+// on a grid a served vertex lowers one or two new heads, so a list of 64
+// overflowed to the next round at once (grid4096 SSSP: 586 rounds with 64
+// entries, 437 with 128 or 256; er23 SSSP 3.47 / 3.40 / 3.29 ms with 64 /
+// 128 / 256 two-word entries).
+constexpr int kLocalCap = 128;
 
 // DIRECT: no head-value load before the atomic (the atomic's returned value
 // decides): one round trip fewer per edge.  Used for BFS passes over the
 // wavefront's own list, whose vertices were just reached and mostly reach
 // new heads in turn (grid4096 BFS 13.5 -> 11.6 ms); for SSSP most heads do
 // not improve and the extra atomics cost more (rmat22 and er23 8-10% slower).
+// The atomics of a lane's U edges are all issued before the first returned
+// value is looked at (then the ballots and list writes), so their round
+// trips overlap instead of following one another.
 template <int A, int U, bool DIRECT = false>
-__device__ __forceinline__ void relax_batch_local(const Round& R, const int* col,
+__device__ __forceinline__ void relax_batch_local(const Round& R, const int* row, const int* col,
                                                   const int (&e)[U], const int (&sv)[U],
                                                   const bool (&ok)[U], int nxt, Acc& acc,
-                                                  int bound, int2* lst, int& ln) {
+                                                  int bound, int4* lst, int& ln) {
     int* val = R.val;
     const int lane = threadIdx.x & 63;
-    int t[U], wt[U], cur[U];
+    int t[U], wt[U], cur[U], nv[U], old[U], rb[U], re[U];
 #pragma unroll
     for (int j = 0; j < U; ++j) t[j] = ok[j] ? col[e[j]] : 0;
     if (A == SSSP) {
@@ -470,30 +501,44 @@ __device__ __forceinline__ void relax_batch_local(const Round& R, const int* col
     for (int j = 0; j < U; ++j) cur[j] = ok[j] ? (DIRECT ? kInf : val[t[j]]) : 0;
 #pragma unroll
     for (int j = 0; j < U; ++j) {
-        bool hit = false;
-        int nv = 0;
+        nv[j] = 0;
+        old[j] = 0;  // no atomic: counts as no decrease
+        rb[j] = re[j] = 0;
         if (ok[j]) {
             acc.e++;
+            bool go;
             if (A == SSSP) {
                 const unsigned cand = (unsigned)sv[j] + (unsigned)wt[j];
-                if (cand < (unsigned)cur[j]) {
-                    nv = (int)cand;
-                    hit = nv < atomicMin(&val[t[j]], nv);
-                }
+                go = cand < (unsigned)cur[j];
+                nv[j] = (int)cand;
             } else {
-                nv = A == BFS ? sv[j] + 1 : sv[j];
-                if (nv < cur[j]) hit = nv < atomicMin(&val[t[j]], nv);
+                nv[j] = A == BFS ? sv[j] + 1 : sv[j];
+                go = nv[j] < cur[j];
+            }
+            if (go) {
+                // only a head below the bound can go to the list
+                if (nv[j] < bound) {
+                    rb[j] = row[t[j]];
+                    re[j] = row[t[j] + 1];
+                }
+                old[j] = atomicMin(&val[t[j]], nv[j]);
+            } else {
+                old[j] = nv[j];
             }
         }
-        const bool keep = hit && nv < bound;
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+        const bool hit = ok[j] && nv[j] < old[j];
+        const bool keep = hit && nv[j] < bound;
         const unsigned long long km = __ballot(keep);
         const int pos = ln + __popcll(km & ((1ull << lane) - 1));
         if (keep && pos < kLocalCap) {
-            lst[pos] = make_int2(t[j], nv);
+            lst[pos] = make_int4(t[j], nv[j], rb[j], re[j]);
         } else if (hit) {
             push(R, nxt, t[j]);
             acc.p++;
-            if (nv < bound) acc.nr = 1;
+            if (nv[j] < bound) acc.nr = 1;
         }
         ln = min(ln + __popcll(km), kLocalCap);
     }
@@ -501,9 +546,10 @@ __device__ __forceinline__ void relax_batch_local(const Round& R, const int* col
 
 // wave_relax_rows with relax_batch_local.
 template <int A, int U, bool DIRECT = false>
-__device__ __forceinline__ void wave_relax_rows_local(const Round& R, const int* col, int beg,
-                                                      int deg, int sv, int nxt, Acc& acc,
-                                                      int bound, int2* lst, int& ln) {
+__device__ __forceinline__ void wave_relax_rows_local(const Round& R, const int* row,
+                                                      const int* col, int beg, int deg, int sv,
+                                                      int nxt, Acc& acc, int bound, int4* lst,
+                                                      int& ln) {
     const int lane = threadIdx.x & 63;
     const int incl = wave_incl_scan(deg);
     const int total = __shfl(incl, 63, 64);
@@ -524,7 +570,7 @@ __device__ __forceinline__ void wave_relax_rows_local(const Round& R, const int*
             s[j] = __shfl(sv, o, 64);
             ok[j] = k < total;
         }
-        relax_batch_local<A, U, DIRECT>(R, col, e, s, ok, nxt, acc, bound, lst, ln);
+        relax_batch_local<A, U, DIRECT>(R, row, col, e, s, ok, nxt, acc, bound, lst, ln);
     }
 }
 
@@ -550,6 +596,10 @@ __global__ __launch_bounds__(256) void k_init(Round R, int algo, int async) {
                 R.ws.tflag[1][t] = 0;
             }
         }
+    }
+    if (async) {
+        const long long words = ((long long)n + 31) / 32;
+        for (long long i = tid; i < words; i += tt) R.ws.hbits[0][i] = R.ws.hbits[1][i] = 0;
     }
     for (long long i = tid; i < kKinds * kMaxStatBlocks; i += tt) R.ws.stat[i] = Stat{0, 0, 0, 0, 0};
     if (tid == 0) *R.ws.ctl = Ctl{};
@@ -894,7 +944,7 @@ __global__ __launch_bounds__(256) void k_esync(Round R) {
 // flagged tiles it finds.
 // Serve the np vertices listed in pend[0, np) of this wavefront (lane k takes
 // entry k): the tail value, far vertices of the near-far schedule back onto
-// the frontier, heavy rows stamped for the chunk kernel, light rows walked by
+// the frontier, heavy rows marked for the chunk kernel, light rows walked by
 // the balanced mapping.
 template <int A, int U>
 __device__ __forceinline__ void serve_list(const Round& R, const int* row, const int* col,
@@ -921,7 +971,7 @@ __device__ __forceinline__ void serve_list(const Round& R, const int* row, const
         }
     }
     const bool hv = on && re - rb > R.g.heavy;
-    if (hv) R.ws.hstamp[u] = R.stamp;
+    if (hv) mark_heavy(R, u);
     wave_relax_rows<A, true, U>(R, col, on && !hv ? rb : 0, on && !hv ? re - rb : 0, sv, nxt, acc,
                                 bound);
 }
@@ -1059,6 +1109,7 @@ __device__ __forceinline__ void vasync_body(const Round& R, Acc& acc, bool nf, i
 template <int A, int MAP, bool NF = false>
 __global__ __launch_bounds__(256) void k_vasync(Round R) {
     if (!round_begin(R)) return;
+    clear_prev_heavy(R);
     const bool nf = NF;
     const int bound = nf ? nearfar_bound(R) : kInf;
     Acc acc;
@@ -1070,11 +1121,12 @@ __global__ __launch_bounds__(256) void k_vasync(Round R) {
 // serve_list under local expansion: the frontier vertices in pend (their
 // current values read here; BFS too, since levels differ within a round),
 // then up to R.hops passes over the wavefront's own list.  lb holds two
-// lists of kLocalCap (vertex, value) entries that the passes alternate.
+// lists of kLocalCap (vertex, value, row begin, row end) entries that the
+// passes alternate.
 template <int A, int U>
 __device__ __forceinline__ void serve_local(const Round& R, const int* row, const int* col,
                                             const int* pend, int np, int nxt, bool nf, int bound,
-                                            Acc& acc, int2* lb) {
+                                            Acc& acc, int4* lb) {
     const int lane = threadIdx.x & 63;
     __builtin_amdgcn_wave_barrier();
     int u = lane < np ? pend[lane] : -1;
@@ -1095,19 +1147,19 @@ __device__ __forceinline__ void serve_local(const Round& R, const int* row, cons
         }
     }
     bool hv = on && re - rb > R.g.heavy;
-    if (hv) R.ws.hstamp[u] = R.stamp;
+    if (hv) mark_heavy(R, u);
     int ln = 0;
-    wave_relax_rows_local<A, U>(R, col, on && !hv ? rb : 0, on && !hv ? re - rb : 0, sv, nxt, acc,
-                                bound, lb, ln);
+    wave_relax_rows_local<A, U>(R, row, col, on && !hv ? rb : 0, on && !hv ? re - rb : 0, sv,
+                                nxt, acc, bound, lb, ln);
     for (int pass = 1; ln > 0; ++pass) {
-        const int2* cur = lb + ((pass - 1) & 1) * kLocalCap;
-        int2* nx = lb + (pass & 1) * kLocalCap;
+        const int4* cur = lb + ((pass - 1) & 1) * kLocalCap;
+        int4* nx = lb + (pass & 1) * kLocalCap;
         const int cn = ln;
         ln = 0;
         // the list is served 64 entries (one per lane) at a time
         for (int base = 0; base < cn; base += 64) {
             __builtin_amdgcn_wave_barrier();
-            const int2 x = base + lane < cn ? cur[base + lane] : make_int2(-1, 0);
+            const int4 x = base + lane < cn ? cur[base + lane] : make_int4(-1, 0, 0, 0);
             __builtin_amdgcn_wave_barrier();
             if (pass > R.hops) {
                 // out of passes: the list goes to the next frontier
@@ -1121,15 +1173,12 @@ __device__ __forceinline__ void serve_local(const Round& R, const int* row, cons
             u = x.x;
             sv = x.y;
             on = u >= 0;
-            rb = re = 0;
-            if (on) {
-                rb = row[u];
-                re = row[u + 1];
-                acc.v++;
-            }
+            rb = x.z;  // loaded with the atomic that put u on the list
+            re = x.w;
+            if (on) acc.v++;
             hv = on && re - rb > R.g.heavy;
-            if (hv) R.ws.hstamp[u] = R.stamp;
-            wave_relax_rows_local<A, U, A == BFS>(R, col, on && !hv ? rb : 0,
+            if (hv) mark_heavy(R, u);
+            wave_relax_rows_local<A, U, A == BFS>(R, row, col, on && !hv ? rb : 0,
                                                   on && !hv ? re - rb : 0, sv, nxt, acc, bound,
                                                   nx, ln);
         }
@@ -1154,9 +1203,9 @@ __device__ __forceinline__ void vasync_local(const Round& R, Acc& acc, bool nf, 
     const long long ntiles = (n + 63) / 64;
     const long long nitems = (ntiles + 63) / 64 * kParts;
     __shared__ int s_pend[4][64];  // blocks of 256 threads: four wavefronts
-    __shared__ int2 s_loc[4][2 * kLocalCap];
+    __shared__ int4 s_loc[4][2 * kLocalCap];
     int* pend = s_pend[threadIdx.x >> 6];
-    int2* lb = s_loc[threadIdx.x >> 6];
+    int4* lb = s_loc[threadIdx.x >> 6];
     int np = 0;
     for (long long it = gw; it < nitems; it += tw) {
         const long long st = it / kParts;
@@ -1189,6 +1238,7 @@ __device__ __forceinline__ void vasync_local(const Round& R, Acc& acc, bool nf, 
 template <int A, bool NF>
 __global__ __launch_bounds__(256) void k_vlocal(Round R) {
     if (!round_begin(R)) return;
+    clear_prev_heavy(R);
     const int bound = NF ? nearfar_bound(R) : kInf;
     Acc acc;
     // the plain rounds' edges in flight: eight (near-far) spill here
@@ -1204,6 +1254,7 @@ __global__ __launch_bounds__(256) void k_vlocal(Round R) {
 template <int A>
 __global__ __launch_bounds__(256) void k_easync(Round R) {
     if (!round_begin(R)) return;
+    clear_prev_heavy(R);
     const DevGraph& g = R.g;
     const int* row = A == CC ? g.srow : g.row;
     const int* col = A == CC ? g.scol : g.col;
@@ -1246,7 +1297,7 @@ __global__ __launch_bounds__(256) void k_easync(Round R) {
             }
             const bool light = in && re - rb <= g.heavy;
             // heavy rows are served by the chunk kernel of this round
-            if (on && !light) R.ws.hstamp[u] = R.stamp;
+            if (on && !light) mark_heavy(R, u);
             const unsigned long long am = __ballot(on && light);
             if (am == 0) continue;
             // walk maximal runs of light rows that contain a flagged row
@@ -1291,6 +1342,7 @@ __global__ __launch_bounds__(256) void k_easync(Round R) {
 // every block computes the same sum, so the direction is grid-uniform.
 __global__ __launch_bounds__(256) void k_bfs_diropt(Round R) {
     if (!round_begin(R)) return;
+    clear_prev_heavy(R);
     const DevGraph& g = R.g;
     Ctl* ctl = R.ws.ctl;
     const int n = g.n;
@@ -1531,6 +1583,7 @@ __device__ void pull_round(const Round& R, Acc& acc) {
 // light rows and reads each in-edge's tail flag before its value.
 __global__ __launch_bounds__(256) void k_sssp_diropt(Round R) {
     if (!round_begin(R)) return;
+    clear_prev_heavy(R);
     Ctl* ctl = R.ws.ctl;
     const bool pull = R.r > 0 && prev_front(R) * kSsspPullRatio > (long long)R.g.m;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1545,9 +1598,9 @@ __global__ __launch_bounds__(256) void k_sssp_diropt(Round R) {
     block_finish(R, acc, R.r % 3, KIND_ROUND);
 }
 
-// Heavy rows of the frontier: the light kernel of the same round stamped
-// them; every wavefront walks the static chunk list and serves the chunks
-// whose row carries this round's stamp.
+// Heavy rows of the frontier: the light kernel of the same round marked
+// them in the round's bitmap; every wavefront walks the static chunk list
+// and serves the chunks whose row is marked.
 template <int A>
 __global__ __launch_bounds__(256) void k_heavy(Round R) {
     Ctl* ctl = R.ws.ctl;
@@ -1564,7 +1617,7 @@ __global__ __launch_bounds__(256) void k_heavy(Round R) {
     const int lane = threadIdx.x & 63;
     const bool nf = A == SSSP && R.delta > 0;
     const int bound = nf ? *(volatile int*)&ctl->bound[R.r % 3] : kInf;
-    // a pulling BFS round or a sweeping CC round stamps no heavy row:
+    // a pulling BFS round or a sweeping CC round marks no heavy row:
     // nothing to serve
     const bool pulled = (A == BFS || ((A == CC || A == SSSP) && R.fedges)) &&
                         *(volatile int*)&ctl->pull[R.r % 3] != 0;
@@ -1572,7 +1625,7 @@ __global__ __launch_bounds__(256) void k_heavy(Round R) {
     // an SSSP pull round read the frontier generation without consuming it:
     // it is cleared here, once the round kernel has completed
     if (A == SSSP && pulled) clear_generation(R, R.r & 1);
-    // 64 chunk stamps are checked at once, then the wavefront serves the
+    // 64 chunks' rows are checked at once, then the wavefront serves the
     // chunks that match.  The 64 chunks of one check are spread over the
     // list with the stride of the whole grid, so that the chunks of one long
     // row (which sit next to each other) land on different wavefronts, and
@@ -1586,7 +1639,7 @@ __global__ __launch_bounds__(256) void k_heavy(Round R) {
         bool on = false;
         if (it < nch) {
             c = chunks[it];
-            on = R.ws.hstamp[c.x] == R.stamp;
+            on = heavy_marked(R, c.x);
         }
         // each lane fetches its own matched chunk's end now, all in
         // parallel, instead of one chunk at a time below.  The tail value is
@@ -1652,6 +1705,7 @@ __global__ __launch_bounds__(256) void k_jump(Round R) {
 // changed after its edges were last read) and clears the frontier it skips.
 __global__ __launch_bounds__(256) void k_cc_diropt(Round R) {
     if (!round_begin(R)) return;
+    clear_prev_heavy(R);
     Ctl* ctl = R.ws.ctl;
     const long long front = R.r > 0 ? prev_front(R) : (long long)R.g.ms;
     const bool sweep = front * kSweepRatio > (long long)R.g.ms || R.r == 0;

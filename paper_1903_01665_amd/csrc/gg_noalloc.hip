@@ -1,7 +1,7 @@
 // gg_noalloc.hip -- BFS without any allocation in the call (gg_bfs_noalloc
 // in include/gg.h), for callers that cannot allocate device memory.
 //
-// The traversal's scratch memory -- frontier flags, round stamps, the
+// The traversal's scratch memory -- frontier flags, heavy-row bits, the
 // control block, per-block counters and push counts, the end word -- lives
 // in one file-scope device array of fixed size instead of a workspace.  Each
 // device holds its own copy of the array; its address on a device is taken
@@ -29,8 +29,9 @@ constexpr long long align256(long long x) { return (x + 255) & ~255LL; }
 // byte offsets of the parts of the array
 constexpr long long kOffVflag = 0;
 constexpr long long kOffTflag = 2 * kNaVBytes;
-constexpr long long kOffStamp = align256(kOffTflag + 2 * kNaTBytes);
-constexpr long long kOffCtl = align256(kOffStamp + 4 * kNaMaxN);
+constexpr long long kNaHWords = (kNaMaxN + 31) / 32;  // heavy-row bits, one generation
+constexpr long long kOffHbits = align256(kOffTflag + 2 * kNaTBytes);
+constexpr long long kOffCtl = align256(kOffHbits + 4 * 2 * kNaHWords);
 constexpr long long kOffStat = align256(kOffCtl + (long long)sizeof(Ctl));
 constexpr long long kOffCount = align256(kOffStat + (long long)sizeof(Stat) * kKinds * kMaxStatBlocks);
 constexpr long long kOffDone = align256(kOffCount + 4LL * 3 * 2 * kMaxStatBlocks);
@@ -38,7 +39,7 @@ constexpr long long kNaBytes = align256(kOffDone + 16);
 
 }  // namespace
 
-// about 26 MB on every device the library runs on, held until the process ends
+// about 10 MB on every device the library runs on, held until the process ends
 static __device__ __align__(256) unsigned char scratch[kNaBytes];
 
 namespace {
@@ -54,23 +55,20 @@ constexpr int kMaxDevices = 64;
 struct NaDevice {
     bool ready = false;
     unsigned char* ptr = nullptr;  // the device address of `scratch` on this device
-    int epoch = 0;                 // round stamps of the next call start here
+    int epoch = 0;                 // tag of the next call
 };
 
 std::mutex g_na_mu;
 NaDevice g_na[kMaxDevices];
 
-// Address of this device's copy of the array, and round stamps reset to
-// "never" (-1), the first time a call runs on the device.
-int na_setup(int dev, hipStream_t s) {
+// Address of this device's copy of the array, the first time a call runs on
+// the device.
+int na_setup(int dev) {
     NaDevice& d = g_na[dev];
     if (d.ready) return GG_OK;
     void* p = nullptr;
     if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return GG_EHIP;
     d.ptr = static_cast<unsigned char*>(p);
-    hipLaunchKernelGGL(k_fill_words, dim3(1024), dim3(256), 0, s,
-                       reinterpret_cast<int*>(d.ptr + kOffStamp), kNaMaxN, -1);
-    if (hipGetLastError() != hipSuccess) return GG_EHIP;
     d.epoch = 0;
     d.ready = true;
     return GG_OK;
@@ -87,7 +85,7 @@ extern "C" int gg_bfs_noalloc(gg_graph g, int32_t source, const gg_opts* opts,
     if (dev < 0 || dev >= kMaxDevices) return GG_ENOTSUP;
     const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     std::lock_guard<std::mutex> lk(g_na_mu);
-    int rc = na_setup(dev, s);
+    int rc = na_setup(dev);
     if (rc != GG_OK) return rc;
     NaDevice& D = g_na[dev];
 
@@ -98,7 +96,8 @@ extern "C" int gg_bfs_noalloc(gg_graph g, int32_t source, const gg_opts* opts,
     w.dev.vflag[1] = D.ptr + kOffVflag + kNaVBytes;
     w.dev.tflag[0] = D.ptr + kOffTflag;
     w.dev.tflag[1] = D.ptr + kOffTflag + kNaTBytes;
-    w.dev.hstamp = reinterpret_cast<int*>(D.ptr + kOffStamp);
+    w.dev.hbits[0] = reinterpret_cast<unsigned*>(D.ptr + kOffHbits);
+    w.dev.hbits[1] = w.dev.hbits[0] + kNaHWords;
     w.dev.ctl = reinterpret_cast<Ctl*>(D.ptr + kOffCtl);
     w.dev.stat = reinterpret_cast<Stat*>(D.ptr + kOffStat);
     w.dev.pcount = reinterpret_cast<int*>(D.ptr + kOffCount);
@@ -111,16 +110,11 @@ extern "C" int gg_bfs_noalloc(gg_graph g, int32_t source, const gg_opts* opts,
     // the end word is in the array: read back with a copy, not polled
     p.R.host_done = done_word;
 
-    // round stamps: restart (stamps reset to -1) long before the int range ends
+    // the call's tag (tags restart long before the int range ends)
     const long long span = (long long)g->n + 3;
-    if ((long long)D.epoch + span > (1LL << 30)) {
-        hipLaunchKernelGGL(k_fill_words, dim3(1024), dim3(256), 0, s, w.dev.hstamp, kNaMaxN, -1);
-        HIPCHK(g, hipGetLastError());
-        D.epoch = 0;
-    }
+    if ((long long)D.epoch + span > (1LL << 30)) D.epoch = 0;
     const int base = D.epoch;
     p.R.epoch = base;
-    p.R.stamp = base;
     // the end word holds the last call's tag: reset it before any round runs
     hipLaunchKernelGGL(k_fill_words, dim3(1), dim3(64), 0, s, done_word, 1LL, -1);
     HIPCHK(g, hipGetLastError());
@@ -135,7 +129,7 @@ extern "C" int gg_bfs_noalloc(gg_graph g, int32_t source, const gg_opts* opts,
     int batch = 2, status = GG_OK, seen = -1;
     for (;;) {
         const long long stop = std::min(r + batch, limit);
-        for (; r < stop; ++r) HIPCHK(g, plan_round(p, (int)r, base + (int)r));
+        for (; r < stop; ++r) HIPCHK(g, plan_round(p, (int)r));
         HIPCHK(g, hipMemcpyAsync(&seen, done_word, sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(g, hipStreamSynchronize(s));
         if (seen == base) break;

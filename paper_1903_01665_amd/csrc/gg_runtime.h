@@ -173,7 +173,7 @@ int plan_make(gg_graph g, gg_ws ws, int algo, int source, const int* sources_dev
 // Enqueue the init kernel (and the seed kernel of a multi-source plan).
 hipError_t plan_init(Plan& p);
 // Enqueue round r (round kernel, heavy-chunk or shortcut kernel as needed).
-hipError_t plan_round(Plan& p, int r, int stamp);
+hipError_t plan_round(Plan& p, int r);
 // Reserve `span` round stamps on a workspace; returns the first.
 int reserve_stamps(gg_ws ws, hipStream_t s, long long span, hipError_t* err);
 // Resumable eager driver of one traversal (see gg_api.hip).

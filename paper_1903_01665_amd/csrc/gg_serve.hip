@@ -1,8 +1,8 @@
 // gg_serve.hip -- serving loop: SSSP/BFS queries admitted as they arrive and
 // advanced together on a pool of streams (declared in include/gg.h).
 //
-// A query needs a workspace of its graph (per-query frontier flags, round
-// stamps, control block) and a stream.  Workspaces are pooled per graph and
+// A query needs a workspace of its graph (per-query frontier flags,
+// heavy-row bits, control block) and a stream.  Workspaces are pooled per graph and
 // reused; the bytes of the workspaces held by queries in flight are bounded
 // by the memory budget.  Admission is first-come first-served: when the
 // head of the queue does not fit (no slot, or its state would exceed the
@@ -51,7 +51,8 @@ long long ws_bytes_of(gg_graph g) {
     const long long ntiles = (g->n + 63) / 64;
     const long long vbytes = ((ntiles + 63) / 64) * 64 * 64;
     const long long tbytes = ((ntiles + 63) / 64) * 64;
-    return 2 * (vbytes + tbytes) + 4LL * g->n + (long long)sizeof(Ctl) +
+    const long long hwords = (g->n + 31) / 32;
+    return 2 * (vbytes + tbytes) + 2 * 4LL * hwords + (long long)sizeof(Ctl) +
            (long long)sizeof(Stat) * kKinds * kMaxStatBlocks + 4LL * 3 * 2 * kMaxStatBlocks;
 }
 

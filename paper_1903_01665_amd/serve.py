@@ -133,6 +133,7 @@ def run_served(hosts, trace, slots=32, mem_budget=8 << 30, upload_every=5.0, n_p
     nxt = 0
     done = 0
     nq = len(trace.t)
+    next_log = 10.0
     while done < nq:
         now = time.perf_counter() - t0
         while nxt < nq and trace.t[nxt] <= now:
@@ -159,6 +160,9 @@ def run_served(hosts, trace, slots=32, mem_budget=8 << 30, upload_every=5.0, n_p
                 service[k] = td - ta
             free_bufs[gi].append(b)
             done += 1
+        if log is not None and tnow >= next_log:
+            log(f"[serve] served: {tnow:.0f}s, {done}/{nq} queries done")
+            next_log += 10.0
         if not res and nxt < nq and trace.t[nxt] > now + 0.0005:
             time.sleep(0.0001)
     wall = time.perf_counter() - t0
@@ -169,7 +173,7 @@ def run_served(hosts, trace, slots=32, mem_budget=8 << 30, upload_every=5.0, n_p
     return lat, status, wall
 
 
-def run_plain(hosts, trace, n_pool=None, upload_every=5.0, service=None):
+def run_plain(hosts, trace, n_pool=None, upload_every=5.0, service=None, log=None):
     """One blocking query at a time in arrival order, graphs uploaded when
     they first appear in the trace (upload time not charged to queries).
     With `service` the time of each call is stored there."""
@@ -180,6 +184,7 @@ def run_plain(hosts, trace, n_pool=None, upload_every=5.0, service=None):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     upload_s = 0.0
+    next_log = 10.0
     for k in range(len(trace.t)):
         gi = int(trace.graph[k])
         if gi not in graphs:
@@ -202,6 +207,9 @@ def run_plain(hosts, trace, n_pool=None, upload_every=5.0, service=None):
         if service is not None:
             service[k] = tn - tq
         lat[k] = tn - t0 - upload_s - trace.t[k]
+        if log is not None and tn - t0 >= next_log:
+            log(f"[serve] plain: {tn - t0:.0f}s, {k + 1}/{len(trace.t)} queries done")
+            next_log += 10.0
     wall = time.perf_counter() - t0 - upload_s
     for g in graphs.values():
         g.free()
