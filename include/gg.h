@@ -123,6 +123,26 @@ typedef enum { GG_ALGO_SSSP = 0, GG_ALGO_BFS = 1, GG_ALGO_CC = 2, GG_ALGO_MSF = 
 #define GG_SYMMETRIC 4u       /* the input already holds v->u for every u->v */
 #define GG_TRANSPOSE 8u       /* also build the weighted in-edge CSR that the pull rounds of
                                  SSSP's per-round schedule read (8 bytes per edge) */
+#define GG_RENUMBER 16u       /* store the graph with its vertices renumbered, hottest first */
+#define GG_KEEP_ORDER 32u     /* never renumber */
+
+/* Vertex order in device memory.  The traversals gather the value of an
+ * edge's head once per edge, so a vertex is gathered as often as it has
+ * in-edges.  On a skewed graph (largest out-degree >= 128 x the mean) of at
+ * least 2^20 edges, and on any graph uploaded with GG_RENUMBER, the library
+ * stores the graph with its vertices numbered by descending total degree
+ * (out + in; ties in the caller's order), so that the values gathered most
+ * often share a few cache lines that stay in each die's L2.  Edges keep
+ * their order within a row.  Nothing of this shows at the interface: every
+ * vertex id and edge index passed in or written out is the caller's
+ * (sources, dist/level/label outputs -- a CC label is the smallest of the
+ * caller's ids in the component -- and the forest flags of gg_msf).  A
+ * traversal of a renumbered graph computes into workspace memory and ends
+ * with one pass that writes out_dev in the caller's order (CC: a
+ * per-component minimum of the caller's ids, then that pass); the
+ * workspace holds 8 more bytes per vertex for it, the graph 4 bytes per
+ * vertex (both orders) and 8 bytes per edge (the forest's edge map).
+ * GG_KEEP_ORDER turns renumbering off; gg_graph_order reports it. */
 
 typedef struct gg_graph_s* gg_graph;
 typedef struct gg_ws_s* gg_ws;
@@ -167,6 +187,15 @@ typedef struct {
                                 shortens high-diameter graphs) */
 #define GG_OPT_PROFILE 2u    /* record a HIP event pair around every kernel launch of the
                                 call (on the caller's stream); read with gg_last_profile */
+/* SSSP with local expansion (hops > 0): how the passes over a wavefront's
+ * own list relax.  Checked: a plain load of the head value first, the atomic
+ * minimum only when it would lower it.  Direct: the atomic minimum at once
+ * (one memory round trip fewer per pass, one atomic more per edge that does
+ * not lower its head).  Neither flag: direct on graphs that gg_graph_probe
+ * found deep (depth class 2), where rounds are chains of passes run by few
+ * wavefronts, checked otherwise.  The result is the same either way. */
+#define GG_OPT_LISTS_CHECKED 4u
+#define GG_OPT_LISTS_DIRECT 8u
 
 /* Statistics of the last traversal run on a workspace. */
 typedef struct {
@@ -231,6 +260,10 @@ int gg_graph_info(gg_graph g, int32_t* n, int64_t* m, int32_t* max_out_degree,
 
 /* First HIP failure recorded on the handle (GG_OK if none). */
 int gg_graph_error(gg_graph g);
+
+/* *renumbered = 1 when the graph is stored in the library's own vertex
+ * order (see GG_RENUMBER), else 0. */
+int gg_graph_order(gg_graph g, int32_t* renumbered);
 
 /* SSSP from `source` (Algorithms 1-2).  dist_out_dev: device int32[n],
  * caller-owned, overwritten.  GG_EINVAL: source outside [0, n), NULL output,
@@ -319,8 +352,9 @@ int gg_ticket_free(gg_ticket t);
 /* BFS for callers that cannot allocate memory (code that must not call
  * hipMalloc, such as tight serving loops or hosts that forbid it): the same
  * traversal as gg_bfs_ex on the graph's arrays, with the scratch memory that
- * a workspace holds (frontier flags, heavy-row bits, control and counters)
- * taken from one fixed device array of the library, about 10 MB, that each
+ * a workspace holds (frontier flags, heavy-row bits, control and counters,
+ * the levels of a renumbered graph in the library's order) taken from one
+ * fixed device array of the library, about 27 MB, that each
  * GPU holds from the first call on it until the process ends.  The call
  * allocates nothing: no device or host memory, no events.  Arguments as
  * gg_bfs_ex without a workspace; GG_OPT_PROFILE is ignored and gg_last_stats

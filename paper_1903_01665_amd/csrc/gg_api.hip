@@ -62,6 +62,8 @@ void free_ws_arrays(gg_ws_s* ws) {
     if (ws->msf_best) (void)hipFree(ws->msf_best);
     ws->msf_parent = nullptr;
     ws->msf_best = nullptr;
+    dfree(ws->rval);
+    dfree(ws->rmin);
     for (auto& e : ws->ev)
         if (e) (void)hipEventDestroy(e);
     for (auto& e : ws->pev)
@@ -91,6 +93,8 @@ int make_ws(gg_graph g, gg_ws_s** out) {
     if (e == hipSuccess) e = dalloc(&ws->dev.ctl, 1);
     if (e == hipSuccess) e = dalloc(&ws->dev.stat, (size_t)kKinds * kMaxStatBlocks);
     if (e == hipSuccess) e = dalloc(&ws->dev.pcount, (size_t)3 * 2 * kMaxStatBlocks);
+    if (e == hipSuccess && g->renumbered) e = dalloc(&ws->rval, (size_t)g->n);
+    if (e == hipSuccess && g->renumbered) e = dalloc(&ws->rmin, (size_t)g->n);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&ws->h_done), 4 * sizeof(int));
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ws->ev[0], hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ws->ev[1], hipEventDisableTiming);
@@ -165,6 +169,95 @@ HostCheck check_host(const int* col, const int* w, long long m, int n) {
 
 // Graphs with fewer edges keep the single edge list for the edge sweep.
 constexpr long long kPartMinEdges = 1LL << 20;
+
+// Renumber an uploaded CSR (device row/col/w of the handle; hrow, the host
+// copy of the offsets): new ids by descending total degree, ties in the
+// caller's order (a stable counting sort on the host), each row's edges
+// kept in order.  Leaves the renumbered arrays in the handle, hrow and hin
+// (in-degrees) in the new order, the id maps, and -- for a weighted graph,
+// the only kind a forest is built on -- the edge maps.  tmp: n + 8 ints.
+int renumber_graph(gg_graph g, std::vector<int>& hrow, std::vector<int>& hin, int* tmp,
+                   hipStream_t s) {
+    const int n = g->n;
+    const long long m = g->m;
+    auto grid = [&](long long units) {
+        return (int)std::max(1LL, std::min<long long>(units, device().max_blocks));
+    };
+    hin.assign((size_t)n, 0);
+    hipError_t e = hipMemsetAsync(tmp, 0, sizeof(int) * n, s);
+    if (e == hipSuccess)
+        e = launch_count_in(g->col, (int)m, tmp, grid((m + kBlock - 1) / kBlock), kBlock, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(hin.data(), tmp, sizeof(int) * n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return GG_EHIP;
+    // keys (out + in degree, < 2^32) and the order: counting sort when the
+    // largest key is small against n, else a stable comparison sort
+    std::vector<long long> key((size_t)n);
+    long long kmax = 0;
+    for (int v = 0; v < n; ++v) {
+        key[v] = (long long)(hrow[v + 1] - hrow[v]) + hin[v];
+        kmax = std::max(kmax, key[v]);
+    }
+    std::vector<int> oldid((size_t)n), newid((size_t)n);
+    if (kmax <= 4LL * n + 1024) {
+        std::vector<int> start((size_t)kmax + 2, 0);
+        for (int v = 0; v < n; ++v) start[(size_t)(kmax - key[v]) + 1]++;
+        for (long long k = 1; k <= kmax + 1; ++k) start[(size_t)k] += start[(size_t)k - 1];
+        for (int v = 0; v < n; ++v) oldid[(size_t)start[(size_t)(kmax - key[v])]++] = v;
+    } else {
+        for (int v = 0; v < n; ++v) oldid[v] = v;
+        std::stable_sort(oldid.begin(), oldid.end(),
+                         [&](int a, int b) { return key[a] > key[b]; });
+    }
+    for (int k = 0; k < n; ++k) newid[(size_t)oldid[k]] = k;
+    std::vector<int> nrow((size_t)n + 1), nin((size_t)n);
+    nrow[0] = 0;
+    for (int k = 0; k < n; ++k) {
+        const int u = oldid[k];
+        nrow[(size_t)k + 1] = nrow[k] + (hrow[(size_t)u + 1] - hrow[u]);
+        nin[k] = hin[(size_t)u];
+    }
+    int *drow = nullptr, *dcol = nullptr, *dw = nullptr;
+    auto fail = [&](hipError_t x) {
+        (void)hipStreamSynchronize(s);
+        dfree(drow);
+        dfree(dcol);
+        dfree(dw);
+        return x == hipErrorOutOfMemory ? GG_ENOMEM : GG_EHIP;
+    };
+    e = dalloc(&g->newid, (size_t)n);
+    if (e == hipSuccess) e = dalloc(&g->oldid, (size_t)n);
+    if (e == hipSuccess) e = dalloc(&drow, (size_t)n + 1);
+    if (e == hipSuccess) e = dalloc(&dcol, (size_t)m);
+    if (e == hipSuccess && g->w) e = dalloc(&dw, (size_t)m);
+    if (e == hipSuccess && g->w) e = dalloc(&g->eorig, (size_t)m);
+    if (e == hipSuccess && g->w) e = dalloc(&g->epos, (size_t)m);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(g->newid, newid.data(), sizeof(int) * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(g->oldid, oldid.data(), sizeof(int) * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(drow, nrow.data(), sizeof(int) * ((size_t)n + 1), hipMemcpyHostToDevice, s);
+    // the caller's edge sources, then every edge to its new place
+    if (e == hipSuccess)
+        e = launch_fill_src(g->row, n, (int)m, g->src, grid((m + 4095) / 4096), kBlock, s);
+    if (e == hipSuccess)
+        e = launch_renumber(g->row, g->col, g->w, g->src, (int)m, g->newid, drow, dcol, dw,
+                            g->eorig, g->epos, grid((m + kBlock - 1) / kBlock), kBlock, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(e);
+    dfree(g->row);
+    dfree(g->col);
+    dfree(g->w);
+    g->row = drow;
+    g->col = dcol;
+    g->w = dw;
+    hrow.swap(nrow);
+    hin.swap(nin);
+    g->h_newid.swap(newid);
+    g->renumbered = true;
+    return GG_OK;
+}
 
 // The edge list again, cut into kXcd parts by head vertex with equal edge
 // counts (part boundaries at the in-degree quantiles), CSR order kept inside
@@ -261,6 +354,10 @@ void free_graph_arrays(gg_graph g) {
     dfree(g->src);
     dfree(g->hchunks);
     dfree(g->shchunks);
+    dfree(g->newid);
+    dfree(g->oldid);
+    dfree(g->eorig);
+    dfree(g->epos);
     g->srow = g->scol = g->ssrc = nullptr;
 }
 
@@ -410,6 +507,15 @@ int plan_make(gg_graph g, gg_ws ws, int algo, int source, const int* sources_dev
     R.ws = ws->dev;
     R.val = out;
     R.source = p.cc ? 0 : source;
+    if (g->renumbered) {
+        // multi-source traversals (batches) run on graphs in the caller's order
+        if (nsrc > 0) return GG_ENOTSUP;
+        p.renum = true;
+        p.out = out;
+        R.val = ws->rval;
+        if (!p.cc) R.source = g->h_newid[(size_t)source];
+        if (p.cc) R.rmin = ws->rmin;
+    }
     R.sources = sources_dev;
     R.nsrc = p.cc ? 0 : nsrc;
     R.mapping = o.mapping;
@@ -422,6 +528,9 @@ int plan_make(gg_graph g, gg_ws ws, int algo, int source, const int* sources_dev
     R.pullmode = diropt && (algo == GG_ALGO_SSSP || (p.cc && o.mode == GG_VERTEX));
     R.hops = p.async && !p.edge && !diropt && o.mapping == GG_MAP_BALANCED ? o.hops : 0;
     R.far_degree = nearfar ? o.far_degree : 0;
+    R.direct_lists = (o.flags & GG_OPT_LISTS_DIRECT)    ? 1
+                     : (o.flags & GG_OPT_LISTS_CHECKED) ? 0
+                                                         : (g->levels >= 256 ? 1 : 0);
 
     const int wpb = kBlock / 64;
     const long long n = g->n;
@@ -524,6 +633,29 @@ hipError_t plan_round(Plan& p, int r) {
     return e;
 }
 
+hipError_t plan_finish(Plan& p) {
+    if (!p.renum) return hipSuccess;
+    gg_graph g = p.g;
+    const int n = g->n;
+    const int gv = (int)std::max(1LL, std::min<long long>((n + kBlock - 1) / kBlock,
+                                                          device().max_blocks));
+    if (p.cc) {
+        // about 64 new ids per lane for the running minimum
+        const int gm = (int)std::max(1LL, std::min<long long>((n + 64LL * kBlock - 1) /
+                                                              (64LL * kBlock), device().cus));
+        hipError_t e = plan_launch(p, KIND_AUX, [&] {
+            return launch_cc_min_ids(p.R.val, g->oldid, p.R.rmin, n, gm, kBlock, p.s);
+        });
+        if (e != hipSuccess) return e;
+        return plan_launch(p, KIND_AUX, [&] {
+            return launch_cc_min_out(p.out, p.R.val, g->newid, p.R.rmin, n, gv, kBlock, p.s);
+        });
+    }
+    return plan_launch(p, KIND_AUX, [&] {
+        return launch_unrenumber(p.out, p.R.val, g->newid, n, gv, kBlock, p.s);
+    });
+}
+
 // Reserve `span` round stamps on the workspace; returns the first.  The
 // first stamp of a traversal is its tag: the round kernel that finds the end
 // stores it into the workspace's pinned word, so a late kernel of an earlier
@@ -565,6 +697,8 @@ int drive_start(Drive& d, long long r0, int stamp_base, int tag) {
     d.status = GG_OK;
     d.finished = false;
     d.stopping = false;
+    d.finishing = false;
+    d.fin_seq = 0;
     // two batches in flight from the start
     for (int i = 0; i < 2; ++i) {
         int rc = drive_enqueue(d);
@@ -589,8 +723,44 @@ int drive_enqueue(Drive& d) {
     return GG_OK;
 }
 
+// The rounds are over (the end was reported, or rounds or time ran out).
+// Without finishing kernels the traversal is finished now; otherwise they
+// are enqueued once, followed by a marker (polled) or an event, and the
+// traversal is finished when that has run: its output is then complete.
+int drive_end(Drive& d, bool block) {
+    Plan& p = d.p;
+    gg_ws ws = p.ws;
+    if (!p.renum) {
+        d.finished = true;
+        return 1;
+    }
+    if (!d.finishing) {
+        HIPCHK(p.g, plan_finish(p));
+        d.finishing = true;
+        if (d.poll) {
+            d.fin_seq = ++ws->prog_seq;
+            HIPCHK(p.g, launch_mark(prog_word(ws), d.fin_seq, p.s));
+        } else {
+            // the older batch's event has completed: its slot is free
+            HIPCHK(p.g, hipEventRecord(ws->ev[d.k & 1], p.s));
+        }
+    }
+    if (d.poll) {
+        if (__atomic_load_n(prog_word(ws), __ATOMIC_ACQUIRE) < d.fin_seq) return 0;
+    } else if (block) {
+        HIPCHK(p.g, hipEventSynchronize(ws->ev[d.k & 1]));
+    } else {
+        const hipError_t q = hipEventQuery(ws->ev[d.k & 1]);
+        if (q == hipErrorNotReady) return 0;
+        HIPCHK(p.g, q);
+    }
+    d.finished = true;
+    return 1;
+}
+
 int drive_step(Drive& d, bool block) {
     if (d.finished) return 1;
+    if (d.finishing) return drive_end(d, block);
     Plan& p = d.p;
     gg_ws ws = p.ws;
     auto reported = [&] { return __atomic_load_n(ws->h_done, __ATOMIC_ACQUIRE) == d.tag; };
@@ -600,16 +770,14 @@ int drive_step(Drive& d, bool block) {
         if (reported()) {
             // the values are final once the end is found; rounds still queued
             // return at their first instruction
-            d.finished = true;
-            return 1;
+            return drive_end(d, block);
         }
         if (d.stopping) {
             // out of rounds or time: the newer batch must complete before the
             // status is final (checked on later steps, never waited for here)
             if (!completed((d.k + 1) & 1)) return 0;
             if (!reported()) d.status = d.stop_status;
-            d.finished = true;
-            return 1;
+            return drive_end(d, block);
         }
         if (!completed(d.k & 1)) return 0;
     } else if (block) {
@@ -619,10 +787,7 @@ int drive_step(Drive& d, bool block) {
         if (q == hipErrorNotReady) return 0;
         HIPCHK(p.g, q);
     }
-    if (reported()) {
-        d.finished = true;
-        return 1;
-    }
+    if (reported()) return drive_end(d, block);
     const long long ms = std::chrono::duration_cast<std::chrono::milliseconds>(
                              std::chrono::steady_clock::now() - d.t0).count();
     if (d.r >= d.max_rounds || ms > p.o.time_limit_ms) {
@@ -635,8 +800,7 @@ int drive_step(Drive& d, bool block) {
             HIPCHK(p.g, hipEventSynchronize(ws->ev[(d.k + 1) & 1]));
         }
         if (!reported()) d.status = st;
-        d.finished = true;
-        return 1;
+        return drive_end(d, block);
     }
     int rc = drive_enqueue(d);
     return rc == GG_OK ? 0 : rc;
@@ -815,13 +979,22 @@ int gg_graph_upload(int32_t n, int64_t m, const int32_t* row_ptr, const int32_t*
             g->avg_w = (double)sum / (double)m;
         }
     }
+    // hottest vertices first: on request, or on a skewed graph large enough
+    // that its values do not fit in the dies' caches anyway
+    std::vector<int> hin;
+    const bool renumber = !(flags & GG_KEEP_ORDER) && m > 0 && n > 1 &&
+                          ((flags & GG_RENUMBER) ||
+                           (g->heavy == kHeavySkewed && m >= kPartMinEdges));
+    if (renumber) {
+        const int rc = renumber_graph(g, hrow, hin, tmp, s);
+        if (rc != GG_OK) return bail(rc);
+    }
     e = launch_fill_src(g->row, n, (int)m, g->src, grid((m + 4095) / 4096), kBlock, s);
     if (e != hipSuccess) return bail(GG_EHIP);
     // in-degrees, counted once for the head-partitioned edge list, the
     // both-directions CSR and the in-edge CSR
     const bool sym_build = (flags & GG_SYMMETRIZE) && !(flags & GG_SYMMETRIC);
-    std::vector<int> hin;
-    if (m > 0 && (m >= kPartMinEdges || sym_build || (flags & GG_TRANSPOSE))) {
+    if (m > 0 && !renumber && (m >= kPartMinEdges || sym_build || (flags & GG_TRANSPOSE))) {
         hin.resize((size_t)n);
         e = hipMemsetAsync(tmp, 0, sizeof(int) * n, s);
         if (e == hipSuccess)
@@ -954,6 +1127,12 @@ int gg_graph_info(gg_graph g, int32_t* n, int64_t* m, int32_t* max_out_degree,
 }
 
 int gg_graph_error(gg_graph g) { return g ? g->err : GG_EINVAL; }
+
+int gg_graph_order(gg_graph g, int32_t* renumbered) {
+    if (!g || !renumbered) return GG_EINVAL;
+    *renumbered = g->renumbered ? 1 : 0;
+    return GG_OK;
+}
 
 int gg_ws_create(gg_graph g, gg_ws* out) {
     if (!g || !out) return GG_EINVAL;

@@ -178,8 +178,10 @@ int gg_batch_create(const gg_instance* inst, int32_t count, uint32_t flags, void
         G.out_off = out_off;
         out_off += G.n;
         b->total_m += G.m;
+        // the group's traversal starts from a device list of caller ids:
+        // kept in the caller's vertex order
         int rc = gg_graph_upload((int)G.n, G.m, row.data(), col.data(),
-                                 weighted ? w.data() : nullptr, 0, stream, &G.g);
+                                 weighted ? w.data() : nullptr, GG_KEEP_ORDER, stream, &G.g);
         if (rc != GG_OK) return bail(rc);
         G.nsrc = (int)src.size();
         if (dalloc(&G.sources, src.size()) != hipSuccess ||

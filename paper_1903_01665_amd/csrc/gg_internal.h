@@ -119,6 +119,10 @@ struct Round {
     int far_degree; // near-far: only rows longer than this wait for the bound (0 = all)
     int pullmode;   // per-round schedule: dense rounds pull over in-edges (SSSP: trow;
                     // CC: the both-directions rows) instead of pushing or sweeping
+    int direct_lists; // SSSP local expansion: list passes issue their atomics without a
+                      // check load of the head value
+    int* rmin;      // CC on a renumbered graph: per-label minimum of the caller's ids,
+                    // filled with INT_MAX by the init kernel (null otherwise)
 };
 
 // Launch entry points (gg_kernels.hip).  Each returns the hipError_t of the
@@ -159,5 +163,20 @@ hipError_t launch_split_count(const int* col, int m, const unsigned char* part, 
 hipError_t launch_split_place(const int* src, const int* col, const int* w, int m,
                               const unsigned char* part, const long long* base, int* psrc,
                               int* pcol, int* pw, hipStream_t s);
+// Renumbering: caller edge e of row u = src[e] goes to place
+// nrow[newid[u]] + (e - row[u]) with head newid[col[e]] and weight w[e];
+// eorig[place] = e and epos[e] = place.  w and nw may be null.
+hipError_t launch_renumber(const int* row, const int* col, const int* w, const int* src, int m,
+                           const int* newid, const int* nrow, int* ncol, int* nw, int* eorig,
+                           int* epos, int grid, int block, hipStream_t s);
+// out[v] = val[newid[v]] for every caller id v
+hipError_t launch_unrenumber(int* out, const int* val, const int* newid, int n, int grid,
+                             int block, hipStream_t s);
+// CC: rmin[label[v']] = least oldid[v'] over the vertices v' of each label
+hipError_t launch_cc_min_ids(const int* label, const int* oldid, int* rmin, int n, int grid,
+                             int block, hipStream_t s);
+// CC: out[v] = rmin[label[newid[v]]] for every caller id v
+hipError_t launch_cc_min_out(int* out, const int* label, const int* newid, const int* rmin,
+                             int n, int grid, int block, hipStream_t s);
 
 }  // namespace gg

@@ -475,19 +475,25 @@ __device__ __forceinline__ void clear_prev_heavy(const Round& R) {
 // 128 / 256 two-word entries).
 constexpr int kLocalCap = 128;
 
-// DIRECT: no head-value load before the atomic (the atomic's returned value
-// decides): one round trip fewer per edge.  Used for BFS passes over the
-// wavefront's own list, whose vertices were just reached and mostly reach
-// new heads in turn (grid4096 BFS 13.5 -> 11.6 ms); for SSSP most heads do
-// not improve and the extra atomics cost more (rmat22 and er23 8-10% slower).
+// direct: no head-value load before the atomic (the atomic's returned value
+// decides): one round trip fewer per edge, one atomic more per edge that
+// would not have lowered its head.  BFS passes over a wavefront's own list
+// are always direct (their vertices were just reached and mostly reach new
+// heads in turn: grid4096 BFS 13.5 -> 11.6 ms).  SSSP passes are direct
+// when Round::direct_lists says so: on a deep graph a round is a chain of
+// dependent passes run by few wavefronts, so the round trip saved counts
+// and the extra atomics do not (grid4096 step +10%); on shallow graphs the
+// rounds are wide and the extra atomics cost more (rmat22 -2%, er23 -4%).
+// Choosing per pass from the share of the previous pass's edges that
+// lowered their head (direct above one half) gained nothing on grid4096.
 // The atomics of a lane's U edges are all issued before the first returned
 // value is looked at (then the ballots and list writes), so their round
 // trips overlap instead of following one another.
-template <int A, int U, bool DIRECT = false>
+template <int A, int U>
 __device__ __forceinline__ void relax_batch_local(const Round& R, const int* row, const int* col,
                                                   const int (&e)[U], const int (&sv)[U],
                                                   const bool (&ok)[U], int nxt, Acc& acc,
-                                                  int bound, int4* lst, int& ln) {
+                                                  int bound, int4* lst, int& ln, bool direct) {
     int* val = R.val;
     const int lane = threadIdx.x & 63;
     int t[U], wt[U], cur[U], nv[U], old[U], rb[U], re[U];
@@ -498,7 +504,7 @@ __device__ __forceinline__ void relax_batch_local(const Round& R, const int* row
         for (int j = 0; j < U; ++j) wt[j] = ok[j] ? R.g.w[e[j]] : 0;
     }
 #pragma unroll
-    for (int j = 0; j < U; ++j) cur[j] = ok[j] ? (DIRECT ? kInf : val[t[j]]) : 0;
+    for (int j = 0; j < U; ++j) cur[j] = ok[j] && !direct ? val[t[j]] : kInf;
 #pragma unroll
     for (int j = 0; j < U; ++j) {
         nv[j] = 0;
@@ -545,11 +551,11 @@ __device__ __forceinline__ void relax_batch_local(const Round& R, const int* row
 }
 
 // wave_relax_rows with relax_batch_local.
-template <int A, int U, bool DIRECT = false>
+template <int A, int U>
 __device__ __forceinline__ void wave_relax_rows_local(const Round& R, const int* row,
                                                       const int* col, int beg, int deg, int sv,
                                                       int nxt, Acc& acc, int bound, int4* lst,
-                                                      int& ln) {
+                                                      int& ln, bool direct) {
     const int lane = threadIdx.x & 63;
     const int incl = wave_incl_scan(deg);
     const int total = __shfl(incl, 63, 64);
@@ -570,7 +576,7 @@ __device__ __forceinline__ void wave_relax_rows_local(const Round& R, const int*
             s[j] = __shfl(sv, o, 64);
             ok[j] = k < total;
         }
-        relax_batch_local<A, U, DIRECT>(R, row, col, e, s, ok, nxt, acc, bound, lst, ln);
+        relax_batch_local<A, U>(R, row, col, e, s, ok, nxt, acc, bound, lst, ln, direct);
     }
 }
 
@@ -586,6 +592,7 @@ __global__ __launch_bounds__(256) void k_init(Round R, int algo, int async) {
     const long long src = R.nsrc > 0 ? -1 : R.source;
     for (long long v = tid; v < n; v += tt) {
         R.val[v] = algo == CC ? (int)v : (v == src ? 0 : kInf);
+        if (R.rmin) R.rmin[v] = kInf;
         if (async) {
             const bool on = algo == CC || v == src;
             R.ws.vflag[0][v] = on;
@@ -1150,7 +1157,8 @@ __device__ __forceinline__ void serve_local(const Round& R, const int* row, cons
     if (hv) mark_heavy(R, u);
     int ln = 0;
     wave_relax_rows_local<A, U>(R, row, col, on && !hv ? rb : 0, on && !hv ? re - rb : 0, sv,
-                                nxt, acc, bound, lb, ln);
+                                nxt, acc, bound, lb, ln, false);
+    const bool direct = A == BFS || (A == SSSP && R.direct_lists);
     for (int pass = 1; ln > 0; ++pass) {
         const int4* cur = lb + ((pass - 1) & 1) * kLocalCap;
         int4* nx = lb + (pass & 1) * kLocalCap;
@@ -1178,9 +1186,9 @@ __device__ __forceinline__ void serve_local(const Round& R, const int* row, cons
             if (on) acc.v++;
             hv = on && re - rb > R.g.heavy;
             if (hv) mark_heavy(R, u);
-            wave_relax_rows_local<A, U, A == BFS>(R, row, col, on && !hv ? rb : 0,
-                                                  on && !hv ? re - rb : 0, sv, nxt, acc, bound,
-                                                  nx, ln);
+            wave_relax_rows_local<A, U>(R, row, col, on && !hv ? rb : 0,
+                                        on && !hv ? re - rb : 0, sv, nxt, acc, bound, nx, ln,
+                                        direct);
         }
         if (pass > R.hops) break;
     }
@@ -1957,6 +1965,104 @@ __global__ __launch_bounds__(256) void k_t_fill(const int* col, const int* w, co
     }
 }
 
+// ------------------------------------------------------- renumbering ----
+// A graph stored with its vertices renumbered (new id newid[v] for caller id
+// v, oldid[] the inverse) keeps each row's edges in order: caller edge e of
+// row u lands at nrow[newid[u]] + (e - row[u]).
+
+__global__ __launch_bounds__(256) void k_renumber(const int* row, const int* col, const int* w,
+                                                  const int* src, int m, const int* newid,
+                                                  const int* nrow, int* ncol, int* nw,
+                                                  int* eorig, int* epos) {
+    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long tt = (long long)gridDim.x * blockDim.x;
+    for (long long e = tid; e < m; e += tt) {
+        const int u = src[e];
+        const int p = nrow[newid[u]] + (int)(e - row[u]);
+        ncol[p] = newid[col[e]];
+        if (nw) nw[p] = w[e];
+        if (eorig) eorig[p] = (int)e;
+        if (epos) epos[e] = p;
+    }
+}
+
+// Output in the caller's order: a coalesced read of newid, one gather.
+__global__ __launch_bounds__(256) void k_unrenumber(int* out, const int* val, const int* newid,
+                                                    int n) {
+    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long tt = (long long)gridDim.x * blockDim.x;
+    for (long long v = tid; v < n; v += tt) out[v] = val[newid[v]];
+}
+
+// CC on a renumbered graph: the label of a component is the least of the
+// caller's ids among its vertices, while the propagation left the least new
+// id.  Each block takes a contiguous range of new ids and keeps, per lane, a
+// running (label, least caller id) pair, written out with a checked atomic
+// minimum whenever the label changes; hottest-first numbering puts most of
+// the large components' vertices next to each other, so the pairs change
+// rarely.  The last pairs are merged per wavefront and per block before
+// their atomics, which keeps the atomics on one label (the giant component)
+// to about one per block.
+__global__ __launch_bounds__(256) void k_cc_min_ids(const int* label, const int* oldid, int* rmin,
+                                                    int n) {
+    const long long per = ((long long)n + gridDim.x - 1) / gridDim.x;
+    const long long v0 = (long long)blockIdx.x * per;
+    const long long v1 = min((long long)n, v0 + per);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int L = -1, mn = kInf;
+    for (long long v = v0 + threadIdx.x; v < v1; v += blockDim.x) {
+        const int l = label[v];
+        const int o = oldid[v];
+        if (l != L) {
+            if (L >= 0 && mn < rmin[L]) atomicMin(&rmin[L], mn);
+            L = l;
+            mn = o;
+        } else {
+            mn = min(mn, o);
+        }
+    }
+    // wavefront: the lanes sharing the first active lane's label reduce
+    const unsigned long long act = __ballot(L >= 0);
+    int wl = -1, wm = kInf;
+    if (act) {
+        const int leader = __ffsll(act) - 1;
+        wl = __shfl(L, leader, 64);
+        const bool same = L == wl;
+        int x = same ? mn : kInf;
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) x = min(x, __shfl_xor(x, d, 64));
+        wm = x;
+        if (!same && L >= 0 && mn < rmin[L]) atomicMin(&rmin[L], mn);
+    }
+    // block: the wavefronts' pairs, merged by label
+    __shared__ int s_l[4], s_m[4];
+    if (lane == 0) {
+        s_l[wid] = wl;
+        s_m[wid] = wm;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (int)(blockDim.x >> 6);
+        for (int i = 0; i < nw; ++i) {
+            if (s_l[i] < 0) continue;
+            int x = s_m[i];
+            for (int j = i + 1; j < nw; ++j)
+                if (s_l[j] == s_l[i]) {
+                    x = min(x, s_m[j]);
+                    s_l[j] = -1;
+                }
+            if (x < rmin[s_l[i]]) atomicMin(&rmin[s_l[i]], x);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cc_min_out(int* out, const int* label, const int* newid,
+                                                    const int* rmin, int n) {
+    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long tt = (long long)gridDim.x * blockDim.x;
+    for (long long v = tid; v < n; v += tt) out[v] = rmin[label[newid[v]]];
+}
+
 // ----------------------------------------------------- launch wrappers ----
 
 // Blocks of `block` threads of kernel f that fit on the device at once.  A
@@ -2105,6 +2211,29 @@ hipError_t launch_check(const int* col, const int* w, int m, int* stats,
 }
 
 int split_blocks(long long m) { return (int)((m + kSplitTile - 1) / kSplitTile); }
+
+hipError_t launch_renumber(const int* row, const int* col, const int* w, const int* src, int m,
+                           const int* newid, const int* nrow, int* ncol, int* nw, int* eorig,
+                           int* epos, int grid, int block, hipStream_t s) {
+    GG_LAUNCH(k_renumber, grid, block, s, row, col, w, src, m, newid, nrow, ncol, nw, eorig, epos);
+}
+
+hipError_t launch_unrenumber(int* out, const int* val, const int* newid, int n, int grid,
+                             int block, hipStream_t s) {
+    GG_LAUNCH(k_unrenumber, grid, block, s, out, val, newid, n);
+}
+
+hipError_t launch_cc_min_ids(const int* label, const int* oldid, int* rmin, int n, int grid,
+                             int block, hipStream_t s) {
+    // one contiguous range per block (the block-level merge assumes 4 waves)
+    if (block != 256) return hipErrorInvalidValue;
+    GG_LAUNCH(k_cc_min_ids, grid, block, s, label, oldid, rmin, n);
+}
+
+hipError_t launch_cc_min_out(int* out, const int* label, const int* newid, const int* rmin,
+                             int n, int grid, int block, hipStream_t s) {
+    GG_LAUNCH(k_cc_min_out, grid, block, s, out, label, newid, rmin, n);
+}
 
 hipError_t launch_split_count(const int* col, int m, const unsigned char* part, int* counts,
                               hipStream_t s) {

@@ -4,7 +4,9 @@
 // the DSL's Set type is a union-find structure (Sec. 2).  Every stored edge
 // e = (src[e], col[e]) with weight w[e] is an undirected edge with the key
 // w[e] * 2^32 + e: keys are distinct, so the forest of least keys is unique
-// and every run returns the same edge set.
+// and every run returns the same edge set.  On a renumbered graph e is the
+// caller's index of the edge (eorig of its stored place; epos maps back), so
+// keys, ties and the output flags are those of the caller's edge order.
 //
 // Boruvka rounds, four kernels each:
 //   min      every edge whose ends lie in different components offers its key
@@ -42,6 +44,8 @@ struct Msf {
     const int* src;
     const int* col;
     const int* w;
+    const int* eorig;          // renumbered graph: caller's index of each stored edge
+    const int* epos;           // ... and stored place of each caller edge (else null)
     int n, m;
     int* parent;               // union-find forest
     unsigned long long* best;  // per root: least key of a crossing edge
@@ -121,7 +125,8 @@ __device__ __forceinline__ bool offer(const Msf& M, int u, int v, int e) {
     if (u == v) return false;
     const int ru = M.parent[u], rv = M.parent[v];
     if (ru == rv) return false;
-    const unsigned long long key = ((unsigned long long)(unsigned)M.w[e] << 32) | (unsigned)e;
+    const int eo = M.eorig ? M.eorig[e] : e;
+    const unsigned long long key = ((unsigned long long)(unsigned)M.w[e] << 32) | (unsigned)eo;
     if (key < M.best[ru]) atomicMin(&M.best[ru], key);
     if (key < M.best[rv]) atomicMin(&M.best[rv], key);
     return true;
@@ -179,7 +184,8 @@ __global__ __launch_bounds__(256) void k_msf_link(Msf M) {
         M.best[v] = kNoEdge;
         const int e = (int)(b & 0xffffffffu);
         M.in_msf[e] = 1;
-        int a = M.src[e], c = M.col[e];
+        const int ep = M.epos ? M.epos[e] : e;
+        int a = M.src[ep], c = M.col[ep];
         for (;;) {
             a = find_linking(M.parent, a);
             c = find_linking(M.parent, c);
@@ -234,13 +240,13 @@ __global__ __launch_bounds__(256) void k_msf_settle(Msf M) {
 // Weight and edge count of the forest: one pair of 64-bit partial sums per
 // block.
 __global__ __launch_bounds__(256) void k_msf_sum(const unsigned char* in_msf, const int* w,
-                                                 int m, long long* partial) {
+                                                 const int* epos, int m, long long* partial) {
     const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long tt = (long long)gridDim.x * blockDim.x;
     long long sw = 0, cnt = 0;
     for (long long e = tid; e < m; e += tt)
         if (in_msf[e]) {
-            sw += w[e];
+            sw += w[epos ? epos[e] : e];
             cnt++;
         }
     __shared__ long long s_w[4], s_c[4];
@@ -310,6 +316,8 @@ int gg_msf(gg_graph g, gg_ws ws, uint8_t* in_msf_dev, int64_t* total_weight, int
     M.src = g->src;
     M.col = g->col;
     M.w = g->w;
+    M.eorig = g->renumbered ? g->eorig : nullptr;
+    M.epos = g->renumbered ? g->epos : nullptr;
     M.n = n;
     M.m = m;
     M.parent = ws->msf_parent;
@@ -356,7 +364,8 @@ int gg_msf(gg_graph g, gg_ws ws, uint8_t* in_msf_dev, int64_t* total_weight, int
     long long* partial = reinterpret_cast<long long*>(ws->dev.pcount);
     const int g_sum = msf_grid(reinterpret_cast<const void*>(k_msf_sum), m);
     std::vector<long long> hp(2 * (size_t)g_sum);
-    hipLaunchKernelGGL(k_msf_sum, dim3(g_sum), dim3(kBlock), 0, s, in_msf_dev, g->w, m, partial);
+    hipLaunchKernelGGL(k_msf_sum, dim3(g_sum), dim3(kBlock), 0, s, in_msf_dev, g->w, M.epos, m,
+                       partial);
     HIPCHK(g, hipGetLastError());
     HIPCHK(g, hipMemcpyAsync(hp.data(), partial, sizeof(long long) * hp.size(),
                              hipMemcpyDeviceToHost, s));

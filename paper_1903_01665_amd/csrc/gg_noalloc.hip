@@ -2,7 +2,8 @@
 // in include/gg.h), for callers that cannot allocate device memory.
 //
 // The traversal's scratch memory -- frontier flags, heavy-row bits, the
-// control block, per-block counters and push counts, the end word -- lives
+// control block, per-block counters and push counts, the end word, and the
+// levels in the library's vertex order when the graph is renumbered -- lives
 // in one file-scope device array of fixed size instead of a workspace.  Each
 // device holds its own copy of the array; its address on a device is taken
 // once, with that device current, at the first call there, and only that
@@ -35,11 +36,12 @@ constexpr long long kOffCtl = align256(kOffHbits + 4 * 2 * kNaHWords);
 constexpr long long kOffStat = align256(kOffCtl + (long long)sizeof(Ctl));
 constexpr long long kOffCount = align256(kOffStat + (long long)sizeof(Stat) * kKinds * kMaxStatBlocks);
 constexpr long long kOffDone = align256(kOffCount + 4LL * 3 * 2 * kMaxStatBlocks);
-constexpr long long kNaBytes = align256(kOffDone + 16);
+constexpr long long kOffRval = align256(kOffDone + 16);  // levels of a renumbered graph
+constexpr long long kNaBytes = align256(kOffRval + 4 * kNaMaxN);
 
 }  // namespace
 
-// about 10 MB on every device the library runs on, held until the process ends
+// about 27 MB on every device the library runs on, held until the process ends
 static __device__ __align__(256) unsigned char scratch[kNaBytes];
 
 namespace {
@@ -101,6 +103,7 @@ extern "C" int gg_bfs_noalloc(gg_graph g, int32_t source, const gg_opts* opts,
     w.dev.ctl = reinterpret_cast<Ctl*>(D.ptr + kOffCtl);
     w.dev.stat = reinterpret_cast<Stat*>(D.ptr + kOffStat);
     w.dev.pcount = reinterpret_cast<int*>(D.ptr + kOffCount);
+    w.rval = g->renumbered ? reinterpret_cast<int*>(D.ptr + kOffRval) : nullptr;
     int* done_word = reinterpret_cast<int*>(D.ptr + kOffDone);
 
     Plan p;
@@ -146,5 +149,10 @@ extern "C" int gg_bfs_noalloc(gg_graph g, int32_t source, const gg_opts* opts,
         batch = std::min(batch * 2, kMaxBatch);
     }
     D.epoch = (int)std::min<long long>((long long)base + r + 1, 1LL << 30);
+    // a renumbered graph: the levels to the caller's order
+    if (p.renum) {
+        HIPCHK(g, plan_finish(p));
+        HIPCHK(g, hipStreamSynchronize(s));
+    }
     return status;
 }

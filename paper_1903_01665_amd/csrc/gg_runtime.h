@@ -74,6 +74,10 @@ struct gg_ws_s {
     // allocated by the first gg_msf call on the workspace
     int* msf_parent = nullptr;
     unsigned long long* msf_best = nullptr;
+    // renumbered graph: the traversal's values in the library's vertex order
+    // and the per-component minimum of the caller's ids (CC)
+    int* rval = nullptr;
+    int* rmin = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
     hipEvent_t finished = nullptr;
     hipStream_t last_stream = nullptr;
@@ -97,7 +101,7 @@ struct gg_graph_s {
     int n = 0;
     long long m = 0;
     int max_deg = 0;
-    int argmax_deg = 0;
+    int argmax_deg = 0;  // a vertex of largest out-degree (caller's id)
     int levels = -1;  // BFS rounds from argmax_deg, measured by gg_graph_probe
     bool weighted = false;
     bool has_sym = false;
@@ -117,6 +121,14 @@ struct gg_graph_s {
     int2* tchunks = nullptr;
     int n_tchunks = 0;
     int poff[gg::kXcd + 1] = {};
+    // renumbered vertex order (GG_RENUMBER): new id of each caller id and
+    // back, on the device, and the new ids on the host (to map sources);
+    // the caller's index of each stored edge and the stored place of each
+    // caller edge (the forest's keys and output)
+    bool renumbered = false;
+    int *newid = nullptr, *oldid = nullptr;
+    int *eorig = nullptr, *epos = nullptr;
+    std::vector<int> h_newid;
     double avg_w = 0;  // mean edge weight (0 when unweighted)
     int max_w = 0;     // largest edge weight
     gg_ws_s* ws0 = nullptr;
@@ -164,6 +176,10 @@ struct Plan {
     Round R{};
     bool async = false, edge = false, cc = false, diropt = false;
     bool need_heavy = false, need_jump = false, prof = false;
+    // renumbered graph: R.val is the workspace's array; the finishing
+    // kernels write `out` in the caller's order
+    bool renum = false;
+    int* out = nullptr;
     int g_init = 1, g_seed = 1, g_round = 1, g_heavy = 1, g_jump = 1;
 };
 
@@ -174,6 +190,9 @@ int plan_make(gg_graph g, gg_ws ws, int algo, int source, const int* sources_dev
 hipError_t plan_init(Plan& p);
 // Enqueue round r (round kernel, heavy-chunk or shortcut kernel as needed).
 hipError_t plan_round(Plan& p, int r);
+// Enqueue what ends a traversal once its rounds are done: on a renumbered
+// graph, the kernels that write the output in the caller's order.
+hipError_t plan_finish(Plan& p);
 // Reserve `span` round stamps on a workspace; returns the first.
 int reserve_stamps(gg_ws ws, hipStream_t s, long long span, hipError_t* err);
 // Resumable eager driver of one traversal (see gg_api.hip).
@@ -194,6 +213,10 @@ struct Drive {
     // before stop_status becomes final
     bool stopping = false;
     int stop_status = GG_OK;
+    // poll, renumbered graph: the finishing kernels are enqueued and the
+    // traversal ends when the marker after them has run
+    bool finishing = false;
+    unsigned long long fin_seq = 0;
 };
 // Bound on the rounds of a traversal planned by p.
 long long max_rounds(const Plan& p);

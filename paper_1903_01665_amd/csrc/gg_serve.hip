@@ -52,7 +52,8 @@ long long ws_bytes_of(gg_graph g) {
     const long long vbytes = ((ntiles + 63) / 64) * 64 * 64;
     const long long tbytes = ((ntiles + 63) / 64) * 64;
     const long long hwords = (g->n + 31) / 32;
-    return 2 * (vbytes + tbytes) + 2 * 4LL * hwords + (long long)sizeof(Ctl) +
+    const long long renum = g->renumbered ? 8LL * g->n : 0;  // values and minima
+    return 2 * (vbytes + tbytes) + 2 * 4LL * hwords + renum + (long long)sizeof(Ctl) +
            (long long)sizeof(Stat) * kKinds * kMaxStatBlocks + 4LL * 3 * 2 * kMaxStatBlocks;
 }
 

@@ -22,8 +22,10 @@ SYNC, ASYNC, SCHED_AUTO, NEARFAR, DIROPT = 0, 1, 2, 3, 4
 MAP_AUTO, MAP_THREAD, MAP_WAVE, MAP_BALANCED = 0, 1, 2, 3
 ALGO_SSSP, ALGO_BFS, ALGO_CC, ALGO_MSF = 0, 1, 2, 3
 SYMMETRIZE, INPUT_ON_DEVICE, SYMMETRIC, TRANSPOSE = 1, 2, 4, 8
+RENUMBER, KEEP_ORDER = 16, 32
 OPT_CC_NO_JUMP = 1
 OPT_PROFILE = 2
+OPT_LISTS_CHECKED, OPT_LISTS_DIRECT = 4, 8
 KINDS = ("round", "heavy", "aux")
 
 STATUS = {0: "GG_OK", -1: "GG_EINVAL", -2: "GG_ENOMEM", -3: "GG_EHIP", -4: "GG_EBUSY",
@@ -40,7 +42,7 @@ EXPORTS = ["gg_graph_upload", "gg_graph_free", "gg_graph_info", "gg_graph_error"
            "gg_server_submit", "gg_server_poll", "gg_server_state", "gg_server_now",
            "gg_server_free", "gg_sssp_async", "gg_bfs_async", "gg_cc_async", "gg_ticket_query",
            "gg_ticket_wait", "gg_ticket_stream_wait", "gg_ticket_times", "gg_ticket_free",
-           "gg_bfs_noalloc"]
+           "gg_bfs_noalloc", "gg_graph_order"]
 BATCH_NO_GRAPH, BATCH_ONE_GROUP = 1, 2
 
 TUNE_TABLE = os.path.join(_HERE, "tune_table.json")
@@ -135,6 +137,7 @@ def lib():
     L.gg_graph_free.argtypes = [vp]
     L.gg_graph_info.argtypes = [vp, P(i32), P(i64), P(i32), P(i32), P(i32)]
     L.gg_graph_error.argtypes = [vp]
+    L.gg_graph_order.argtypes = [vp, P(i32)]
     L.gg_sssp.argtypes = [vp, i32, i32, i32, vp, vp]
     L.gg_bfs.argtypes = [vp, i32, i32, i32, vp, vp]
     L.gg_cc.argtypes = [vp, i32, i32, vp, vp]
@@ -284,7 +287,10 @@ class Graph:
     """A graph resident in HBM (CSR, edge list, optional both-directions CSR)."""
 
     def __init__(self, n, row_ptr, col, w=None, symmetrize=False, symmetric=False, stream=None,
-                 transpose=False):
+                 transpose=False, renumber=None):
+        """renumber: None lets the library decide (skewed graphs of >= 2^20
+        edges are stored hottest vertex first), True forces it, False keeps
+        the caller's order.  Ids at the interface are the caller's either way."""
         L = lib()
         self.n = int(n)
         self._row, prow = _arr(row_ptr)
@@ -294,7 +300,8 @@ class Graph:
         if w is not None:
             self._w, pw = _arr(w if len(w) else np.zeros(1, np.int32))
         flags = (SYMMETRIZE if symmetrize else 0) | (SYMMETRIC if symmetric else 0) | \
-            (TRANSPOSE if transpose else 0)
+            (TRANSPOSE if transpose else 0) | \
+            (0 if renumber is None else RENUMBER if renumber else KEEP_ORDER)
         h = ctypes.c_void_p()
         _check(L.gg_graph_upload(self.n, m, prow, pcol, pw, flags, _stream_ptr(stream),
                                  ctypes.byref(h)), "gg_graph_upload")
@@ -305,10 +312,16 @@ class Graph:
             del self._w
 
     @classmethod
-    def from_host(cls, hg, symmetrize=False, stream=None, transpose=False):
+    def from_host(cls, hg, symmetrize=False, stream=None, transpose=False, renumber=None):
         """Upload a :class:`paper_1903_01665_amd.gen.HostGraph`."""
         return cls(hg.n, hg.row_ptr, hg.col, hg.w, symmetrize=symmetrize and not hg.symmetric,
-                   symmetric=hg.symmetric, stream=stream, transpose=transpose)
+                   symmetric=hg.symmetric, stream=stream, transpose=transpose, renumber=renumber)
+
+    def renumbered(self):
+        """True when the library stores the graph in its own vertex order."""
+        r = ctypes.c_int32()
+        _check(lib().gg_graph_order(self.handle, ctypes.byref(r)), "gg_graph_order")
+        return bool(r.value)
 
     def info(self):
         n, m, d, hw, hs = (ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(),

@@ -334,12 +334,16 @@ def test_local_expansion(gg):
         g = gg.Graph.from_host(hg, symmetrize=True)
         try:
             for hops in (1, 3, 64):
-                for algo, sched, delta in (("sssp", gg.ASYNC, 0), ("sssp", gg.NEARFAR, 0),
-                                           ("sssp", gg.NEARFAR, 5), ("bfs", gg.ASYNC, 0),
-                                           ("cc", gg.ASYNC, 0)):
+                for algo, sched, delta, fl in (
+                        ("sssp", gg.ASYNC, 0, 0), ("sssp", gg.NEARFAR, 0, 0),
+                        ("sssp", gg.NEARFAR, 5, 0), ("sssp", gg.NEARFAR, 5, gg.OPT_LISTS_DIRECT),
+                        ("sssp", gg.ASYNC, 0, gg.OPT_LISTS_DIRECT),
+                        ("sssp", gg.NEARFAR, 0, gg.OPT_LISTS_CHECKED),
+                        ("bfs", gg.ASYNC, 0, 0), ("cc", gg.ASYNC, 0, 0)):
                     say(f"[gpu] local {hg.name} n={hg.n} {algo} sched={sched} delta={delta} "
-                        f"hops={hops}")
-                    o = gg.make_opts(gg.VERTEX, sched, gg.MAP_BALANCED, delta=delta, hops=hops)
+                        f"hops={hops} flags={fl}")
+                    o = gg.make_opts(gg.VERTEX, sched, gg.MAP_BALANCED, delta=delta, hops=hops,
+                                     flags=fl)
                     got = (g.cc(opts=o) if algo == "cc" else getattr(g, algo)(s, opts=o))
                     st = g.stats()
                     assert st["rc"] == 0, st
