@@ -210,6 +210,9 @@ int renumber_graph(gg_graph g, std::vector<int>& hrow, std::vector<int>& hin, in
                          [&](int a, int b) { return key[a] > key[b]; });
     }
     for (int k = 0; k < n; ++k) newid[(size_t)oldid[k]] = k;
+    // vertices without any edge come last
+    int active = n;
+    while (active > 0 && key[(size_t)oldid[(size_t)active - 1]] == 0) --active;
     std::vector<int> nrow((size_t)n + 1), nin((size_t)n);
     nrow[0] = 0;
     for (int k = 0; k < n; ++k) {
@@ -256,6 +259,7 @@ int renumber_graph(gg_graph g, std::vector<int>& hrow, std::vector<int>& hin, in
     hin.swap(nin);
     g->h_newid.swap(newid);
     g->renumbered = true;
+    g->n_active = active;
     return GG_OK;
 }
 
@@ -512,6 +516,7 @@ int plan_make(gg_graph g, gg_ws ws, int algo, int source, const int* sources_dev
         if (nsrc > 0) return GG_ENOTSUP;
         p.renum = true;
         p.out = out;
+        p.src_caller = p.cc ? -1 : source;
         R.val = ws->rval;
         if (!p.cc) R.source = g->h_newid[(size_t)source];
         if (p.cc) R.rmin = ws->rmin;
@@ -639,20 +644,25 @@ hipError_t plan_finish(Plan& p) {
     const int n = g->n;
     const int gv = (int)std::max(1LL, std::min<long long>((n + kBlock - 1) / kBlock,
                                                           device().max_blocks));
+    // a vertex without edges (new id >= n_active) is its own component and
+    // reached only as the source: its value needs no gather
+    const int na = g->n_active;
     if (p.cc) {
         // about 64 new ids per lane for the running minimum
-        const int gm = (int)std::max(1LL, std::min<long long>((n + 64LL * kBlock - 1) /
+        const int gm = (int)std::max(1LL, std::min<long long>((na + 64LL * kBlock - 1) /
                                                               (64LL * kBlock), device().cus));
-        hipError_t e = plan_launch(p, KIND_AUX, [&] {
-            return launch_cc_min_ids(p.R.val, g->oldid, p.R.rmin, n, gm, kBlock, p.s);
-        });
+        hipError_t e = hipSuccess;
+        if (na > 0)
+            e = plan_launch(p, KIND_AUX, [&] {
+                return launch_cc_min_ids(p.R.val, g->oldid, p.R.rmin, na, gm, kBlock, p.s);
+            });
         if (e != hipSuccess) return e;
         return plan_launch(p, KIND_AUX, [&] {
-            return launch_cc_min_out(p.out, p.R.val, g->newid, p.R.rmin, n, gv, kBlock, p.s);
+            return launch_cc_min_out(p.out, p.R.val, g->newid, p.R.rmin, n, na, gv, kBlock, p.s);
         });
     }
     return plan_launch(p, KIND_AUX, [&] {
-        return launch_unrenumber(p.out, p.R.val, g->newid, n, gv, kBlock, p.s);
+        return launch_unrenumber(p.out, p.R.val, g->newid, n, na, p.src_caller, gv, kBlock, p.s);
     });
 }
 

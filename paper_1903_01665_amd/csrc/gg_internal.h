@@ -169,14 +169,16 @@ hipError_t launch_split_place(const int* src, const int* col, const int* w, int 
 hipError_t launch_renumber(const int* row, const int* col, const int* w, const int* src, int m,
                            const int* newid, const int* nrow, int* ncol, int* nw, int* eorig,
                            int* epos, int grid, int block, hipStream_t s);
-// out[v] = val[newid[v]] for every caller id v
-hipError_t launch_unrenumber(int* out, const int* val, const int* newid, int n, int grid,
-                             int block, hipStream_t s);
+// out[v] = val[newid[v]] for every caller id v; a vertex whose new id is
+// >= n_active (no edge) gets 0 if it is the source, else INF
+hipError_t launch_unrenumber(int* out, const int* val, const int* newid, int n, int n_active,
+                             int source, int grid, int block, hipStream_t s);
 // CC: rmin[label[v']] = least oldid[v'] over the vertices v' of each label
 hipError_t launch_cc_min_ids(const int* label, const int* oldid, int* rmin, int n, int grid,
                              int block, hipStream_t s);
-// CC: out[v] = rmin[label[newid[v]]] for every caller id v
+// CC: out[v] = rmin[label[newid[v]]] for every caller id v (v itself when
+// its new id is >= n_active: no edge, a component of its own)
 hipError_t launch_cc_min_out(int* out, const int* label, const int* newid, const int* rmin,
-                             int n, int grid, int block, hipStream_t s);
+                             int n, int n_active, int grid, int block, hipStream_t s);
 
 }  // namespace gg

@@ -1986,12 +1986,16 @@ __global__ __launch_bounds__(256) void k_renumber(const int* row, const int* col
     }
 }
 
-// Output in the caller's order: a coalesced read of newid, one gather.
+// Output in the caller's order: a coalesced read of newid, one gather (none
+// for a vertex without edges: it is reached only as the source).
 __global__ __launch_bounds__(256) void k_unrenumber(int* out, const int* val, const int* newid,
-                                                    int n) {
+                                                    int n, int n_active, int source) {
     const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long tt = (long long)gridDim.x * blockDim.x;
-    for (long long v = tid; v < n; v += tt) out[v] = val[newid[v]];
+    for (long long v = tid; v < n; v += tt) {
+        const int k = newid[v];
+        out[v] = k < n_active ? val[k] : (v == source ? 0 : kInf);
+    }
 }
 
 // CC on a renumbered graph: the label of a component is the least of the
@@ -2057,10 +2061,13 @@ __global__ __launch_bounds__(256) void k_cc_min_ids(const int* label, const int*
 }
 
 __global__ __launch_bounds__(256) void k_cc_min_out(int* out, const int* label, const int* newid,
-                                                    const int* rmin, int n) {
+                                                    const int* rmin, int n, int n_active) {
     const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long tt = (long long)gridDim.x * blockDim.x;
-    for (long long v = tid; v < n; v += tt) out[v] = rmin[label[newid[v]]];
+    for (long long v = tid; v < n; v += tt) {
+        const int k = newid[v];
+        out[v] = k < n_active ? rmin[label[k]] : (int)v;
+    }
 }
 
 // ----------------------------------------------------- launch wrappers ----
@@ -2218,9 +2225,9 @@ hipError_t launch_renumber(const int* row, const int* col, const int* w, const i
     GG_LAUNCH(k_renumber, grid, block, s, row, col, w, src, m, newid, nrow, ncol, nw, eorig, epos);
 }
 
-hipError_t launch_unrenumber(int* out, const int* val, const int* newid, int n, int grid,
-                             int block, hipStream_t s) {
-    GG_LAUNCH(k_unrenumber, grid, block, s, out, val, newid, n);
+hipError_t launch_unrenumber(int* out, const int* val, const int* newid, int n, int n_active,
+                             int source, int grid, int block, hipStream_t s) {
+    GG_LAUNCH(k_unrenumber, grid, block, s, out, val, newid, n, n_active, source);
 }
 
 hipError_t launch_cc_min_ids(const int* label, const int* oldid, int* rmin, int n, int grid,
@@ -2231,8 +2238,8 @@ hipError_t launch_cc_min_ids(const int* label, const int* oldid, int* rmin, int 
 }
 
 hipError_t launch_cc_min_out(int* out, const int* label, const int* newid, const int* rmin,
-                             int n, int grid, int block, hipStream_t s) {
-    GG_LAUNCH(k_cc_min_out, grid, block, s, out, label, newid, rmin, n);
+                             int n, int n_active, int grid, int block, hipStream_t s) {
+    GG_LAUNCH(k_cc_min_out, grid, block, s, out, label, newid, rmin, n, n_active);
 }
 
 hipError_t launch_split_count(const int* col, int m, const unsigned char* part, int* counts,

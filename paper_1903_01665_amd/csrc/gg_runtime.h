@@ -126,6 +126,7 @@ struct gg_graph_s {
     // the caller's index of each stored edge and the stored place of each
     // caller edge (the forest's keys and output)
     bool renumbered = false;
+    int n_active = 0;  // renumbered: vertices with an edge (new ids below this)
     int *newid = nullptr, *oldid = nullptr;
     int *eorig = nullptr, *epos = nullptr;
     std::vector<int> h_newid;
@@ -180,6 +181,7 @@ struct Plan {
     // kernels write `out` in the caller's order
     bool renum = false;
     int* out = nullptr;
+    int src_caller = -1;  // the source as the caller numbers it (-1: CC)
     int g_init = 1, g_seed = 1, g_round = 1, g_heavy = 1, g_jump = 1;
 };
 
