@@ -471,13 +471,14 @@ def run_workload(name, args, *, sources_kind="random8", variants=False, cpu=True
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rmat22")
     ap.add_argument("--no-variants", action="store_true", help="skip the per-variant table")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--headline-only", action="store_true",
-                    help="skip the other workloads (er16k, grid4096, er23) and the copy ceiling")
+                    help="skip the other configurations (er16k, grid4096, er23, batched) "
+                         "and the copy ceiling")
     ap.add_argument("--reps", type=int, default=3, help="repeats per variant in the table")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (counter calibration)")
@@ -486,6 +487,8 @@ def main():
     ap.add_argument("--workloads", default="er16k,rmat16,rmat22",
                     help="concurrent: workloads to run")
     ap.add_argument("--instances", type=int, default=512, help="batched: instance count")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="single: leave the batched configuration out of the default run")
     ap.add_argument("--duration", type=float, default=12.0, help="serve: trace seconds")
     ap.add_argument("--serve-warmup", type=float, default=0.0,
                     help="serve: seconds of trace before the measured part")
@@ -552,6 +555,10 @@ def main():
             others[w] = run_workload(w, args, sources_kind=sk, variants=False,
                                      cpu=not args.no_cpu, named=named)
             torch.cuda.empty_cache()
+        # C4: the batched launch of 512 small instances
+        if not args.no_batched:
+            others["batched"] = bench_batched(args, emit=False)
+            torch.cuda.empty_cache()
 
     line = {
         "metric": "GTEPS (SSSP+BFS+CC)", "value": head["GTEPS"], "unit": "GTEPS",
@@ -576,17 +583,23 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def common_line(args, metric, value, unit, ms_per_step, config, **extra):
+def make_line(args, metric, value, unit, ms_per_step, config, **extra):
     line = {"metric": metric, "value": round(value, 4), "unit": unit, "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
             "data": "synthetic", "config": config}
     line.update(extra)
-    print(json.dumps(line), flush=True)
+    return line
 
 
-def bench_batched(args):
-    """512 instances: one batch (tuned groups, HIP-graph replay) vs plain calls."""
+def common_line(args, metric, value, unit, ms_per_step, config, **extra):
+    print(json.dumps(make_line(args, metric, value, unit, ms_per_step, config, **extra)),
+          flush=True)
+
+
+def bench_batched(args, emit=True):
+    """512 instances: one batch (tuned groups, HIP-graph replay) vs plain calls.
+    emit=False returns the line instead of printing it."""
     import torch
 
     from paper_1903_01665_amd import gen, gg
@@ -690,7 +703,8 @@ def bench_batched(args):
                "host": host_info()}
         log(f"[bench] oracle on {threads} threads: {tc:.2f}s ({cpu['value']} GTEPS); "
             f"GPU results match: {verified}")
-    common_line(args, "GTEPS batched (512 SSSP/BFS instances)", m_trav / tb / 1e9, "GTEPS",
+    out = (common_line if emit else make_line)(
+                args, "GTEPS batched (512 SSSP/BFS instances)", m_trav / tb / 1e9, "GTEPS",
                 tb * 1e3,
                 {"workload": "batched-rmat-10..18", "instances": len(inst), "edges": total_m,
                  "traversed_edges": m_trav, "reached_vertices": v_reach, "groups": groups,
@@ -698,6 +712,7 @@ def bench_batched(args):
                 roofline=roof, cpu_baseline=cpu,
                 plain={"GTEPS": round(m_trav / tp / 1e9, 4), "ms_per_pass": round(tp * 1e3, 3)},
                 speedup_vs_plain=round(tp / tb, 3), results_identical_to_plain=same)
+    return out
 
 
 def bench_msf(args):

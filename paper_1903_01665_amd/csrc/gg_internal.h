@@ -18,7 +18,7 @@ constexpr int kMaxStatBlocks = 4096; // per-block statistics slots
 // graph it cuts short rows into underfilled chunks)
 constexpr int kHeavySkewed = 16;
 constexpr int kHeavyUniform = 32;
-constexpr int kChunk = 256;          // edges per heavy-row chunk
+constexpr int kChunk = 512;          // edges per heavy-row chunk
 constexpr int kKinds = 3;            // statistics kinds: round, heavy chunks, auxiliary
 constexpr int kParts = 8;            // frontier work items per 64-tile group (8 tiles each)
 constexpr int kXcd = 8;              // accelerator dies; workgroups go to them round-robin

@@ -851,7 +851,7 @@ __device__ __forceinline__ void esync_body(const Round& R, Acc& acc) {
 // indices only -- no label gathers, and no atomics except one per heavy-row
 // chunk.  Light rows: a wavefront takes a tile of 64 rows, walks their edges
 // with the balanced mapping and reduces per row in LDS.  Heavy rows: one
-// wavefront per 256-edge chunk, one atomic minimum per chunk.  Every vertex
+// wavefront per heavy-row chunk, one atomic minimum per chunk.  Every vertex
 // whose label drops is pushed (with its row length counted), as a sweep
 // does.  (An in-place edge sweep carries labels further than this one
 // synchronous step, so the plain sweep schedule keeps its first sweep: on a
