@@ -35,6 +35,9 @@ VARIANTS = [(V, gg.SYNC, gg.MAP_THREAD, 0, 0, 0), (V, gg.SYNC, gg.MAP_WAVE, 0, 0
 LOCAL = [(V, gg.ASYNC, BAL, 0, h, 0) for h in (2, 8)]
 NEARFAR = ([(V, NF, BAL, de, 0, 0) for de in (8, 16, 32, 64, 128, 512)] +
            [(V, NF, BAL, de, h, 0) for de in (8, 16, 32, 64, 128) for h in (2, 8, 32)] +
+           # long chains of passes (deep graphs) and finer widths around them
+           [(V, NF, BAL, de, 64, 0) for de in (24, 32, 48)] +
+           [(V, NF, BAL, de, 32, 0) for de in (24, 48)] +
            # narrow buckets that hold back only long rows (skewed graphs)
            [(V, NF, BAL, de, 4, far) for de in (2, 3, 4, 6) for far in (32, 96)])
 DIROPT = [(V, gg.DIROPT, BAL, 0, 0, 0)]
@@ -157,6 +160,9 @@ def measure(args, known=None):
                     raise RuntimeError(f"measurements do not match: {ka} {kc} vs {algo} {cls}")
                 if hg.name not in redo:
                     times = dict(kt)
+                elif args.remeasure_local:
+                    # only the variants with local expansion are timed again
+                    times = {v: t for v, t in kt.items() if v[4] == 0}
             extra = (NEARFAR + SSSP_DIROPT if algo == "sssp" else DIROPT if algo == "bfs"
                      else CC_DIROPT)
             for v in VARIANTS + LOCAL + extra:
@@ -186,6 +192,8 @@ def main(argv=None):
     ap.add_argument("--remeasure", default="", metavar="NAMES",
                     help="with --extend: time every variant again on these calibration "
                          "graphs (comma-separated, e.g. rmat20,rmat22)")
+    ap.add_argument("--remeasure-local", action="store_true",
+                    help="with --remeasure: only the variants with local expansion")
     args = ap.parse_args(argv)
 
     def load(path):
