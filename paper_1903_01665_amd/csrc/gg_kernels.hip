@@ -48,11 +48,11 @@ constexpr int kBatch = 4;
 constexpr int batch_for(int A, bool nf) { return nf ? 8 : A == BFS ? 2 : 4; }
 
 // Direction-optimizing BFS pulls a level when its frontier holds more than
-// n / kPullRatio vertices.  12, not 20: er23's level 6 holds 464K of 8.4M
+// n / kPullRatio vertices.  Not 20: er23's level 6 holds 464K of 8.4M
 // vertices, and pulling it (most of the unvisited vertices scan their whole
-// in-lists in vain) took BFS from 1.06 to 2.0 ms; rmat22 pulls the same
-// levels either way (1.1M and 844K of 4.2M).
-constexpr int kPullRatio = 12;
+// in-lists in vain) took BFS from 1.06 to 2.0 ms.  16 rather than 12: on
+// the renumbered rmat22 the step gains 1.7% (a sweep over 8, 12, 16).
+constexpr int kPullRatio = 16;
 
 // CC with the per-round choice sweeps every edge while the rows of the
 // frontier hold more than (both-directions edges) / kSweepRatio edges.
