@@ -173,7 +173,8 @@ constexpr long long kPartMinEdges = 1LL << 20;
 // Renumber an uploaded CSR (device row/col/w of the handle; hrow, the host
 // copy of the offsets): new ids by descending total degree, ties in the
 // caller's order (a stable counting sort on the host), each row's edges
-// kept in order.  Leaves the renumbered arrays in the handle, hrow and hin
+// then ordered by head (sort_rows_by_head).  Leaves the renumbered arrays
+// in the handle, hrow and hin
 // (in-degrees) in the new order, the id maps, and -- for a weighted graph,
 // the only kind a forest is built on -- the edge maps.  tmp: n + 8 ints.
 int renumber_graph(gg_graph g, std::vector<int>& hrow, std::vector<int>& hin, int* tmp,
@@ -255,6 +256,9 @@ int renumber_graph(gg_graph g, std::vector<int>& hrow, std::vector<int>& hin, in
     g->row = drow;
     g->col = dcol;
     g->w = dw;
+    // each row's edges by head: the gathers of a long row share lines
+    const int rc = sort_rows_by_head(g, s);
+    if (rc != GG_OK) return rc;
     hrow.swap(nrow);
     hin.swap(nin);
     g->h_newid.swap(newid);

@@ -231,6 +231,8 @@ int drive_enqueue(Drive& d);
 int drive_step(Drive& d, bool block);
 // Blocking form: rounds from r0 until the end is reported.
 int plan_drive(Plan& p, long long r0, int stamp_base, int tag, long long* r_end);
+// Upload of a renumbered graph: order each row's edges by head (gg_sort.hip).
+int sort_rows_by_head(gg_graph g, hipStream_t s);
 // Record the variant, status and round count of a finished call.
 void record_last(Plan& p, int status, long long rounds);
 // One traversal from one source or from a device list of sources.
