@@ -132,8 +132,9 @@ typedef enum { GG_ALGO_SSSP = 0, GG_ALGO_BFS = 1, GG_ALGO_CC = 2, GG_ALGO_MSF = 
  * least 2^20 edges, and on any graph uploaded with GG_RENUMBER, the library
  * stores the graph with its vertices numbered by descending total degree
  * (out + in; ties in the caller's order), so that the values gathered most
- * often share a few cache lines that stay in each die's L2.  Edges keep
- * their order within a row.  Nothing of this shows at the interface: every
+ * often share a few cache lines that stay in each die's L2, and each row's
+ * edges are stored ordered by head, so that the heads a wavefront gathers
+ * at once share lines too.  Nothing of this shows at the interface: every
  * vertex id and edge index passed in or written out is the caller's
  * (sources, dist/level/label outputs -- a CC label is the smallest of the
  * caller's ids in the component -- and the forest flags of gg_msf).  A
