@@ -49,7 +49,7 @@ VARIANTS = {"vertex-sync": (0, 0, 3, 0, 0, 0), "vertex-async": (0, 1, 3, 0, 0, 0
             "edge-sync": (1, 0, 0, 0, 0, 0), "edge-async": (1, 1, 0, 0, 0, 0),
             "nearfar": (0, 3, 3, 0, 0, 0), "diropt": (0, 4, 3, 0, 0, 0),
             "vertex-async-h8": (0, 1, 3, 8, 0, 0), "nearfar-h32": (0, 3, 3, 32, 0, 0),
-            "nearfar-long64-h4": (0, 3, 3, 4, 64, 3)}
+            "nearfar-long64-h4": (0, 3, 3, 4, 64, 3), "unionfind": (0, 5, 3, 0, 0, 0)}
 
 
 def log(*a):
@@ -74,6 +74,8 @@ def log(*a):
 #   CC diropt     swept edges as edge sync (16 B), the other edges, vertices
 #                 and tiles as vertex async; 4 B per update; per push 2 B of
 #                 flags and 8 B for the pushed vertex's row length
+#   CC union-find 8 B per vertex per phase (row offsets), 16 B per linked edge
+#                 (column, two roots, the swap); the compressions as aux
 # heavy kernels: per edge 12 / 8 B, per push 2 B (10 B under CC diropt)
 # aux kernels:   init 4 B per vertex (+2 B of flags when async); CC shortcut
 #                8 B per vertex per launch
@@ -82,6 +84,10 @@ def algorithmic_bytes(algo, mode, sched, kind, n, prof_kind, launches):
     V = prof_kind["vertices_processed"]
     U = prof_kind["updates"]
     P = prof_kind["pushes"]
+    if sched == 5 and kind == "round":
+        # union-find: the row offsets of every vertex per linking phase, per
+        # linked edge its column, the two roots found and the swap
+        return 8 * n * launches + 16 * E
     per_edge = 12 if algo == "sssp" else 8
     if sched == 4 and (algo == "sssp" or (algo == "cc" and mode == 0)):
         # per-round push/pull (SSSP; CC in vertex mode): an edge is 12 B
@@ -122,6 +128,8 @@ def kernel_symbol(algo, kind, mode, sched, mapping, hops=0):
         return f"void gg::k_heavy<{a}>(gg::Round)"
     if kind == "aux":
         return "gg::k_init(gg::Round, int, int)"
+    if sched == 5:
+        return "gg::k_uf(gg::Round)"
     if sched == 4:
         return f"gg::k_{algo}_diropt(gg::Round)"
     if mode == 1:
@@ -166,7 +174,7 @@ def traversed_edges(deg, dist):
     return int(deg[dist < INF].sum())
 
 
-SCHED_NAMES = ["sync", "async", "auto", "nearfar", "diropt"]
+SCHED_NAMES = ["sync", "async", "auto", "nearfar", "diropt", "unionfind"]
 
 
 def host_info():
@@ -360,6 +368,8 @@ def run_workload(name, args, *, sources_kind="random8", variants=False, cpu=True
             for vname, (mode, sched, mp, hops, far, de) in VARIANTS.items():
                 if (sched == 3 and a != "sssp") or (sched == 4 and a == "sssp"):
                     continue  # near-far is an SSSP schedule, the per-round choice BFS/CC
+                if sched == 5 and a != "cc":
+                    continue  # union-find: CC only
                 if hops and a == "cc":
                     continue  # label propagation gains nothing from local expansion
                 if sched == 4 and a == "cc":

@@ -99,13 +99,23 @@ typedef enum { GG_VERTEX = 0, GG_EDGE = 1, GG_MODE_AUTO = 2 } gg_mode;
  *   1/4 of the stored edges is pulled instead -- every vertex takes the
  *   least dist[u] + w over its in-edges whose tail u is on the frontier.
  * With GG_MODE_AUTO an explicit GG_DIROPT takes the mode it runs in (edge
- * for CC, vertex otherwise). */
+ * for CC, vertex otherwise).
+ * GG_UNIONFIND (CC only, vertex-based; needs the both-directions CSR): the
+ *   components through the DSL's Set type, a union-find structure (Sec. 2):
+ *   every vertex is linked with its first and then its second neighbour
+ *   (each pass followed by a compression), the root most of 1024 sampled
+ *   vertices share is taken as the giant component's, and only the vertices
+ *   outside it link their remaining neighbours (Sutton, Ben-Nun and Barak's
+ *   Afforest).  Linking hangs the larger root under the smaller, so the
+ *   labels are the same: the smallest id of each component.  Four rounds,
+ *   whatever the graph's diameter. */
 typedef enum {
     GG_SYNC = 0,
     GG_ASYNC = 1,
     GG_SCHED_AUTO = 2,
     GG_NEARFAR = 3,
-    GG_DIROPT = 4
+    GG_DIROPT = 4,
+    GG_UNIONFIND = 5
 } gg_sched;
 
 /* How vertex-based work is mapped to lanes.  THREAD: one lane walks a whole

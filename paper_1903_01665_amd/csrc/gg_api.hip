@@ -423,7 +423,7 @@ void resolve(gg_graph g, int algo, const gg_opts* in, gg_opts* out) {
     if (in) o = *in;
     const bool auto_mode = o.mode != GG_VERTEX && o.mode != GG_EDGE;
     const bool auto_sched = o.sched != GG_SYNC && o.sched != GG_ASYNC && o.sched != GG_NEARFAR &&
-                            o.sched != GG_DIROPT;
+                            o.sched != GG_DIROPT && o.sched != GG_UNIONFIND;
     const bool auto_map = o.mapping < GG_MAP_THREAD || o.mapping > GG_MAP_BALANCED;
     int32_t sc = 0, kc = 0, dc = -1;
     gg_class_of(g->m, g->n, g->max_deg, g->levels, &sc, &kc, &dc);
@@ -460,6 +460,12 @@ void resolve(gg_graph g, int algo, const gg_opts* in, gg_opts* out) {
     }
     if (auto_sched && o.sched == GG_NEARFAR && (algo != GG_ALGO_SSSP || o.mode != GG_VERTEX))
         o.sched = GG_ASYNC;
+    if (auto_sched && o.sched == GG_UNIONFIND && (algo != GG_ALGO_CC || !g->has_sym)) {
+        o.sched = algo == GG_ALGO_CC ? GG_SYNC : GG_ASYNC;
+        if (algo == GG_ALGO_CC && auto_mode) o.mode = GG_EDGE;
+    }
+    // an explicit union-find schedule runs vertex-based
+    if (!auto_sched && o.sched == GG_UNIONFIND && auto_mode) o.mode = GG_VERTEX;
     // without the both-directions CSR only the edge sweep can run CC
     if (algo == GG_ALGO_CC && !g->has_sym) {
         if (auto_mode) o.mode = GG_EDGE;
@@ -501,6 +507,8 @@ int plan_make(gg_graph g, gg_ws ws, int algo, int source, const int* sources_dev
     if (o.delta < 0 || o.hops < 0 || o.hops > 64 || o.far_degree < 0) return GG_EINVAL;
     const bool diropt = o.sched == GG_DIROPT;
     if (diropt && !diropt_ok(g, algo, o.mode)) return GG_ENOTSUP;
+    const bool uf = o.sched == GG_UNIONFIND;
+    if (uf && (algo != GG_ALGO_CC || o.mode != GG_VERTEX || !g->has_sym)) return GG_ENOTSUP;
     const Dev& dv = device();
     const int cap_blocks = o.max_blocks > 0 ? std::min(o.max_blocks, dv.max_blocks) : dv.max_blocks;
     auto grid = [&](long long units) {
@@ -508,6 +516,7 @@ int plan_make(gg_graph g, gg_ws ws, int algo, int source, const int* sources_dev
     };
     p.async = o.sched == GG_ASYNC || nearfar || diropt;
     p.diropt = diropt;
+    p.uf = uf;
     p.edge = o.mode == GG_EDGE;
     p.cc = algo == GG_ALGO_CC;
     Round& R = p.R;
@@ -560,6 +569,8 @@ int plan_make(gg_graph g, gg_ws ws, int algo, int source, const int* sources_dev
         p.g_round = grid(std::max(ngroups * kParts, ntiles + g->n_tchunks) / wpb + 1);
     } else if (diropt) {
         p.g_round = grid(std::max(ngroups * kParts, ntiles) / wpb + 1);
+    } else if (uf) {
+        p.g_round = grid((n + kBlock - 1) / kBlock);
     } else {
         p.g_round = grid((ngroups * kParts + wpb - 1) / wpb);
     }
@@ -569,7 +580,7 @@ int plan_make(gg_graph g, gg_ws ws, int algo, int source, const int* sources_dev
     p.g_heavy = grid((nh + 64LL * wpb - 1) / (64LL * wpb));
     if (diropt && algo == GG_ALGO_SSSP)  // enough blocks to clear the flags quickly
         p.g_heavy = std::max(p.g_heavy, grid((ngroups * 256 + kBlock - 1) / kBlock));
-    p.need_jump = p.cc && p.edge && (!p.async || diropt) && R.jump;
+    p.need_jump = p.cc && p.edge && (!p.async || diropt) && R.jump && !uf;
     // ... and the shortcut kernel of a CC pull round
     if (diropt && p.cc && R.pullmode) p.need_jump = true;
     p.g_jump = grid((n + kBlock - 1) / kBlock);
@@ -627,6 +638,7 @@ hipError_t plan_round(Plan& p, int r) {
     Round& R = p.R;
     R.r = r;
     hipError_t e = plan_launch(p, KIND_ROUND, [&] {
+        if (p.uf) return launch_uf(R, p.g_round, kBlock, p.s);
         if (p.diropt && p.cc) return launch_cc_diropt(R, p.g_round, kBlock, p.s);
         if (p.diropt && p.algo == GG_ALGO_SSSP) return launch_sssp_diropt(R, p.g_round, kBlock, p.s);
         if (p.diropt) return launch_bfs_diropt(R, p.g_round, kBlock, p.s);
@@ -639,6 +651,9 @@ hipError_t plan_round(Plan& p, int r) {
         e = plan_launch(p, KIND_HEAVY, [&] { return launch_heavy(R, p.algo, p.g_heavy, kBlock, p.s); });
     if (e == hipSuccess && p.need_jump)
         e = plan_launch(p, KIND_AUX, [&] { return launch_jump(R, p.g_jump, kBlock, p.s); });
+    // union-find: a compression after each linking phase
+    if (e == hipSuccess && p.uf && r != 2 && r <= 3)
+        e = plan_launch(p, KIND_AUX, [&] { return launch_uf_compress(R, p.g_round, kBlock, p.s); });
     return e;
 }
 

@@ -39,7 +39,8 @@ struct Ctl {
     int grid[4];     // [r % 3] = grid of round r's round kernel (push counts below)
     int hgrid[4];    // [r % 3] = grid of round r's heavy kernel
     int pull[4];     // [r % 3] = round r took the dense form (BFS pull, CC edge sweep)
-    int pad[2];
+    int giant;       // CC by union-find: the root most sampled vertices have
+    int pad[1];
 };
 
 // Per-block counters, summed on the host after a traversal; one array of
@@ -138,6 +139,10 @@ hipError_t launch_bfs_diropt(const Round& R, int grid, int block, hipStream_t s)
 hipError_t launch_jump(const Round& R, int grid, int block, hipStream_t s);
 hipError_t launch_cc_diropt(const Round& R, int grid, int block, hipStream_t s);
 hipError_t launch_sssp_diropt(const Round& R, int grid, int block, hipStream_t s);
+// CC by union-find (GG_UNIONFIND), phase R.r: link, find the giant root,
+// link the rest; and the compression pass after a linking phase
+hipError_t launch_uf(const Round& R, int grid, int block, hipStream_t s);
+hipError_t launch_uf_compress(const Round& R, int grid, int block, hipStream_t s);
 // One thread stores v into the pinned host word *p (system scope) once every
 // earlier kernel of the stream has completed.
 hipError_t launch_mark(unsigned long long* p, unsigned long long v, hipStream_t s);

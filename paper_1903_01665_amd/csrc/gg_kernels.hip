@@ -1965,6 +1965,132 @@ __global__ __launch_bounds__(256) void k_t_fill(const int* col, const int* w, co
     }
 }
 
+// ----------------------------------------------------- CC by union-find ----
+// The DSL's Set type is a union-find structure (Sec. 2); CC over it, in the
+// order of Sutton, Ben-Nun and Barak's Afforest: every vertex is linked with
+// its first neighbour (phase 0) and its second (phase 1) in the
+// both-directions rows, each followed by a compression; phase 2 samples the
+// roots of 1024 vertices and takes the most frequent as the giant
+// component's; phase 3 links, for every vertex outside that component, all
+// its remaining neighbours (an edge with one end in the giant component is
+// seen from the other end; edges inside it need nothing), and a last
+// compression makes every parent a root.  Linking hangs the larger of two
+// roots under the smaller with a compare-and-swap, so a root is always the
+// smallest id of its tree, and the parent array ends as the smallest id of
+// each component -- the labels of the other schedules.  The value array is
+// the parent array (labels start as the ids).  Phases set the round's
+// change flag except the last, so the round after it ends the traversal.
+__device__ __forceinline__ int uf_load(int* p, int x) {
+    return __hip_atomic_load(p + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Root of x while other lanes link: path halving (only non-roots change).
+__device__ __forceinline__ int uf_find(int* parent, int x) {
+    int p = uf_load(parent, x);
+    while (p != x) {
+        const int gp = uf_load(parent, p);
+        if (gp != p) __hip_atomic_store(parent + x, gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        x = gp;
+        p = uf_load(parent, x);
+    }
+    return x;
+}
+
+__device__ __forceinline__ bool uf_link(int* parent, int a, int b) {
+    for (;;) {
+        a = uf_find(parent, a);
+        b = uf_find(parent, b);
+        if (a == b) return false;
+        if (a < b) {
+            const int t = a;
+            a = b;
+            b = t;
+        }
+        int expect = a;  // a > b: hang root a under root b
+        if (__hip_atomic_compare_exchange_strong(parent + a, &expect, b, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            return true;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_uf(Round R) {
+    if (!round_begin(R)) return;
+    const DevGraph& g = R.g;
+    int* parent = R.val;
+    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long tt = (long long)gridDim.x * blockDim.x;
+    Acc acc;
+    if (R.r <= 1) {
+        for (long long v = tid; v < g.n; v += tt) {
+            const int b = g.srow[v];
+            if (g.srow[v + 1] - b > R.r) {
+                acc.e++;
+                acc.u += uf_link(parent, (int)v, g.scol[b + R.r]);
+            }
+        }
+    } else if (R.r == 2) {
+        // the giant component's root: the most frequent root of 1024
+        // vertices spread over the ids (a multiplicative hash of i)
+        __shared__ int s_root[1024];
+        if (blockIdx.x == 0) {
+            for (int i = threadIdx.x; i < 1024; i += blockDim.x) {
+                const unsigned h = (unsigned)i * 2654435761u;
+                s_root[i] = parent[(int)((unsigned long long)h * (unsigned)g.n >> 32)];
+            }
+            __syncthreads();
+            int best = -1, best_count = 0;
+            for (int i = threadIdx.x; i < 1024; i += blockDim.x) {
+                int c = 0;
+                for (int k = 0; k < 1024; ++k) c += s_root[k] == s_root[i];
+                if (c > best_count || (c == best_count && s_root[i] < best)) {
+                    best_count = c;
+                    best = s_root[i];
+                }
+            }
+            __shared__ int s_bc[256], s_b[256];
+            s_bc[threadIdx.x] = best_count;
+            s_b[threadIdx.x] = best;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                for (int i = 1; i < (int)blockDim.x; ++i)
+                    if (s_bc[i] > best_count || (s_bc[i] == best_count && s_b[i] < best)) {
+                        best_count = s_bc[i];
+                        best = s_b[i];
+                    }
+                R.ws.ctl->giant = best;
+            }
+        }
+    } else if (R.r == 3) {
+        const int giant = *(volatile int*)&R.ws.ctl->giant;
+        for (long long v = tid; v < g.n; v += tt) {
+            if (parent[v] == giant) continue;  // roots after the compression
+            const int b = g.srow[v], e1 = g.srow[v + 1];
+            for (int e = b + 2; e < e1; ++e) {
+                acc.e++;
+                acc.u += uf_link(parent, (int)v, g.scol[e]);
+            }
+        }
+    }
+    // phases 0-2 keep the traversal going (one push on the books); the
+    // last one changes nothing the next round would read
+    if (R.r < 3) acc.p = tid == 0;
+    else acc.u = acc.p = 0;
+    block_finish(R, acc, R.r % 3, KIND_ROUND);
+}
+
+// Every parent to its root; each thread writes its own vertex only.
+__global__ __launch_bounds__(256) void k_uf_compress(Round R) {
+    if (*(volatile int*)&R.ws.ctl->done) return;
+    int* parent = R.val;
+    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long tt = (long long)gridDim.x * blockDim.x;
+    for (long long v = tid; v < R.g.n; v += tt) {
+        int x = parent[v];
+        while (parent[x] != x) x = parent[x];
+        parent[v] = x;
+    }
+}
+
 // ------------------------------------------------------- renumbering ----
 // A graph stored with its vertices renumbered (new id newid[v] for caller id
 // v, oldid[] the inverse) keeps each row's edges in order: caller edge e of
@@ -2180,6 +2306,14 @@ hipError_t launch_sssp_diropt(const Round& R, int grid, int block, hipStream_t s
 
 __global__ __launch_bounds__(64) void k_mark(unsigned long long* p, unsigned long long v) {
     if (threadIdx.x == 0) __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+hipError_t launch_uf(const Round& R, int grid, int block, hipStream_t s) {
+    GG_LAUNCH(k_uf, grid, block, s, R);
+}
+
+hipError_t launch_uf_compress(const Round& R, int grid, int block, hipStream_t s) {
+    GG_LAUNCH(k_uf_compress, grid, block, s, R);
 }
 
 hipError_t launch_mark(unsigned long long* p, unsigned long long v, hipStream_t s) {

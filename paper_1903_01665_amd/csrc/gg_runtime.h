@@ -175,7 +175,7 @@ struct Plan {
     gg_opts o{};
     hipStream_t s = nullptr;
     Round R{};
-    bool async = false, edge = false, cc = false, diropt = false;
+    bool async = false, edge = false, cc = false, diropt = false, uf = false;
     bool need_heavy = false, need_jump = false, prof = false;
     // renumbered graph: R.val is the workspace's array; the finishing
     // kernels write `out` in the caller's order

@@ -21,7 +21,8 @@ bool valid(const gg_tune_entry& e) {
             (e.sched == GG_NEARFAR && e.algo == GG_ALGO_SSSP && e.mode == GG_VERTEX) ||
             (e.sched == GG_DIROPT && e.algo == GG_ALGO_BFS && e.mode == GG_VERTEX) ||
             (e.sched == GG_DIROPT && e.algo == GG_ALGO_SSSP && e.mode == GG_VERTEX) ||
-            (e.sched == GG_DIROPT && e.algo == GG_ALGO_CC)) &&
+            (e.sched == GG_DIROPT && e.algo == GG_ALGO_CC) ||
+            (e.sched == GG_UNIONFIND && e.algo == GG_ALGO_CC && e.mode == GG_VERTEX)) &&
            e.mapping >= GG_MAP_AUTO && e.mapping <= GG_MAP_BALANCED && e.delta_eighths >= 0 &&
            e.delta_eighths <= 1 << 23 && e.hops >= 0 && e.hops <= 64 && e.far_degree >= 0 &&
            (e.far_degree == 0 || e.sched == GG_NEARFAR) &&

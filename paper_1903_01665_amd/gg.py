@@ -18,7 +18,7 @@ INF = 2**31 - 1
 
 # enums of gg.h
 VERTEX, EDGE, MODE_AUTO = 0, 1, 2
-SYNC, ASYNC, SCHED_AUTO, NEARFAR, DIROPT = 0, 1, 2, 3, 4
+SYNC, ASYNC, SCHED_AUTO, NEARFAR, DIROPT, UNIONFIND = 0, 1, 2, 3, 4, 5
 MAP_AUTO, MAP_THREAD, MAP_WAVE, MAP_BALANCED = 0, 1, 2, 3
 ALGO_SSSP, ALGO_BFS, ALGO_CC, ALGO_MSF = 0, 1, 2, 3
 SYMMETRIZE, INPUT_ON_DEVICE, SYMMETRIC, TRANSPOSE = 1, 2, 4, 8

@@ -42,7 +42,9 @@ NEARFAR = ([(V, NF, BAL, de, 0, 0) for de in (8, 16, 32, 64, 128, 512)] +
            [(V, NF, BAL, de, 4, far) for de in (2, 3, 4, 6) for far in (32, 96)])
 DIROPT = [(V, gg.DIROPT, BAL, 0, 0, 0)]
 # CC's per-round schedule with edge sweeps or vertex pulls as dense rounds
-CC_DIROPT = [(gg.EDGE, gg.DIROPT, BAL, 0, 0, 0), (V, gg.DIROPT, BAL, 0, 0, 0)]
+CC_DIROPT = [(gg.EDGE, gg.DIROPT, BAL, 0, 0, 0), (V, gg.DIROPT, BAL, 0, 0, 0),
+             # the union-find Set (sampled links, then the rest off the giant)
+             (V, gg.UNIONFIND, BAL, 0, 0, 0)]
 # SSSP's per-round schedule (pull rounds over the weighted in-edge CSR)
 SSSP_DIROPT = [(V, gg.DIROPT, BAL, 0, 0, 0)]
 

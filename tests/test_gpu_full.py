@@ -18,7 +18,7 @@ COMBOS = [("auto", None), ("vertex-sync", (0, 0, 3)), ("vertex-async", (0, 1, 3)
           ("edge-sync", (1, 0, 0)), ("edge-async", (1, 1, 0))]
 # per-round schedules: (name, variant, algorithms it applies to)
 PER_ROUND = [("vertex-diropt", (0, 4, 3), ("sssp", "bfs", "cc")),
-             ("edge-diropt", (1, 4, 0), ("cc",))]
+             ("edge-diropt", (1, 4, 0), ("cc",)), ("unionfind", (0, 5, 3), ("cc",))]
 
 
 def say(*a):

@@ -615,3 +615,43 @@ def test_auto_carries_the_tuned_schedule_knobs(gg):
     finally:
         gg.tune_set(saved)
         g.free()
+
+
+def test_unionfind_cc(gg):
+    """CC through the union-find Set (sampled links, the giant root, the rest
+    linked): the smallest-id labels on graphs of every shape -- empty rows,
+    isolated vertices, many small components, a path (high diameter), hubs,
+    self-loops and parallel edges -- in the caller's and the renumbered
+    order, and at grid caps that make every block loop."""
+    rng = np.random.default_rng(5150)
+    graphs = [read_golden(f)[0] for f in golden_files()]
+    for i in range(10):
+        n = int(rng.integers(1, 500))
+        graphs.append(random_graph(rng, n, int(rng.integers(0, 2 * n + 1)), 1, 9, name=f"uf{i}"))
+    graphs += [gen.workload("er16k"), gen.workload("grid96"), gen.workload("rmat14"),
+               path_graph(3000, np.ones(2999)), star(200, [[1, 2]] * 200),
+               random_graph(rng, 5000, 1200, 1, 9, name="sparse5000")]
+    for hg in graphs:
+        want = oracle.cc(hg.n, hg.row_ptr, hg.col)
+        for renumber in (False, True):
+            g = gg.Graph.from_host(hg, symmetrize=True, renumber=renumber)
+            try:
+                for cap in (0, 1, 7):
+                    say(f"[gpu] unionfind cc {hg.name} n={hg.n} renumber={renumber} cap={cap}")
+                    o = gg.make_opts(VERTEX, gg.UNIONFIND, BALANCED, max_blocks=cap)
+                    got = g.cc(opts=o).cpu().numpy()
+                    st = g.stats()
+                    assert st["rc"] == 0 and st["iterations"] == 4, st
+                    np.testing.assert_array_equal(got, want, err_msg=f"{hg.name} cap={cap}")
+                with pytest.raises(gg.GGError):
+                    g.bfs(0, opts=gg.make_opts(VERTEX, gg.UNIONFIND, BALANCED))
+            finally:
+                g.free()
+    # without the both-directions CSR the schedule cannot run
+    hg = gen.workload("er300x900")
+    g = gg.Graph(hg.n, hg.row_ptr, hg.col, hg.w)
+    try:
+        with pytest.raises(gg.GGError):
+            g.cc(opts=gg.make_opts(VERTEX, gg.UNIONFIND, BALANCED))
+    finally:
+        g.free()

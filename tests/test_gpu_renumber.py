@@ -22,7 +22,8 @@ VARIANTS = [("vertex-sync-thread", 0, 0, 1, 0, 0), ("vertex-sync-balanced", 0, 0
             ("vertex-async-wave", 0, 1, 2, 0, 0), ("vertex-async-balanced", 0, 1, 3, 0, 0),
             ("vertex-async-local8", 0, 1, 3, 8, 0), ("edge-sync", 1, 0, 0, 0, 0),
             ("edge-async", 1, 1, 0, 0, 0), ("nearfar-local4", 0, 3, 3, 4, 20),
-            ("vertex-diropt", 0, 4, 3, 0, 0), ("edge-diropt", 1, 4, 0, 0, 0)]
+            ("vertex-diropt", 0, 4, 3, 0, 0), ("edge-diropt", 1, 4, 0, 0, 0),
+            ("unionfind", 0, 5, 3, 0, 0)]
 
 
 def say(*a):
@@ -54,6 +55,8 @@ def applies(algo, v):
     if sched == 3 and algo != "sssp":
         return False
     if sched == 4 and mode == 1 and algo != "cc":
+        return False
+    if sched == 5 and algo != "cc":
         return False
     return True
 
