@@ -122,14 +122,15 @@ def algorithmic_bytes(algo, mode, sched, kind, n, prof_kind, launches):
 
 
 def kernel_symbol(algo, kind, mode, sched, mapping, hops=0):
-    """HIP symbol of the kernel that runs (algo, kind) in a variant."""
+    """HIP symbol of the kernel that runs (algo, kind) in a variant (None when
+    the variant launches no kernel of that kind)."""
     a = {"sssp": 0, "bfs": 1, "cc": 2}[algo]
+    if sched == 5:  # union-find CC: linking rounds and compressions, no chunk kernel
+        return {"round": "gg::k_uf(gg::Round)", "aux": "gg::k_uf_compress(gg::Round)"}.get(kind)
     if kind == "heavy":
         return f"void gg::k_heavy<{a}>(gg::Round)"
     if kind == "aux":
         return "gg::k_init(gg::Round, int, int)"
-    if sched == 5:
-        return "gg::k_uf(gg::Round)"
     if sched == 4:
         return f"gg::k_{algo}_diropt(gg::Round)"
     if mode == 1:

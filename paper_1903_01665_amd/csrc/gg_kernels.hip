@@ -967,15 +967,17 @@ __device__ __forceinline__ void serve_list(const Round& R, const int* row, const
         tail_value<A, true>(R, u, sv, acc);
         rb = row[u];
         re = row[u + 1];
-        if (nf && sv >= bound && (R.far_degree == 0 || re - rb > R.far_degree)) {
-            // a far vertex waits on the frontier for a later bound (with
-            // far_degree > 0 only its long rows wait; short ones go now)
+        // a far vertex waits on the frontier for a later bound (with
+        // far_degree > 0 only its long rows wait; short ones go now)
+        const bool defer = nf && sv >= bound && (R.far_degree == 0 || re - rb > R.far_degree);
+        if (defer) {
             push(R, nxt, u);
-            acc.u++;
             on = false;
-        } else {
-            acc.v++;
         }
+        // counted without a branch: incrementing one of two counters
+        // under a condition made the compiler keep them in scratch memory
+        acc.u += defer;
+        acc.v += !defer;
     }
     const bool hv = on && re - rb > R.g.heavy;
     if (hv) mark_heavy(R, u);
@@ -1069,16 +1071,17 @@ __device__ __forceinline__ void vasync_body(const Round& R, Acc& acc, bool nf, i
             int rb = 0, re = 0, sv = 0;
             if (on) {
                 tail_value<A, true>(R, u, sv, acc);
-                if (nf && sv >= bound) {
-                    // a far vertex waits on the frontier for a later bound
+                // a far vertex waits on the frontier for a later bound
+                const bool defer = nf && sv >= bound;
+                if (defer) {
                     push(R, nxt, u);
-                    acc.u++;
                     on = false;
                 } else {
                     rb = row[u];
                     re = row[u + 1];
-                    acc.v++;
                 }
+                acc.u += defer;
+                acc.v += !defer;
             }
             if (MAP == MAP_THREAD) {
                 if (on)
@@ -1145,13 +1148,13 @@ __device__ __forceinline__ void serve_local(const Round& R, const int* row, cons
         else tail_value<A, true>(R, u, sv, acc);
         rb = row[u];
         re = row[u + 1];
-        if (nf && sv >= bound && (R.far_degree == 0 || re - rb > R.far_degree)) {
+        const bool defer = nf && sv >= bound && (R.far_degree == 0 || re - rb > R.far_degree);
+        if (defer) {
             push(R, nxt, u);
-            acc.u++;
             on = false;
-        } else {
-            acc.v++;
         }
+        acc.u += defer;  // without a branch, as in serve_list
+        acc.v += !defer;
     }
     bool hv = on && re - rb > R.g.heavy;
     if (hv) mark_heavy(R, u);
@@ -1243,8 +1246,10 @@ __device__ __forceinline__ void vasync_local(const Round& R, Acc& acc, bool nf, 
 }
 
 // Worklist round with local expansion (balanced mapping; NF: near-far).
+// At most 80 VGPRs (six wavefronts per SIMD): the near-far form otherwise
+// takes 81 and launches 1,280 resident blocks instead of 1,536.
 template <int A, bool NF>
-__global__ __launch_bounds__(256) void k_vlocal(Round R) {
+__global__ __launch_bounds__(256, 6) void k_vlocal(Round R) {
     if (!round_begin(R)) return;
     clear_prev_heavy(R);
     const int bound = NF ? nearfar_bound(R) : kInf;

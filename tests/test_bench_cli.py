@@ -66,4 +66,7 @@ def test_tuned_rmat22_kernels_are_in_the_traffic_summary():
         e = gg.tune_lookup(ai, *gg.class_of(1 << 26, 1 << 22, 159873, 7), full=True)
         for kind in ("round", "heavy"):
             sym = bench.kernel_symbol(algo, kind, e["mode"], e["sched"], e["mapping"], e["hops"])
+            if sym is None:  # no kernel of this kind (union-find CC has no chunk kernel)
+                assert e["sched"] == 5 and kind == "heavy", (algo, kind, e)
+                continue
             assert sym in keys, (algo, kind, e, sym)
