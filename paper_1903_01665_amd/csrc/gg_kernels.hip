@@ -2281,6 +2281,25 @@ hipError_t launch_esync(const Round& R, int algo, int grid, int block, hipStream
     }
 }
 
+// Resident blocks per CU for the local-expansion round kernels.  Their
+// rounds wait for the slowest wavefront, and a CU holding a seventh block
+// slows its wavefronts: grid4096 BFS (the BFS form fits seven blocks per CU)
+// took 50 us per round with 1,792 blocks, 46 us with 1,600 and 39 us with
+// 1,536 or fewer.
+constexpr int kLocalBlocksPerCu = 6;
+
+static int local_grid(int grid) {
+    static const int cap = [] {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus < 1)
+            return 1 << 30;
+        return kLocalBlocksPerCu * cus;
+    }();
+    return grid < cap ? grid : cap;
+}
+
 template <int A>
 static hipError_t vasync_a(const Round& R, int grid, int block, hipStream_t s) {
     switch (R.mapping) {
@@ -2289,10 +2308,10 @@ static hipError_t vasync_a(const Round& R, int grid, int block, hipStream_t s) {
         default:
             if constexpr (A == SSSP)
                 if (R.delta > 0) {
-                    if (R.hops > 0) GG_LAUNCH((k_vlocal<A, true>), grid, block, s, R);
+                    if (R.hops > 0) GG_LAUNCH((k_vlocal<A, true>), local_grid(grid), block, s, R);
                     GG_LAUNCH((k_vasync<A, MAP_BALANCED, true>), grid, block, s, R);
                 }
-            if (R.hops > 0) GG_LAUNCH((k_vlocal<A, false>), grid, block, s, R);
+            if (R.hops > 0) GG_LAUNCH((k_vlocal<A, false>), local_grid(grid), block, s, R);
             GG_LAUNCH((k_vasync<A, MAP_BALANCED>), grid, block, s, R);
     }
 }
