@@ -160,7 +160,8 @@ def measure(args, known=None):
                 ka, kc, kt = known[len(results)]
                 if (ka, tuple(kc)) != (algo, tuple(cls)):
                     raise RuntimeError(f"measurements do not match: {ka} {kc} vs {algo} {cls}")
-                if hg.name not in redo:
+                algos = set(getattr(args, "remeasure_algos", "").split(",")) - {""}
+                if hg.name not in redo or (algos and algo not in algos):
                     times = dict(kt)
                 elif args.remeasure_local:
                     # only the variants with local expansion are timed again
@@ -196,6 +197,8 @@ def main(argv=None):
                          "graphs (comma-separated, e.g. rmat20,rmat22)")
     ap.add_argument("--remeasure-local", action="store_true",
                     help="with --remeasure: only the variants with local expansion")
+    ap.add_argument("--remeasure-algos", default="", metavar="ALGOS",
+                    help="with --remeasure: only these algorithms (comma-separated, e.g. cc)")
     args = ap.parse_args(argv)
 
     def load(path):
