@@ -655,3 +655,93 @@ def test_unionfind_cc(gg):
             g.cc(opts=gg.make_opts(VERTEX, gg.UNIONFIND, BALANCED))
     finally:
         g.free()
+
+
+def _rows_of(rng, n, degs, wlo=1, whi=9, name="rows"):
+    """Vertex v with degs[v] out-edges to random heads."""
+    degs = np.asarray(degs, np.int64)
+    src = np.repeat(np.arange(n, dtype=np.int32), degs)
+    dst = rng.integers(0, n, size=len(src), dtype=np.int64).astype(np.int32)
+    w = rng.integers(wlo, whi + 1, size=len(src), dtype=np.int64).astype(np.int32)
+    return gen.from_edges(n, src, dst, w, name=name)
+
+
+def test_local_short_rows(gg):
+    """Local-expansion passes over lists whose rows all have at most five
+    edges take one lane per row; lists with a longer row take the balanced
+    walk.  Graphs with every row short, and with row lengths around the
+    limit (so that a traversal switches between the two), give the oracle's
+    distances, levels and labels."""
+    rng = np.random.default_rng(55)
+    graphs = [_rows_of(rng, 3000, np.full(3000, d), name=f"deg{d}") for d in (1, 2, 4, 5)]
+    graphs.append(_rows_of(rng, 4000, rng.integers(0, 9, size=4000), name="deg0to8"))
+    graphs.append(_rows_of(rng, 4000, rng.choice([4, 5, 6], size=4000, p=[0.9, 0.08, 0.02]),
+                           wlo=1, whi=1000, name="deg456"))
+    graphs.append(gen.workload("grid96"))
+    for hg in graphs:
+        s = int(rng.integers(0, hg.n))
+        want = expected(hg, s)
+        g = gg.Graph.from_host(hg, symmetrize=True)
+        try:
+            for algo, sched, delta, hops, fl in (
+                    ("sssp", gg.NEARFAR, 0, 64, gg.OPT_LISTS_DIRECT),
+                    ("sssp", gg.NEARFAR, 0, 64, gg.OPT_LISTS_CHECKED),
+                    ("sssp", gg.NEARFAR, 3, 8, 0), ("sssp", gg.ASYNC, 0, 8, 0),
+                    ("bfs", gg.ASYNC, 0, 8, 0), ("cc", gg.ASYNC, 0, 4, 0)):
+                say(f"[gpu] short rows {hg.name} n={hg.n} {algo} sched={sched} hops={hops} "
+                    f"flags={fl}")
+                o = gg.make_opts(gg.VERTEX, sched, gg.MAP_BALANCED, delta=delta, hops=hops,
+                                 flags=fl)
+                got = (g.cc(opts=o) if algo == "cc" else getattr(g, algo)(s, opts=o))
+                assert g.stats()["rc"] == 0
+                np.testing.assert_array_equal(got.cpu().numpy()[: hg.n], want[algo],
+                                              err_msg=f"{hg.name} {algo} hops={hops}")
+        finally:
+            g.free()
+
+
+def test_cc_plain_sweeps_under_contention(gg):
+    """Plain CC edge sweeps lower labels with stores: concurrent stores into
+    one label can lose the lower value, which a later sweep restores.  Hubs
+    with the largest ids and tens of thousands of smaller neighbours make
+    every lane of a sweep store into the same labels; the labels must still
+    be the smallest id of each component, on every repetition, with the
+    both-directions arrays (head stores only) and without them (both ends)."""
+    rng = np.random.default_rng(77)
+    n = 40000
+    hubs = np.arange(n - 8, n, dtype=np.int32)  # eight hubs with the largest ids
+    leaves = np.arange(0, n - 8, dtype=np.int32)
+    src = np.concatenate([leaves, leaves[::-1]])
+    dst = np.concatenate([hubs[leaves % 8], hubs[(leaves * 7 + 3) % 8]])
+    stars = gen.from_edges(n, src, dst, np.ones(len(src), np.int32), name="hubs")
+    # two components: even and odd vertices, each a random graph in one direction
+    m = 200000
+    a = rng.integers(0, n // 2, size=m).astype(np.int32)
+    b = rng.integers(0, n // 2, size=m).astype(np.int32)
+    par = rng.integers(0, 2, size=m).astype(np.int32)
+    split = gen.from_edges(n, 2 * a + par, 2 * b + par, np.ones(m, np.int32), name="evenodd")
+    def both_ways(hg):
+        # the edges in both directions, uploaded as a symmetric graph: the
+        # sweeps store into head labels only
+        s0 = np.repeat(np.arange(hg.n, dtype=np.int32), np.diff(hg.row_ptr))
+        c0 = np.asarray(hg.col, np.int32)
+        return gen.from_edges(hg.n, np.concatenate([s0, c0]), np.concatenate([c0, s0]),
+                              np.ones(2 * len(c0), np.int32), name=hg.name + "-sym",
+                              symmetric=True)
+
+    for hg in (stars, split, both_ways(stars), both_ways(split)):
+        want = oracle.cc(hg.n, hg.row_ptr, hg.col)
+        for sym in ((True,) if hg.symmetric else (True, False)):
+            g = gg.Graph.from_host(hg, symmetrize=sym)
+            try:
+                for cap in (0, 7, 64):
+                    for rep in range(5):
+                        say(f"[gpu] cc plain sweeps {hg.name} symmetrize={sym} cap={cap} "
+                            f"rep={rep}")
+                        o = gg.make_opts(EDGE, SYNC, 0, max_blocks=cap)
+                        got = g.cc(opts=o).cpu().numpy()
+                        assert g.stats()["rc"] == 0
+                        np.testing.assert_array_equal(got, want,
+                                                      err_msg=f"{hg.name} sym={sym} cap={cap}")
+            finally:
+                g.free()
