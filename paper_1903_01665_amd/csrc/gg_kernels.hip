@@ -748,10 +748,11 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 // id), that edge stays inconsistent and a later sweep lowers it again.
 // Plain sweeps end after a sweep in which no lane stored anything, which saw
 // every edge consistent: each component then holds one label, the id of one
-// of its vertices and no larger than any of them -- the smallest.  A
-// device-scope atomic leaves the die and is performed beside memory, and a
-// first sweep lowers labels across half of the edges (er23 CC: 3.10 ms with
-// atomics, 2.59 ms with stores).
+// of its vertices and no larger than any of them -- the smallest.  Every
+// device-scope atomic sends its write on to memory (32 bytes of write
+// traffic each by the counters), where stores stay in the die's cache until
+// the sweep ends, and a first sweep lowers labels across half of the edges
+// (er23 CC: 3.10 ms with atomics, 2.59 ms with stores).
 template <bool PUSH>
 __device__ __forceinline__ void cc_lower(int* p, int x) {
     if (PUSH) atomicMin(p, x);
